@@ -1,0 +1,334 @@
+#!/usr/bin/env python3
+"""Benchmark: walker-steps/s of batched low-rank determinant updates on one MI355X.
+
+Default workload (the paper-shaped scale configuration): orbital matrix Phi
+512 x 256 iid N(0,1), 1024 walkers, each step moves k ~ U{1,2,4} electrons to
+empty sites, delayed updates with K = 16 flushed by an MFMA GEMM, FP64 refresh
+every 128 steps.  One benchmark "step" is one refresh period: 128 Markov-chain
+steps of every walker (build hop -> ratio -> accept -> delayed update, 8
+flushes) plus the FP64 refresh, replayed as one HIP graph.  Mode: forced
+accept (every proposal is applied, a deterministic byte count).
+
+The JSON line also carries: the dominant kernel's roofline (HIP events around
+the delayed accept kernel), the oracle on the host cores (cpu_baseline), full
+recompute on the same GPU (rocSOLVER via torch.linalg.slogdet), the FP32-bulk
+variant, and the measured relative error against the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "walker-steps/s det & pf LRU vs full recompute, same GPU, at stated rel. error"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed refresh periods")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="slater_n256_k124")
+    ap.add_argument("--walkers", type=int, default=0, help="override the walker count")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-recompute", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+class Run:
+    """One walker batch with its pre-generated draws, stepping one refresh period at a time."""
+
+    def __init__(self, wl, dtype, walkers, seed_offset=0):
+        import torch
+        from paper_2602_05255_amd import inputs as gen
+        from paper_2602_05255_amd import lrx
+        from paper_2602_05255_amd.walkers import Walkers
+        self.torch, self.lrx = torch, lrx
+        self.wl = wl
+        phi, occ, emp, g = gen.slater_inputs(wl, walkers=walkers, seed_offset=seed_offset)
+        self.phi = phi
+        self.W = walkers
+        self.P = wl.refresh
+        t0 = time.time()
+        k, e, s = gen.hop_draws_batch(g, self.P, walkers, wl.n, wl.sites - wl.n, wl.ranks, wl.k_max)
+        log(f"  draws {self.P} x {walkers}: {time.time() - t0:.1f}s")
+        dev = torch.device("cuda")
+        self.k = torch.as_tensor(k).to(dev)
+        self.e = torch.as_tensor(e).to(dev)
+        self.s = torch.as_tensor(s).to(dev)
+        self.wk = Walkers(lrx.LRX_DET, dtype, phi, occ, emp, wl.k_max, wl.delay, refresh_period=0)
+        self.graph = None
+
+    def period(self, timer=None):
+        """One refresh period: P steps with forced accept, flushes every K, then refresh."""
+        wk, lrx = self.wk, self.lrx
+        for t in range(self.P):
+            wk.use_draws(self.k[t], self.e[t], self.s[t])
+            wk.propose()
+            wk.decide(mode=lrx.LRX_MH_FORCE)
+            if timer is not None:
+                timer.begin("accept", wk.st.slot)
+            lrx.lrx_det_accept_update(wk.st, wk._k, wk._elec, wk.u, wk.accept)
+            if timer is not None:
+                timer.end("accept")
+            lrx.lrx_hop_commit(wk.W, wk.n, wk.n_empty, wk.k_max, wk._k, wk._elec, wk._slot, wk.accept,
+                               wk.occ, wk.empty)
+            if wk.delay and wk.st.slot == wk.delay:
+                if timer is not None:
+                    timer.begin("flush", wk.st.slot)
+                wk.flush()
+                if timer is not None:
+                    timer.end("flush")
+        if timer is not None:
+            timer.begin("refresh", 0)
+        wk.refresh(report=False)
+        if timer is not None:
+            timer.end("refresh")
+
+    def capture(self):
+        torch = self.torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.period()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.period()
+        torch.cuda.synchronize()
+        self.graph = g
+
+    def step(self):
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self.period()
+
+
+class EventTimer:
+    """HIP events around selected launches on the current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.rec = []
+        self.cur = {}
+
+    def begin(self, name, tau):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record()
+        self.cur[name] = (ev, tau)
+
+    def end(self, name):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record()
+        b, tau = self.cur.pop(name)
+        self.rec.append((name, tau, b, ev))
+
+    def results(self):
+        self.torch.cuda.synchronize()
+        out = {}
+        for name, tau, b, e in self.rec:
+            out.setdefault(name, []).append((tau, b.elapsed_time(e) * 1e-3))
+        return out
+
+
+def accept_bytes(wl, s, W, tau):
+    """Algorithmic HBM bytes of one delayed accept launch (all walkers accepted):
+    read A_0^-1 (n^2), read the tau live b-slot rows (n * tau * k_max), read
+    u and C (2 n k_max), write slot tau of a and b (2 n k_max)."""
+    n, km = wl.n, wl.k_max
+    return W * s * (n * n + n * km * tau + 4 * n * km)
+
+
+def measure(wl, dtype, walkers, args, torch, label):
+    run = Run(wl, dtype, walkers)
+    elem = torch.empty((), dtype=dtype).element_size()
+    # roofline pass: eager, HIP events around every accept launch of one period
+    run.period()
+    torch.cuda.synchronize()
+    timer = EventTimer(torch)
+    run.period(timer)
+    res = timer.results()
+    acc = res["accept"]
+    bytes_tot = sum(accept_bytes(wl, elem, walkers, tau) for tau, _ in acc)
+    t_tot = sum(dt for _, dt in acc)
+    fl = res.get("flush", [])
+    flush_t = np.mean([dt for _, dt in fl]) if fl else None
+    refresh_t = np.mean([dt for _, dt in res["refresh"]])
+    if not args.no_graph:
+        run.capture()
+    for _ in range(args.warmup):
+        run.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        run.step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu = e0.elapsed_time(e1) * 1e-3
+    T = max(wall, gpu)
+    value = walkers * run.P * args.steps / T
+    # flush roofline: algorithmic flops 2 n^2 K k_max per walker; bytes RW of M0 + panels
+    n, K, km = wl.n, wl.delay, wl.k_max
+    flush = None
+    if flush_t:
+        fflops = walkers * 2.0 * n * n * K * km
+        fbytes = walkers * elem * (2 * n * n + 2 * n * K * km)
+        flush = {"avg_us": flush_t * 1e6, "tflops": fflops / flush_t / 1e12,
+                 "gbs": fbytes / flush_t / 1e9,
+                 "mfma_frac": fflops / flush_t / 1e12 / (FP64_PEAK_TFS if elem == 8 else FP32_PEAK_TFS),
+                 "hbm_frac": fbytes / flush_t / 1e9 / HBM_PEAK_GBS}
+    log(f"  [{label}] {value:.4g} walker-steps/s, {T / args.steps * 1e3:.3f} ms per period; accept "
+        f"{t_tot / len(acc) * 1e6:.1f} us avg, {bytes_tot / t_tot / 1e9:.0f} GB/s; refresh {refresh_t * 1e3:.2f} ms")
+    return run, {
+        "value": value, "ms_per_step": T / args.steps * 1e3,
+        "accept_avg_us": t_tot / len(acc) * 1e6, "accept_gbs": bytes_tot / t_tot / 1e9,
+        "accept_bytes_per_launch": bytes_tot / len(acc),
+        "refresh_ms": refresh_t * 1e3, "flush": flush,
+    }
+
+
+def rel_error(run, torch, sample):
+    """Max relative error of the GPU inverse and log|det| against the oracle on sampled walkers."""
+    import oracle as orc
+    orc.build(force=False)
+    wk = run.wk
+    inv = wk.inverse()[sample].cpu().numpy()
+    occ = wk.occ[sample].cpu().numpy()
+    la, ph, oinv = orc.slogdet(orc.slater_matrices(run.phi, occ))
+    e_inv = np.linalg.norm(inv - oinv, axis=(1, 2)) / np.linalg.norm(oinv, axis=(1, 2))
+    e_la = np.abs(wk.st.logabs[sample].cpu().numpy() - la)
+    return {"inverse_max": float(e_inv.max()), "logdet_abs_max": float(e_la.max()), "walkers": len(sample)}
+
+
+def cpu_baseline(wl, seconds):
+    """The oracle (full recompute: LU + inverse per walker-step) on the host cores."""
+    import oracle as orc
+    from paper_2602_05255_amd import inputs as gen
+    orc.build(force=False)
+    W = 64
+    phi, occ, emp, g = gen.slater_inputs(wl, walkers=W, seed_offset=7)
+    chain = orc.DetChain(phi, occ, emp)
+    done, t0 = 0, time.perf_counter()
+    while True:
+        k, e, s = gen.hop_draws(g, W, wl.n, wl.sites - wl.n, wl.ranks, wl.k_max)
+        chain.propose(k, e, s)
+        chain.accept(k, e, s, np.ones(W, bool))
+        done += W
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": done / el, "unit": "walker-steps/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{W} walkers x {done // W} steps of the {wl.name} workload (n={wl.n}), "
+                      f"full FP64 LU + inverse per walker-step, {el:.1f}s"}
+
+
+def recompute(wl, run, torch, reps=5):
+    """Full recompute on the same GPU: gather Phi[occ] + torch.linalg.slogdet (rocSOLVER), FP64."""
+    phi = torch.as_tensor(run.phi).cuda()
+    occ = run.wk.occ.long()
+    out = {}
+    chunk = 128     # batched getrf on the whole 1024-matrix batch fails to allocate its workspace
+    for name, fn in (("slogdet", lambda a: torch.linalg.slogdet(a)),
+                     ("slogdet+inv", lambda a: (torch.linalg.slogdet(a), torch.linalg.inv(a)))):
+        def batch():
+            for c0 in range(0, run.W, chunk):
+                fn(phi[occ[c0:c0 + chunk]])
+        try:
+            batch()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                batch()
+            torch.cuda.synchronize()
+        except RuntimeError as exc:        # report, do not fail the benchmark line
+            out[name] = {"error": str(exc).splitlines()[0]}
+            continue
+        dt = (time.perf_counter() - t0) / reps
+        n = wl.n
+        flops = run.W * (2 * n ** 3 / 3 + (2 * n ** 3 if "inv" in name else 0))
+        out[name] = {"walker_steps_per_s": run.W / dt, "ms_per_batch": dt * 1e3, "tflops": flops / dt / 1e12}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): walkers are independent chains, "
+              "so the path shards by walker with no exchange; multi-GPU runs are not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2602_05255_amd import inputs as gen
+    from paper_2602_05255_amd import lrx  # noqa: F401  (fails loudly without liblrx.so)
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = gen.WORKLOADS[args.workload]
+    assert wl.kind == "det" and wl.n > 0, "the default benchmark drives a uniform-n determinant workload"
+    W = args.walkers or wl.walkers
+    log(f"workload {wl.name}: W={W} n={wl.n} L={wl.sites} ranks={wl.ranks} K={wl.delay} refresh={wl.refresh}")
+
+    run64, r64 = measure(wl, torch.float64, W, args, torch, "f64")
+    sample = np.linspace(0, W - 1, 8).astype(int)
+    err64 = rel_error(run64, torch, sample)
+    log(f"  f64 error vs oracle: {err64}")
+    rc = None if args.no_recompute else recompute(wl, run64, torch)
+    del run64
+    torch.cuda.empty_cache()
+    fp32 = None
+    if not args.no_fp32:
+        run32, r32 = measure(wl, torch.float32, W, args, torch, "f32")
+        err32 = rel_error(run32, torch, sample)
+        log(f"  f32 error vs oracle: {err32}")
+        fp32 = {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "rel_error": err32,
+                "accept_gbs": r32["accept_gbs"], "refresh_ms": r32["refresh_ms"]}
+        del run32
+    cpu = None if args.no_cpu else cpu_baseline(wl, args.cpu_seconds)
+
+    achieved = r64["accept_gbs"]
+    line = {
+        "metric": METRIC, "value": r64["value"], "unit": "walker-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "walkers": W, "n": wl.n, "sites": wl.sites, "ranks": list(wl.ranks),
+                   "delay": wl.delay, "refresh_every": wl.refresh, "mc_steps_per_bench_step": wl.refresh,
+                   "mode": "forced-accept", "graph": not args.no_graph},
+        "roofline": {"bound": "hbm", "kernel": "det_accept_kernel (delayed)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_us": r64["accept_avg_us"], "bytes_per_launch": r64["accept_bytes_per_launch"]},
+        "cpu_baseline": cpu,
+        "rel_error": err64,
+        "recompute": rc,
+        "speedup_vs_recompute": (r64["value"] / rc["slogdet"]["walker_steps_per_s"])
+        if rc and "walker_steps_per_s" in rc.get("slogdet", {}) else None,
+        "flush": r64["flush"], "refresh_ms": r64["refresh_ms"],
+        "fp32": fp32,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

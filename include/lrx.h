@@ -1,0 +1,320 @@
+/*
+ * lrx.h -- C ABI of liblrx: batched low-rank updates (LRU) of determinants
+ * and Pfaffians for many Markov-chain walkers on one MI355X (gfx950) GPU.
+ *
+ * Method: Chen & Roth, "lrux: Fast low-rank updates of determinants and
+ * Pfaffians in JAX", arXiv 2602.05255.  Section references below are to that
+ * paper (Sec. II = determinant, Sec. III = Pfaffian, Appendix A = Pfaffian
+ * definition, properties and gradient).
+ *
+ * Conventions that hold for every entry point
+ * -------------------------------------------
+ * - Pointers named in a signature are DEVICE pointers unless the comment says
+ *   "host".  The caller owns all memory: the library never allocates or frees
+ *   device memory, and keeps no per-call state besides the caller's
+ *   lrx_state (a host struct).
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *   only enqueues work on it and returns without synchronising.  Calls on
+ *   distinct states are thread-safe; calls on one state must be ordered by
+ *   the caller (one stream).
+ * - Return codes are synchronous and come from host-side validation (shape,
+ *   dtype, null pointers, slot bookkeeping) or from a failed kernel launch:
+ *   LRX_OK (0) or one of the LRX_E* codes.  Numerical trouble is reported per
+ *   walker in st->flags (device, uint32 [W]) and never as a return code.
+ * - Dense matrices are row-major, batch-contiguous ([W][rows][cols]).
+ *   Complex data are interleaved (re, im) pairs of the element's real type.
+ *   Complex means transpose, never conjugate transpose (Sec. II-III use the
+ *   plain transpose throughout).
+ * - Index base is 0.
+ *
+ * Per-walker state (device buffers sized by lrx_state_sizes)
+ * ----------------------------------------------------------
+ * inv   : DET: M = A^-T, i.e. A^-1 stored column-major, so column i of A^-1
+ *         (the one a row-i update needs) is the contiguous row i of M.
+ *         PF : M = A^-1 row-major, kept exactly skew-symmetric.
+ *         Bulk dtype, [W][n][n].  With delay K > 0 it holds A_0^-1 of the
+ *         current delay window (Sec. II.C / III.C).
+ * fa    : delayed factors a_t (DET Eq. det_a, PF Eq. pf_a), stored as columns:
+ *         [W][K*KA][n] with KA = k_max (DET) or 2*k_max (PF).
+ * fb    : DET: b_t (Eq. det_b) as rows, [W][n][K*k_max];
+ *         PF : R_t^-1 (2k x 2k), [W][K][2k_max][2k_max].
+ * stash : per-walker scratch written by propose and read by accept
+ *         (ratio, the gathered columns of A^-1, R^-1, small products).
+ * logabs: double [W], log|det A| (or log|pf A|) tracked through the ratios.
+ * phase : real states: double [W] (+1/-1); complex: complex double [W].
+ * flags : uint32 [W], LRX_FLAG_* bits; a flagged walker's accept is a no-op
+ *         until the next init/refresh clears the flags.
+ * work  : init/refresh workspace (FP64 / complex128 copies of the matrices).
+ */
+#ifndef LRX_H
+#define LRX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRX_VERSION 1
+
+/* Return codes. */
+enum {
+    LRX_OK = 0,
+    LRX_EINVAL = 1,        /* null pointer, bad mode or negative size           */
+    LRX_EUNSUPPORTED = 2,  /* dtype/kind/rank combination not provided          */
+    LRX_ESHAPE = 3,        /* n, W, k_max or K out of range                     */
+    LRX_ENEEDFLUSH = 4,    /* accept with slot == K: flush_delayed first        */
+    LRX_EODD = 5,          /* Pfaffian state with odd n (pf is 0 by definition) */
+    LRX_EHIP = 6,          /* a HIP launch or runtime call failed               */
+    LRX_EKIND = 7          /* DET entry point on a PF state or vice versa       */
+};
+
+/* Kinds and bulk dtypes. */
+enum { LRX_DET = 0, LRX_PF = 1 };
+enum { LRX_F32 = 0, LRX_F64 = 1, LRX_C64 = 2, LRX_C128 = 3 };
+
+/* Per-walker flag bits (device, st->flags). */
+enum {
+    LRX_FLAG_SINGULAR_R = 1u,  /* det R = 0 / pf R = 0 or non-finite: update impossible (Sec. II.A) */
+    LRX_FLAG_NONFINITE = 2u,   /* non-finite ratio                                                  */
+    LRX_FLAG_SINGULAR_A = 4u,  /* init/refresh met an exactly singular matrix                        */
+    LRX_FLAG_BADINDEX = 8u     /* a row/column/site index outside its range (clamped, step skipped)  */
+};
+
+/* Limits. */
+#define LRX_MAX_N 1024
+#define LRX_MAX_KMAX_DET 8
+#define LRX_MAX_KMAX_PF 1
+#define LRX_MAX_DELAY 64
+
+/* Metropolis modes for lrx_metropolis. */
+enum {
+    LRX_MH_UNIFORMS = 0,  /* accept iff u01[w] < min(1, |r|^2)                      */
+    LRX_MH_DEVICE_RNG = 1,/* same rule, u from a counter-based generator (seed, ctr) */
+    LRX_MH_FORCE = 2      /* accept every unflagged walker with a finite nonzero r    */
+};
+
+typedef struct lrx_shape {
+    int32_t kind;     /* LRX_DET or LRX_PF                                    */
+    int32_t dtype;    /* bulk dtype of inv/fa/fb and of the update vectors   */
+    int32_t walkers;  /* W >= 1                                               */
+    int32_t n;        /* matrix dimension, 1..LRX_MAX_N (PF: even)            */
+    int32_t k_max;    /* largest rank per step (DET 1..8, PF 1)               */
+    int32_t delay;    /* K: 0 = plain update every step, else 1..LRX_MAX_DELAY */
+} lrx_shape;
+
+typedef struct lrx_sizes {     /* bytes; every buffer 256-byte aligned by the caller */
+    size_t inv, fa, fb, stash, logabs, phase, flags, work;
+    size_t stash_stride;       /* bytes of stash per walker                   */
+} lrx_sizes;
+
+typedef struct lrx_state {
+    lrx_shape shape;
+    int32_t slot;     /* delay slot tau in [0, K] (the paper's current_delay,
+                         Sec. II.C): accept_update writes slot `slot` and
+                         increments it; flush_delayed resets it to 0.  Uniform
+                         across the batch.                                     */
+    int32_t reserved;
+    void *inv, *fa, *fb, *stash;
+    double *logabs;
+    void *phase;
+    uint32_t *flags;
+    void *work;
+} lrx_state;
+
+/* Library version (LRX_VERSION). */
+int lrx_version(void);
+
+/* Static text for a return code (host). */
+const char *lrx_strerror(int code);
+
+/*
+ * Buffer sizes for a shape (host only; no GPU needed).
+ *   shape: host; out: host.  Returns LRX_ESHAPE / LRX_EUNSUPPORTED / LRX_EODD
+ *   for shapes the library does not handle.
+ */
+int lrx_state_sizes(const lrx_shape *shape, lrx_sizes *out);
+
+/* Host-side validation of a filled state (shape, non-null buffers, slot range). */
+int lrx_validate(const lrx_state *st);
+
+/* ------------------------------------------------------------------------ */
+/* Slater determinants (Sec. II)                                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Build A_0 and factorise it from scratch in FP64 (real states) or complex128
+ * (complex states): Gauss-Jordan inversion with partial pivoting, log|det A|
+ * and phase from the pivots.  Writes inv (cast to the bulk dtype), logabs,
+ * phase; clears flags; sets st->slot = 0 (delay slots are always rewritten
+ * before they are read, so they need no clearing).
+ *   phi : [sites][n] orbital matrix (FP64 or complex128), row s = orbital
+ *         values at site s.  A[w][i][:] = phi[occ[w][i]][:] (rows are electron
+ *         labels).  If occ is NULL, phi is instead a dense batch [W][n][n] and
+ *         A[w] = phi[w].
+ *   occ : int32 [W][n] occupied site of each electron, or NULL.
+ * An exactly singular A_0 sets LRX_FLAG_SINGULAR_A for that walker.
+ */
+int lrx_det_init_inverse(lrx_state *st, const void *phi, int32_t sites,
+                         const int32_t *occ, void *stream);
+
+/*
+ * Periodic refresh (bounds the drift of reduced-precision bulk updates,
+ * Sec. II.A stability remark).  Same factorisation as init_inverse on the
+ * current occupancy.  Pending delayed factors must have been flushed
+ * (st->slot == 0, else LRX_ENEEDFLUSH).
+ *   report: double [W][2] or NULL.  report[w][0] = ||M_lru - M_new||_F /
+ *           ||M_new||_F (inverse drift); report[w][1] = |log|det|_lru -
+ *           log|det|_new| + |phase_lru - phase_new| (log-determinant drift).
+ */
+int lrx_det_refresh(lrx_state *st, const void *phi, int32_t sites,
+                    const int32_t *occ, double *report, void *stream);
+
+/*
+ * Build the update vectors of one hop step (Sec. II.B rank-1 / rank-k row
+ * updates): electron elec[w][c] moves from site s = occ[w][elec[w][c]] to the
+ * empty site s' = empty[w][slot[w][c]], c < k[w], and
+ *   u[w][c][:] = phi[s'][:] - phi[s][:]   (computed in FP64/complex128, stored in
+ *                                          the bulk dtype; zero rows for c >= k[w]).
+ * The row-update form is A_t = A_{t-1} + v u^T with v the one-hot selector of
+ * rows elec[w][:k].
+ *   phi: [sites][n] FP64/complex128; occ: int32 [W][n]; empty: int32 [W][n_empty];
+ *   k: int32 [W] in 1..k_max; elec, slot: int32 [W][k_max]; u: bulk [W][k_max][n].
+ */
+int lrx_det_build_hop(const lrx_state *st, const void *phi, int32_t sites,
+                      const int32_t *occ, const int32_t *empty, int32_t n_empty,
+                      const int32_t *k, const int32_t *elec, const int32_t *slot,
+                      void *u, void *stream);
+
+/*
+ * Ratio of a proposed rank-k row update (Sec. II.A Eqs. det_ratio, det_R;
+ * delayed form Sec. II.C):
+ *   C = A_{tau-1}^-1[:, rows]  = (rows of M0) - sum_t a_t (b_t[rows, :])^T
+ *   R = I_k + u^T C,  r = det R   (k x k LU with partial pivoting).
+ * Stashes C, R^-1 and r for accept_update; writes ratio (double [W] for real
+ * states, complex double [W] for complex).  Reads no n x n data: the cost is
+ * O(n k + tau n k) per walker.  Entries c >= k[w] of rows/u are ignored.
+ *   k: int32 [W]; rows: int32 [W][k_max] distinct electron labels (the one-hot
+ *   v of Sec. II.B); u: bulk [W][k_max][n].
+ * det R == 0 or non-finite sets LRX_FLAG_SINGULAR_R / LRX_FLAG_NONFINITE.
+ */
+int lrx_det_propose_ratio(lrx_state *st, const int32_t *k, const int32_t *rows,
+                          const void *u, void *ratio, void *stream);
+
+/*
+ * Apply the proposal to walkers with accept[w] != 0 (and no flag set);
+ * logabs += log|r|, phase *= r/|r|.
+ *   K == 0: Sherman-Morrison/Woodbury, Eq. det_inv, in one pass over the rows
+ *           of M: M[q,:] -= (R^-1 (M[q,:] u)) . C^T.
+ *   K  > 0: writes slot tau = st->slot: a_tau = C and
+ *           b_tau = (M_{tau-1} u) R^-T  (Eqs. det_a, det_b and the a_tau/b_tau
+ *           recurrences of Sec. II.C); rejected walkers get a zero slot.
+ *           Then st->slot += 1.  Returns LRX_ENEEDFLUSH if st->slot == K.
+ * Must follow lrx_det_propose_ratio with the same k/rows/u.
+ *   accept: uint8 [W], in/out.  Walkers whose update is impossible (flagged,
+ *           or a zero / non-finite ratio, Sec. II.A) are skipped and their
+ *           accept byte is cleared, so a following lrx_hop_commit leaves
+ *           their occupancy unchanged.
+ */
+int lrx_det_accept_update(lrx_state *st, const int32_t *k, const int32_t *rows,
+                          const void *u, uint8_t *accept, void *stream);
+
+/*
+ * Flush the delay window (Eq. delayed_Ainv): M0 -= sum_{t<tau} b_t a_t^T as one
+ * batched MFMA GEMM with inner dimension tau*k_max, then zero the slots and
+ * set st->slot = 0.  A no-op when st->slot == 0 or K == 0.
+ */
+int lrx_det_flush_delayed(lrx_state *st, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Pfaffians (Sec. III)                                                     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Build A_0[w][i][j] = f[occ[w][i]][occ[w][j]] (or the dense skew batch f
+ * [W][n][n] when occ is NULL) and factorise from scratch in FP64/complex128:
+ * Parlett-Reid elimination for log|pf| and phase (Appendix A), Gauss-Jordan
+ * inversion, then M = (X - X^T)/2 so that M is exactly skew.  n must be even.
+ *   f: [sites][sites] skew pairing matrix (FP64 or complex128).
+ */
+int lrx_pf_init_inverse(lrx_state *st, const void *f, int32_t sites,
+                        const int32_t *occ, void *stream);
+
+/* Refresh of a Pfaffian state; report as for lrx_det_refresh. */
+int lrx_pf_refresh(lrx_state *st, const void *f, int32_t sites,
+                   const int32_t *occ, double *report, void *stream);
+
+/*
+ * Update vector of a single-electron hop in the Pfaffian state (Sec. III.B,
+ * "update of 1 row and 1 column", Eq. pf_rank2): electron i = elec[w][0]
+ * moves from s = occ[w][i] to s' = empty[w][slot[w][0]];
+ *   x[w][j] = f[s'][occ[w][j]] - f[s][occ[w][j]]  (j != i),  x[w][i] = 0,
+ * so that A_t = A_{t-1} - u J u^T with u = (x, e_i).  k must be 1.
+ *   x: bulk [W][n].
+ */
+int lrx_pf_build_hop(const lrx_state *st, const void *f, int32_t sites,
+                     const int32_t *occ, const int32_t *empty, int32_t n_empty,
+                     const int32_t *k, const int32_t *elec, const int32_t *slot,
+                     void *x, void *stream);
+
+/*
+ * Pfaffian ratio of u = (x, e_i) (Eqs. pf_ratio, pf_R with k = 1, pf J = 1):
+ *   col = A_{tau-1}^-1[:, i] = -M0[i, :]^T + sum_t a_t R_t^-1 a_t[i, :]^T
+ *   r   = R_12 = 1 + x . col.
+ * (R_11 = x^T A^-1 x vanishes because M is exactly skew.)  Stashes col, r and
+ * a_t^T x.  cols: int32 [W][k_max] (the one-hot e_i); x: bulk [W][n].
+ */
+int lrx_pf_propose_ratio(lrx_state *st, const int32_t *k, const int32_t *cols,
+                         const void *x, void *ratio, void *stream);
+
+/*
+ * Apply accepted Pfaffian hops.
+ *   K == 0: Eq. pf_inv with k = 1: a_x = M x (one pass), then
+ *           M += (col a_x^T - a_x col^T) / r (second pass), exactly skew.
+ *   K  > 0: slot tau: a_tau = [M_{tau-1} x, col], R_tau^-1 = [[0,-1/r],[1/r,0]]
+ *           (Eq. pf_a and the a_tau recurrence of Sec. III.C, with u_tau in
+ *           its first term).  Then st->slot += 1.
+ * accept is in/out as for lrx_det_accept_update.
+ */
+int lrx_pf_accept_update(lrx_state *st, const int32_t *k, const int32_t *cols,
+                         const void *x, uint8_t *accept, void *stream);
+
+/*
+ * Flush (Eq. pf_delayed_Ainv): M0 += sum_t a_t R_t^-1 a_t^T on MFMA, computing
+ * only tiles on and above the diagonal and writing the lower triangle as the
+ * exact negative transpose, so M0 stays exactly skew.  Zeroes the slots and
+ * sets st->slot = 0.
+ */
+int lrx_pf_flush_delayed(lrx_state *st, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Markov-chain helpers                                                     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Accept decisions from ratios (the chain's acceptance rule; the paper gives
+ * none, the library uses Metropolis on |r|^2).
+ *   ratio: as written by *_propose_ratio; u01: double [W] (mode
+ *   LRX_MH_UNIFORMS) or NULL; seed/counter: Philox-4x32-10 key and counter
+ *   (mode LRX_MH_DEVICE_RNG); accept: uint8 [W] out.  Flagged walkers, zero
+ *   and non-finite ratios are always rejected.
+ */
+int lrx_metropolis(const lrx_state *st, const void *ratio, const double *u01,
+                   uint64_t seed, uint64_t counter, int32_t mode,
+                   uint8_t *accept, void *stream);
+
+/*
+ * Occupancy bookkeeping after a step: for accepted walkers and c < k[w],
+ * swap occ[w][elec[w][c]] with empty[w][slot[w][c]].
+ */
+int lrx_hop_commit(int32_t walkers, int32_t n, int32_t n_empty, int32_t k_max,
+                   const int32_t *k, const int32_t *elec, const int32_t *slot,
+                   const uint8_t *accept, int32_t *occ, int32_t *empty,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRX_H */

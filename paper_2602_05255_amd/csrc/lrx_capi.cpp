@@ -1,0 +1,334 @@
+// C ABI of liblrx: host-side validation, buffer sizing and kernel dispatch.
+// Every check here runs on the host before anything is enqueued, so the error
+// paths are testable without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include "../../include/lrx.h"
+#include "lrx_internal.hpp"
+
+namespace lrx {
+
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+Layout stash_layout(const lrx_shape &s) {
+    const size_t es = bulk_bytes(s.dtype);
+    const int n = s.n, KM = s.k_max, K = s.delay;
+    const bool pf = s.kind == LRX_PF;
+    const int KA = pf ? 2 * KM : KM;
+    Layout L;
+    size_t off = 0;
+    L.c = (uint32_t)off; off += al256((size_t)(pf ? 1 : KM) * n * es);
+    L.rinv = (uint32_t)off; off += al256((size_t)KM * KM * es);
+    L.g = (uint32_t)off; off += al256((size_t)(K > 0 ? K : 1) * KA * (pf ? 1 : KM) * es);
+    L.ratio = (uint32_t)off; off += al256(16);
+    L.kslot = (uint32_t)off; off += al256((size_t)(K > 0 ? K : 1) * 4);
+    L.ax = (uint32_t)off; off += al256(pf ? (size_t)n * es : 16);
+    L.stride = (uint32_t)off;
+    return L;
+}
+
+// Largest padded row length the row-streaming kernels hold in LDS.
+static size_t padded_n(int n, size_t es) {
+    const int per = (int)(16 / es) * 64;
+    int nch = (n + per - 1) / per;
+    int p2 = 1;
+    while (p2 < nch) p2 <<= 1;
+    return (size_t)p2 * per;
+}
+
+static int check_shape(const lrx_shape *s) {
+    if (!s) return LRX_EINVAL;
+    if (s->kind != LRX_DET && s->kind != LRX_PF) return LRX_EUNSUPPORTED;
+    if (s->dtype < LRX_F32 || s->dtype > LRX_C128) return LRX_EUNSUPPORTED;
+    if (s->walkers < 1 || s->n < 1 || s->n > LRX_MAX_N) return LRX_ESHAPE;
+    if (s->delay < 0 || s->delay > LRX_MAX_DELAY) return LRX_ESHAPE;
+    const size_t es = bulk_bytes(s->dtype);
+    if (s->kind == LRX_DET) {
+        if (s->k_max != 1 && s->k_max != 2 && s->k_max != 4 && s->k_max != 8) return LRX_ESHAPE;
+        if (s->k_max > s->n) return LRX_ESHAPE;
+        // accept kernel keeps u and C panels in LDS
+        if (2 * (size_t)s->k_max * padded_n(s->n, es) * es > 65536) return LRX_EUNSUPPORTED;
+        // delayed accept: a lane owns at most 4 slot columns
+        if ((size_t)s->delay * s->k_max > 256) return LRX_ESHAPE;
+        // propose keeps b-slot rows I in LDS
+        if ((size_t)s->k_max * s->delay * s->k_max * es > 49152) return LRX_EUNSUPPORTED;
+    } else {
+        if (s->n & 1) return LRX_EODD;
+        if (s->k_max != 1) return LRX_EUNSUPPORTED;
+        if (s->n < 2) return LRX_ESHAPE;
+    }
+    return LRX_OK;
+}
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+static int hip_rc(hipError_t e) { return e == hipSuccess ? LRX_OK : LRX_EHIP; }
+
+static StepArgs step_args(const lrx_state *st) {
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.W = st->shape.walkers;
+    a.n = st->shape.n;
+    a.KM = st->shape.k_max;
+    a.K = st->shape.delay;
+    a.tau = st->slot;
+    a.aligned = ((size_t)st->shape.n * bulk_bytes(st->shape.dtype)) % 16 == 0 ? 1 : 0;
+    a.inv = st->inv;
+    a.fa = st->fa;
+    a.fb = st->fb;
+    a.stash = static_cast<uint8_t *>(st->stash);
+    a.L = stash_layout(st->shape);
+    a.logabs = st->logabs;
+    a.phase = st->phase;
+    a.flags = st->flags;
+    return a;
+}
+
+}  // namespace lrx
+
+using namespace lrx;
+
+extern "C" {
+
+int lrx_version(void) { return LRX_VERSION; }
+
+const char *lrx_strerror(int code) {
+    switch (code) {
+        case LRX_OK: return "ok";
+        case LRX_EINVAL: return "invalid argument (null pointer, bad mode or size)";
+        case LRX_EUNSUPPORTED: return "unsupported kind/dtype/rank combination";
+        case LRX_ESHAPE: return "shape out of range (n, walkers, k_max or delay)";
+        case LRX_ENEEDFLUSH: return "delay window full: call flush_delayed first";
+        case LRX_EODD: return "Pfaffian state with odd n";
+        case LRX_EHIP: return "HIP launch or runtime error";
+        case LRX_EKIND: return "entry point does not match the state kind";
+    }
+    return "unknown error";
+}
+
+int lrx_state_sizes(const lrx_shape *shape, lrx_sizes *out) {
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    if (!out) return LRX_EINVAL;
+    const size_t W = shape->walkers, n = shape->n, K = shape->delay, KM = shape->k_max;
+    const size_t es = bulk_bytes(shape->dtype);
+    const bool pf = shape->kind == LRX_PF;
+    const size_t KA = pf ? 2 * KM : KM;
+    memset(out, 0, sizeof(*out));
+    out->inv = W * n * n * es;
+    out->fa = W * K * KA * n * es;
+    out->fb = pf ? W * K * KA * KA * es : W * n * K * KM * es;
+    const Layout L = stash_layout(*shape);
+    out->stash_stride = L.stride;
+    out->stash = W * L.stride;
+    out->logabs = W * 8;
+    out->phase = W * wide_bytes(shape->dtype);
+    out->flags = W * 4;
+    out->work = factor_work_bytes(shape->kind, shape->dtype, shape->walkers, shape->n);
+    return LRX_OK;
+}
+
+int lrx_validate(const lrx_state *st) {
+    if (!st) return LRX_EINVAL;
+    int rc = check_shape(&st->shape);
+    if (rc) return rc;
+    if (!st->inv || !st->stash || !st->logabs || !st->phase || !st->flags || !st->work) return LRX_EINVAL;
+    if (st->shape.delay > 0 && (!st->fa || !st->fb)) return LRX_EINVAL;
+    if (st->slot < 0 || st->slot > st->shape.delay) return LRX_EINVAL;
+    return LRX_OK;
+}
+
+static int check_kind(const lrx_state *st, int kind) {
+    int rc = lrx_validate(st);
+    if (rc) return rc;
+    return st->shape.kind == kind ? LRX_OK : LRX_EKIND;
+}
+
+static int factor_common(lrx_state *st, int kind, const void *src, int32_t sites, const int32_t *occ,
+                         double *report, int refresh, void *stream) {
+    int rc = check_kind(st, kind);
+    if (rc) return rc;
+    if (!src) return LRX_EINVAL;
+    if (occ) {
+        if (kind == LRX_DET && sites < 1) return LRX_ESHAPE;
+        if (kind == LRX_PF && sites < st->shape.n) return LRX_ESHAPE;
+    }
+    if (refresh && st->shape.delay > 0 && st->slot != 0) return LRX_ENEEDFLUSH;
+    FactorArgs a;
+    a.kind = kind;
+    a.dtype = st->shape.dtype;
+    a.W = st->shape.walkers;
+    a.n = st->shape.n;
+    a.sites = sites;
+    a.src = src;
+    a.occ = occ;
+    a.work = st->work;
+    a.inv = st->inv;
+    a.logabs = st->logabs;
+    a.phase = st->phase;
+    a.flags = st->flags;
+    a.report = refresh ? report : nullptr;
+    a.refresh = refresh;
+    rc = hip_rc(factor(a, as_stream(stream)));
+    if (rc == LRX_OK) st->slot = 0;
+    return rc;
+}
+
+int lrx_det_init_inverse(lrx_state *st, const void *phi, int32_t sites, const int32_t *occ, void *stream) {
+    return factor_common(st, LRX_DET, phi, sites, occ, nullptr, 0, stream);
+}
+
+int lrx_det_refresh(lrx_state *st, const void *phi, int32_t sites, const int32_t *occ, double *report,
+                    void *stream) {
+    return factor_common(st, LRX_DET, phi, sites, occ, report, 1, stream);
+}
+
+int lrx_pf_init_inverse(lrx_state *st, const void *f, int32_t sites, const int32_t *occ, void *stream) {
+    return factor_common(st, LRX_PF, f, sites, occ, nullptr, 0, stream);
+}
+
+int lrx_pf_refresh(lrx_state *st, const void *f, int32_t sites, const int32_t *occ, double *report,
+                   void *stream) {
+    return factor_common(st, LRX_PF, f, sites, occ, report, 1, stream);
+}
+
+static int build_hop_common(const lrx_state *st, int kind, const void *phi, int32_t sites, const int32_t *occ,
+                            const int32_t *empty, int32_t n_empty, const int32_t *k, const int32_t *elec,
+                            const int32_t *slot, void *out, void *stream) {
+    int rc = check_kind(st, kind);
+    if (rc) return rc;
+    if (!phi || !occ || !empty || !k || !elec || !slot || !out) return LRX_EINVAL;
+    if (sites < st->shape.n || n_empty < 1) return LRX_ESHAPE;
+    HopArgs a;
+    a.W = st->shape.walkers;
+    a.n = st->shape.n;
+    a.KM = st->shape.k_max;
+    a.sites = sites;
+    a.n_empty = n_empty;
+    a.phi = phi;
+    a.occ = occ;
+    a.empty = empty;
+    a.k = k;
+    a.elec = elec;
+    a.slot = slot;
+    a.out = out;
+    a.flags = st->flags;
+    hipError_t e = kind == LRX_DET ? det_build_hop(st->shape.dtype, a, as_stream(stream))
+                                   : pf_build_hop(st->shape.dtype, a, as_stream(stream));
+    return hip_rc(e);
+}
+
+int lrx_det_build_hop(const lrx_state *st, const void *phi, int32_t sites, const int32_t *occ,
+                      const int32_t *empty, int32_t n_empty, const int32_t *k, const int32_t *elec,
+                      const int32_t *slot, void *u, void *stream) {
+    return build_hop_common(st, LRX_DET, phi, sites, occ, empty, n_empty, k, elec, slot, u, stream);
+}
+
+int lrx_pf_build_hop(const lrx_state *st, const void *f, int32_t sites, const int32_t *occ,
+                     const int32_t *empty, int32_t n_empty, const int32_t *k, const int32_t *elec,
+                     const int32_t *slot, void *x, void *stream) {
+    return build_hop_common(st, LRX_PF, f, sites, occ, empty, n_empty, k, elec, slot, x, stream);
+}
+
+int lrx_det_propose_ratio(lrx_state *st, const int32_t *k, const int32_t *rows, const void *u, void *ratio,
+                          void *stream) {
+    int rc = check_kind(st, LRX_DET);
+    if (rc) return rc;
+    if (!k || !rows || !u || !ratio) return LRX_EINVAL;
+    if (st->shape.delay > 0 && st->slot >= st->shape.delay) return LRX_ENEEDFLUSH;
+    StepArgs a = step_args(st);
+    a.k = k;
+    a.rows = rows;
+    a.u = u;
+    a.ratio = ratio;
+    return hip_rc(det_propose(st->shape.dtype, a, as_stream(stream)));
+}
+
+int lrx_det_accept_update(lrx_state *st, const int32_t *k, const int32_t *rows, const void *u,
+                          uint8_t *accept, void *stream) {
+    int rc = check_kind(st, LRX_DET);
+    if (rc) return rc;
+    if (!k || !rows || !u || !accept) return LRX_EINVAL;
+    if (st->shape.delay > 0 && st->slot >= st->shape.delay) return LRX_ENEEDFLUSH;
+    StepArgs a = step_args(st);
+    a.k = k;
+    a.rows = rows;
+    a.u = u;
+    a.accept = accept;
+    rc = hip_rc(det_accept(st->shape.dtype, a, as_stream(stream)));
+    if (rc == LRX_OK && st->shape.delay > 0) st->slot += 1;
+    return rc;
+}
+
+int lrx_det_flush_delayed(lrx_state *st, void *stream) {
+    int rc = check_kind(st, LRX_DET);
+    if (rc) return rc;
+    if (st->shape.delay == 0 || st->slot == 0) return LRX_OK;
+    StepArgs a = step_args(st);
+    rc = hip_rc(det_flush(st->shape.dtype, a, as_stream(stream)));
+    if (rc == LRX_OK) st->slot = 0;
+    return rc;
+}
+
+int lrx_pf_propose_ratio(lrx_state *st, const int32_t *k, const int32_t *cols, const void *x, void *ratio,
+                         void *stream) {
+    int rc = check_kind(st, LRX_PF);
+    if (rc) return rc;
+    if (!k || !cols || !x || !ratio) return LRX_EINVAL;
+    if (st->shape.delay > 0 && st->slot >= st->shape.delay) return LRX_ENEEDFLUSH;
+    StepArgs a = step_args(st);
+    a.k = k;
+    a.rows = cols;
+    a.u = x;
+    a.ratio = ratio;
+    return hip_rc(pf_propose(st->shape.dtype, a, as_stream(stream)));
+}
+
+int lrx_pf_accept_update(lrx_state *st, const int32_t *k, const int32_t *cols, const void *x,
+                         uint8_t *accept, void *stream) {
+    int rc = check_kind(st, LRX_PF);
+    if (rc) return rc;
+    if (!k || !cols || !x || !accept) return LRX_EINVAL;
+    if (st->shape.delay > 0 && st->slot >= st->shape.delay) return LRX_ENEEDFLUSH;
+    StepArgs a = step_args(st);
+    a.k = k;
+    a.rows = cols;
+    a.u = x;
+    a.accept = accept;
+    rc = hip_rc(pf_accept(st->shape.dtype, a, as_stream(stream)));
+    if (rc == LRX_OK && st->shape.delay > 0) st->slot += 1;
+    return rc;
+}
+
+int lrx_pf_flush_delayed(lrx_state *st, void *stream) {
+    int rc = check_kind(st, LRX_PF);
+    if (rc) return rc;
+    if (st->shape.delay == 0 || st->slot == 0) return LRX_OK;
+    StepArgs a = step_args(st);
+    rc = hip_rc(pf_flush(st->shape.dtype, a, as_stream(stream)));
+    if (rc == LRX_OK) st->slot = 0;
+    return rc;
+}
+
+int lrx_metropolis(const lrx_state *st, const void *ratio, const double *u01, uint64_t seed, uint64_t counter,
+                   int32_t mode, uint8_t *accept, void *stream) {
+    int rc = lrx_validate(st);
+    if (rc) return rc;
+    if (!ratio || !accept) return LRX_EINVAL;
+    if (mode != LRX_MH_UNIFORMS && mode != LRX_MH_DEVICE_RNG && mode != LRX_MH_FORCE) return LRX_EINVAL;
+    if (mode == LRX_MH_UNIFORMS && !u01) return LRX_EINVAL;
+    return hip_rc(metropolis(st->shape.dtype, st->shape.walkers, ratio, u01, seed, counter, mode, st->flags,
+                             accept, as_stream(stream)));
+}
+
+int lrx_hop_commit(int32_t walkers, int32_t n, int32_t n_empty, int32_t k_max, const int32_t *k,
+                   const int32_t *elec, const int32_t *slot, const uint8_t *accept, int32_t *occ,
+                   int32_t *empty, void *stream) {
+    if (walkers < 1 || n < 1 || n_empty < 1 || k_max < 1 || k_max > LRX_MAX_KMAX_DET) return LRX_ESHAPE;
+    if (!k || !elec || !slot || !accept || !occ || !empty) return LRX_EINVAL;
+    return hip_rc(hop_commit(walkers, n, n_empty, k_max, k, elec, slot, accept, occ, empty, as_stream(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+// Shared device helpers for the lrx kernels (gfx950, wave64).
+//
+// Scalar types: float, double, cf32, cf64 (interleaved complex).  Complex
+// arithmetic is written out so that the same template code serves all four
+// bulk dtypes; products are never conjugated (the method uses plain
+// transposes for complex matrices).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "../../include/lrx.h"
+
+#define LRX_WAVE 64
+
+struct cf32 { float x, y; };
+struct cf64 { double x, y; };
+
+template <class T> struct Real;
+template <> struct Real<float> { using type = float; static constexpr bool cplx = false; };
+template <> struct Real<double> { using type = double; static constexpr bool cplx = false; };
+template <> struct Real<cf32> { using type = float; static constexpr bool cplx = true; };
+template <> struct Real<cf64> { using type = double; static constexpr bool cplx = true; };
+
+// Wide ("FP64 or complex128") type used by init/refresh and for ratios.
+template <class T> struct Wide;
+template <> struct Wide<float> { using type = double; };
+template <> struct Wide<double> { using type = double; };
+template <> struct Wide<cf32> { using type = cf64; };
+template <> struct Wide<cf64> { using type = cf64; };
+
+// ---------------------------------------------------------------- arithmetic
+__host__ __device__ inline cf32 operator+(cf32 a, cf32 b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cf32 operator-(cf32 a, cf32 b) { return {a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline cf32 operator-(cf32 a) { return {-a.x, -a.y}; }
+__host__ __device__ inline cf32 operator*(cf32 a, cf32 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__host__ __device__ inline cf64 operator+(cf64 a, cf64 b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cf64 operator-(cf64 a, cf64 b) { return {a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline cf64 operator-(cf64 a) { return {-a.x, -a.y}; }
+__host__ __device__ inline cf64 operator*(cf64 a, cf64 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+
+template <class T> __device__ __forceinline__ T zero() { return T{}; }
+template <class T> __device__ __forceinline__ T one();
+template <> __device__ __forceinline__ float one<float>() { return 1.0f; }
+template <> __device__ __forceinline__ double one<double>() { return 1.0; }
+template <> __device__ __forceinline__ cf32 one<cf32>() { return {1.0f, 0.0f}; }
+template <> __device__ __forceinline__ cf64 one<cf64>() { return {1.0, 0.0}; }
+
+// a*b + c
+__device__ __forceinline__ float fmac(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ cf32 fmac(cf32 a, cf32 b, cf32 c) {
+    return {fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y))};
+}
+__device__ __forceinline__ cf64 fmac(cf64 a, cf64 b, cf64 c) {
+    return {fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
+}
+// c - a*b
+__device__ __forceinline__ float fmsc(float a, float b, float c) { return fmaf(-a, b, c); }
+__device__ __forceinline__ double fmsc(double a, double b, double c) { return fma(-a, b, c); }
+__device__ __forceinline__ cf32 fmsc(cf32 a, cf32 b, cf32 c) { return fmac(-a, b, c); }
+__device__ __forceinline__ cf64 fmsc(cf64 a, cf64 b, cf64 c) { return fmac(-a, b, c); }
+
+__device__ __forceinline__ double absv(float a) { return fabs((double)a); }
+__device__ __forceinline__ double absv(double a) { return fabs(a); }
+__device__ __forceinline__ double absv(cf32 a) { return hypot((double)a.x, (double)a.y); }
+__device__ __forceinline__ double absv(cf64 a) { return hypot(a.x, a.y); }
+
+__device__ __forceinline__ bool finite_v(float a) { return isfinite(a); }
+__device__ __forceinline__ bool finite_v(double a) { return isfinite(a); }
+__device__ __forceinline__ bool finite_v(cf32 a) { return isfinite(a.x) && isfinite(a.y); }
+__device__ __forceinline__ bool finite_v(cf64 a) { return isfinite(a.x) && isfinite(a.y); }
+
+__device__ __forceinline__ bool is_zero(float a) { return a == 0.0f; }
+__device__ __forceinline__ bool is_zero(double a) { return a == 0.0; }
+__device__ __forceinline__ bool is_zero(cf32 a) { return a.x == 0.0f && a.y == 0.0f; }
+__device__ __forceinline__ bool is_zero(cf64 a) { return a.x == 0.0 && a.y == 0.0; }
+
+// Division a / b.
+__device__ __forceinline__ float divv(float a, float b) { return a / b; }
+__device__ __forceinline__ double divv(double a, double b) { return a / b; }
+__device__ __forceinline__ cf64 divv(cf64 a, cf64 b) {
+    // Smith's algorithm (avoids overflow in |b|^2).
+    if (fabs(b.x) >= fabs(b.y)) {
+        double r = b.y / b.x, d = b.x + b.y * r;
+        return {(a.x + a.y * r) / d, (a.y - a.x * r) / d};
+    }
+    double r = b.x / b.y, d = b.x * r + b.y;
+    return {(a.x * r + a.y) / d, (a.y * r - a.x) / d};
+}
+__device__ __forceinline__ cf32 divv(cf32 a, cf32 b) {
+    cf64 q = divv(cf64{a.x, a.y}, cf64{b.x, b.y});
+    return {(float)q.x, (float)q.y};
+}
+
+// Conversions between precisions (same complexness).
+template <class D, class S> __device__ __forceinline__ D conv(S s);
+template <> __device__ __forceinline__ float conv<float, double>(double s) { return (float)s; }
+template <> __device__ __forceinline__ double conv<double, double>(double s) { return s; }
+template <> __device__ __forceinline__ double conv<double, float>(float s) { return (double)s; }
+template <> __device__ __forceinline__ float conv<float, float>(float s) { return s; }
+template <> __device__ __forceinline__ cf32 conv<cf32, cf64>(cf64 s) { return {(float)s.x, (float)s.y}; }
+template <> __device__ __forceinline__ cf64 conv<cf64, cf64>(cf64 s) { return s; }
+template <> __device__ __forceinline__ cf64 conv<cf64, cf32>(cf32 s) { return {(double)s.x, (double)s.y}; }
+template <> __device__ __forceinline__ cf32 conv<cf32, cf32>(cf32 s) { return s; }
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ float shfl_xor_v(float v, int m) { return __shfl_xor(v, m, LRX_WAVE); }
+__device__ __forceinline__ double shfl_xor_v(double v, int m) { return __shfl_xor(v, m, LRX_WAVE); }
+__device__ __forceinline__ cf32 shfl_xor_v(cf32 v, int m) {
+    return {__shfl_xor(v.x, m, LRX_WAVE), __shfl_xor(v.y, m, LRX_WAVE)};
+}
+__device__ __forceinline__ cf64 shfl_xor_v(cf64 v, int m) {
+    return {__shfl_xor(v.x, m, LRX_WAVE), __shfl_xor(v.y, m, LRX_WAVE)};
+}
+
+// Sum over the 64 lanes of a wave; every lane receives the total.
+template <class T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = v + shfl_xor_v(v, m);
+    return v;
+}
+
+// Reduce NV values per lane across the wave with a butterfly that halves the
+// live values each round: the round exchanging with lane ^ h keeps the upper
+// half of the live values on lanes with bit h set, so after log2(NV) rounds
+// lane l holds a partial of value (l mod NV); the remaining rounds finish the
+// sum.  Returns the total of value (lane mod NV) on every lane.  NV must be a
+// power of two <= 64.  Cost: NV - 1 + 6 - log2(NV) exchanges instead of 6 NV.
+template <class T, int NV> __device__ __forceinline__ T wave_sum_multi(T (&v)[NV]) {
+    const int lane = threadIdx.x & (LRX_WAVE - 1);
+#pragma unroll
+    for (int half = NV / 2; half >= 1; half >>= 1) {
+        const int bit = half;
+        const bool up = (lane & bit) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            T send = up ? v[i] : v[i + half];
+            T keep = up ? v[i + half] : v[i];
+            v[i] = keep + shfl_xor_v(send, bit);
+        }
+    }
+    T r = v[0];
+#pragma unroll
+    for (int m = NV; m < LRX_WAVE; m <<= 1) r = r + shfl_xor_v(r, m);
+    return r;
+}
+
+// ---------------------------------------------------------------- small LU
+// In-place LU with partial pivoting of a k x k matrix held by one thread
+// (row-major, stride KM).  Returns det(R) in the wide type, writes R^-1 into
+// inv (stride KM).  singular = true when a pivot is exactly zero.
+template <class T, int KM>
+__device__ void small_lu_det_inv(T (&r)[KM * KM], int k, T (&inv)[KM * KM],
+                                 typename Wide<T>::type &det, bool &singular) {
+    using W = typename Wide<T>::type;
+    int piv[KM];
+    W d = one<W>();
+    singular = false;
+    for (int j = 0; j < k; ++j) {
+        int p = j;
+        double best = absv(r[j * KM + j]);
+        for (int i = j + 1; i < k; ++i) {
+            double a = absv(r[i * KM + j]);
+            if (a > best) { best = a; p = i; }
+        }
+        piv[j] = p;
+        if (p != j) {
+            for (int c = 0; c < k; ++c) { T t = r[j * KM + c]; r[j * KM + c] = r[p * KM + c]; r[p * KM + c] = t; }
+            d = -d;
+        }
+        T dj = r[j * KM + j];
+        d = d * conv<W>(dj);
+        if (is_zero(dj)) { singular = true; continue; }
+        for (int i = j + 1; i < k; ++i) {
+            T l = divv(r[i * KM + j], dj);
+            r[i * KM + j] = l;
+            for (int c = j + 1; c < k; ++c) r[i * KM + c] = fmsc(l, r[j * KM + c], r[i * KM + c]);
+        }
+    }
+    det = d;
+    if (singular) return;
+    // Columns of the inverse: solve L U x = P e_c.
+    for (int c = 0; c < k; ++c) {
+        T col[KM];
+        for (int i = 0; i < k; ++i) col[i] = (i == c) ? one<T>() : zero<T>();
+        for (int j = 0; j < k; ++j) { int p = piv[j]; if (p != j) { T t = col[j]; col[j] = col[p]; col[p] = t; } }
+        for (int i = 0; i < k; ++i) {
+            T s = col[i];
+            for (int j = 0; j < i; ++j) s = fmsc(r[i * KM + j], col[j], s);
+            col[i] = s;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            T s = col[i];
+            for (int j = i + 1; j < k; ++j) s = fmsc(r[i * KM + j], col[j], s);
+            col[i] = divv(s, r[i * KM + i]);
+        }
+        for (int i = 0; i < k; ++i) inv[i * KM + c] = col[i];
+    }
+}
+
+// ---------------------------------------------------------------- log|r|, phase
+__device__ __forceinline__ void accum_logphase(double r, double *logabs, double *phase) {
+    *logabs += log(fabs(r));
+    if (r < 0) *phase = -*phase;
+}
+__device__ __forceinline__ void accum_logphase(cf64 r, double *logabs, cf64 *phase) {
+    double m = hypot(r.x, r.y);
+    *logabs += log(m);
+    cf64 u = {r.x / m, r.y / m};
+    *phase = (*phase) * u;
+}
+
+// ---------------------------------------------------------------- XCD mapping
+// Work-groups are dispatched round-robin over the 8 XCDs of the MI355X
+// (block b runs on XCD b % 8).  Remap so that consecutive logical blocks --
+// the row blocks of one walker -- land on the same XCD and share its L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nblocks) {
+    const uint32_t nx = 8;
+    uint32_t per = nblocks / nx;
+    if (per == 0 || b >= per * nx) return b;   // ragged tail keeps its own order
+    return (b % nx) * per + (b / nx);
+}
+
+// ---------------------------------------------------------------- 16-byte IO
+template <class T> constexpr int vec16() { return (int)(16 / sizeof(T)); }
+
+template <class T>
+__device__ __forceinline__ void ld16(const T *p, T (&o)[vec16<T>()]) {
+    uint4 raw = *reinterpret_cast<const uint4 *>(p);
+    __builtin_memcpy(&o[0], &raw, 16);
+}
+template <class T>
+__device__ __forceinline__ void st16(T *p, const T (&o)[vec16<T>()]) {
+    uint4 raw;
+    __builtin_memcpy(&raw, &o[0], 16);
+    *reinterpret_cast<uint4 *>(p) = raw;
+}

@@ -1,0 +1,671 @@
+// Initialisation and periodic refresh: from-scratch factorisation in FP64 /
+// complex128 (the paper advises double precision for the stored inverse and
+// the determinant, Sec. I and the stability remark of Sec. II.A).
+//
+//   DET: B = A^T is inverted by blocked Gauss-Jordan elimination with partial
+//        pivoting, giving M = B^-1 = A^-T directly in the state layout;
+//        log|det A| and its phase come from the pivots.
+//   PF : log|pf A| and phase by Parlett-Reid elimination (a congruence that
+//        brings the largest entry of the leading column next to the diagonal,
+//        pf(B A B^T) = det(B) pf(A), then the block Schur step of Appendix A,
+//        Eq. pf_block, which splits off a 2x2 block whose Pfaffian is its (0,1)
+//        entry); A^-1 by the same Gauss-Jordan kernels, then M = (X - X^T)/2.
+//
+// Blocked Gauss-Jordan, one panel of nb columns at a time (all in the
+// workspace X, row-major):
+//   panel kernel : LU with partial pivoting of the panel rows j0..n-1 in LDS;
+//                  with Y_P the pivoted nb x nb diagonal block, the transform
+//                  that turns the panel into identity columns is I + Z E_P^T
+//                  with Z[P] = Y_P^-1 - I, Z[below] = -L21 L11^-1,
+//                  Z[above] = -Y_above Y_P^-1.  The panel columns become the
+//                  matching inverse columns, Z + E_P.
+//   update kernel: every other column: swap rows, then X += Z X[P rows].
+//   final kernel : undo the row pivoting as a column permutation, cast to the
+//                  bulk dtype, and (refresh) measure the drift of the old state.
+#include "lrx_common.hpp"
+#include "lrx_internal.hpp"
+
+namespace {
+
+using lrx::FactorArgs;
+
+constexpr int kT = 256;
+constexpr size_t kAlign = 256;
+inline size_t al(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+struct DetAcc {          // per-walker accumulators in the workspace
+    double logabs;       // LU (Gauss-Jordan) log|det|
+    double pad0;
+    double ph[2];        // LU phase (re, im)
+    double pf_logabs;    // Parlett-Reid log|pf|
+    double pad1;
+    double pf_ph[2];     // Parlett-Reid phase
+    double dsq, nsq;     // refresh drift sums
+    int singular;        // LU met a zero pivot
+    int pf_zero;         // Parlett-Reid met a zero pivot
+};
+
+struct WorkLayout {
+    size_t x, z, piv, src, acc, stride;
+};
+
+inline int panel_nb(int n, size_t ws) {
+    // Largest power of two <= 32 with n * nb * ws <= 64 KiB of LDS.
+    int nb = 32;
+    while (nb > 1 && (size_t)n * nb * ws > 65536) nb >>= 1;
+    return nb;
+}
+
+inline WorkLayout work_layout(int n, size_t ws) {
+    WorkLayout L;
+    size_t off = 0;
+    L.x = off; off += al((size_t)n * n * ws);
+    L.z = off; off += al((size_t)n * 32 * ws);
+    L.piv = off; off += al((size_t)n * 4);
+    L.src = off; off += al((size_t)n * 4);
+    L.acc = off; off += al(sizeof(DetAcc));
+    L.stride = off;
+    return L;
+}
+
+struct FA {              // device-side argument block
+    int kind, W, n, sites, nb;
+    const void *src;
+    const int32_t *occ;
+    uint8_t *work;
+    WorkLayout L;
+    void *inv;
+    double *logabs;
+    void *phase;
+    uint32_t *flags;
+    double *report;
+    int refresh;
+};
+
+template <class Wd> __device__ __forceinline__ Wd *wX(const FA &a, int w) {
+    return reinterpret_cast<Wd *>(a.work + (size_t)w * a.L.stride + a.L.x);
+}
+template <class Wd> __device__ __forceinline__ Wd *wZ(const FA &a, int w) {
+    return reinterpret_cast<Wd *>(a.work + (size_t)w * a.L.stride + a.L.z);
+}
+__device__ __forceinline__ int *wPiv(const FA &a, int w) {
+    return reinterpret_cast<int *>(a.work + (size_t)w * a.L.stride + a.L.piv);
+}
+__device__ __forceinline__ int *wSrc(const FA &a, int w) {
+    return reinterpret_cast<int *>(a.work + (size_t)w * a.L.stride + a.L.src);
+}
+__device__ __forceinline__ DetAcc *wAcc(const FA &a, int w) {
+    return reinterpret_cast<DetAcc *>(a.work + (size_t)w * a.L.stride + a.L.acc);
+}
+
+__device__ __forceinline__ void set_ph(double *p, double v) { p[0] = v; p[1] = 0.0; }
+__device__ __forceinline__ void set_ph(double *p, cf64 v) { p[0] = v.x; p[1] = v.y; }
+template <class Wd> __device__ __forceinline__ Wd get_ph(const double *p);
+template <> __device__ __forceinline__ double get_ph<double>(const double *p) { return p[0]; }
+template <> __device__ __forceinline__ cf64 get_ph<cf64>(const double *p) { return {p[0], p[1]}; }
+__device__ __forceinline__ double unit(double v) { return v < 0 ? -1.0 : 1.0; }
+__device__ __forceinline__ cf64 unit(cf64 v) { double m = hypot(v.x, v.y); return {v.x / m, v.y / m}; }
+__device__ __forceinline__ double absdiff(double a, double b) { return fabs(a - b); }
+__device__ __forceinline__ double absdiff(cf64 a, cf64 b) { return hypot(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double abs2(double a) { return a * a; }
+__device__ __forceinline__ double half_of(double a) { return 0.5 * a; }
+__device__ __forceinline__ cf64 half_of(cf64 a) { return {0.5 * a.x, 0.5 * a.y}; }
+__device__ __forceinline__ double abs2(cf64 a) { return a.x * a.x + a.y * a.y; }
+
+// ------------------------------------------------------------------ load
+// X <- A^T (DET) or A (PF).  A[i][j]: DET phi[occ[i]][j] (or dense src[w][i][j]);
+// PF f[occ[i]][occ[j]] (or dense).  32x32 tiles transposed through LDS.
+template <class Wd>
+__global__ __launch_bounds__(kT) void load_kernel(FA a, int tiles) {
+    __shared__ Wd tile[32][33];
+    const int n = a.n;
+    const int w = blockIdx.x / (tiles * tiles);
+    const int t = blockIdx.x - w * tiles * tiles;
+    const int ti = t / tiles, tj = t - ti * tiles;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const Wd *src = static_cast<const Wd *>(a.src);
+    Wd *X = wX<Wd>(a, w);
+    const int32_t *occ = a.occ ? a.occ + (size_t)w * n : nullptr;
+    // Tile of A: rows ti*32.., columns tj*32..
+    for (int r = ty; r < 32; r += 8) {
+        const int i = ti * 32 + r, j = tj * 32 + tx;
+        Wd v = zero<Wd>();
+        if (i < n && j < n) {
+            // Out-of-range sites give a zero row (the walker is then flagged singular).
+            if (a.kind == LRX_DET) {
+                if (!occ) v = src[((size_t)w * n + i) * n + j];
+                else if (occ[i] >= 0 && occ[i] < a.sites) v = src[(size_t)occ[i] * n + j];
+            } else {
+                if (!occ) v = src[((size_t)w * n + i) * n + j];
+                else if (occ[i] >= 0 && occ[i] < a.sites && occ[j] >= 0 && occ[j] < a.sites)
+                    v = src[(size_t)occ[i] * a.sites + occ[j]];
+            }
+        }
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    if (a.kind == LRX_DET) {   // X[j][i] = A[i][j]
+        for (int r = ty; r < 32; r += 8) {
+            const int j = tj * 32 + r, i = ti * 32 + tx;
+            if (i < n && j < n) X[(size_t)j * n + i] = tile[tx][r];
+        }
+    } else {
+        for (int r = ty; r < 32; r += 8) {
+            const int i = ti * 32 + r, j = tj * 32 + tx;
+            if (i < n && j < n) X[(size_t)i * n + j] = tile[r][tx];
+        }
+    }
+}
+
+template <class Wd>
+__global__ void init_acc_kernel(FA a) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    DetAcc *d = wAcc(a, w);
+    d->logabs = 0.0;
+    d->ph[0] = 1.0; d->ph[1] = 0.0;
+    d->pf_logabs = 0.0;
+    d->pf_ph[0] = 1.0; d->pf_ph[1] = 0.0;
+    d->dsq = 0.0; d->nsq = 0.0;
+    d->singular = 0; d->pf_zero = 0;
+}
+
+// Block-wide argmax of |v| with ties to the lowest index.  Returns the index
+// on every thread (or -1 when the block saw no candidate).
+__device__ int block_argmax(double val, int idx, double *s_val, int *s_idx) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int m = 32; m >= 1; m >>= 1) {
+        double ov = __shfl_xor(val, m, 64);
+        int oi = __shfl_xor(idx, m, 64);
+        bool take = (oi >= 0) && (idx < 0 || ov > val || (ov == val && oi < idx));
+        if (take) { val = ov; idx = oi; }
+    }
+    if (lane == 0) { s_val[wv] = val; s_idx[wv] = idx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bv = s_val[0];
+        int bi = s_idx[0];
+        for (int q = 1; q < kT / 64; ++q) {
+            double ov = s_val[q];
+            int oi = s_idx[q];
+            if (oi >= 0 && (bi < 0 || ov > bv || (ov == bv && oi < bi))) { bv = ov; bi = oi; }
+        }
+        s_idx[0] = bi;
+    }
+    __syncthreads();
+    int r = s_idx[0];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ Parlett-Reid
+// Unblocked, one work-group per matrix, on the workspace copy of A (PF only).
+// Uses the skew symmetry of every trailing block: column j below the
+// diagonal is minus row j to the right of it, so the pivot search reads a
+// contiguous row.
+template <class Wd>
+__global__ __launch_bounds__(kT) void parlett_reid_kernel(FA a) {
+    __shared__ double s_val[kT / 64];
+    __shared__ int s_idx[kT / 64];
+    const int w = blockIdx.x, n = a.n;
+    Wd *X = wX<Wd>(a, w);
+    DetAcc *d = wAcc(a, w);
+    double la = 0.0;
+    Wd ph = one<Wd>();
+    bool zero_pf = (n & 1) != 0;
+    for (int j = 0; j + 1 < n && !zero_pf; j += 2) {
+        // pivot: argmax_{i > j} |X[j][i]|
+        double bv = -1.0;
+        int bi = -1;
+        for (int i = j + 1 + threadIdx.x; i < n; i += kT) {
+            double v = absv(X[(size_t)j * n + i]);
+            if (bi < 0 || v > bv) { bv = v; bi = i; }
+        }
+        const int p = block_argmax(bv, bi, s_val, s_idx);
+        const int q = j + 1;
+        if (p != q) {
+            // swap rows q, p (columns >= j) and columns q, p (rows >= j)
+            for (int c = j + threadIdx.x; c < n; c += kT) {
+                Wd t = X[(size_t)q * n + c];
+                X[(size_t)q * n + c] = X[(size_t)p * n + c];
+                X[(size_t)p * n + c] = t;
+            }
+            __syncthreads();
+            for (int r = j + threadIdx.x; r < n; r += kT) {
+                Wd t = X[(size_t)r * n + q];
+                X[(size_t)r * n + q] = X[(size_t)r * n + p];
+                X[(size_t)r * n + p] = t;
+            }
+            __syncthreads();
+            ph = -ph;
+        }
+        const Wd alpha = X[(size_t)j * n + j + 1];
+        if (is_zero(alpha)) { zero_pf = true; break; }
+        la += log(absv(alpha));
+        ph = ph * unit(alpha);
+        // Trailing update X[r][s] += w_r c_s - c_r w_s, r, s >= j+2, with
+        // c = X[j][j+2:]/alpha (stored over row j, which is not needed again)
+        // and w = X[j+1][j+2:].
+        __syncthreads();
+        for (int r = j + 2 + threadIdx.x; r < n; r += kT) X[(size_t)j * n + r] = divv(X[(size_t)j * n + r], alpha);
+        __syncthreads();
+        const int m = n - j - 2;
+        for (int idx = threadIdx.x; idx < m * m; idx += kT) {
+            const int r = j + 2 + idx / m, s = j + 2 + idx % m;
+            const Wd cr = X[(size_t)j * n + r], wr = X[(size_t)(j + 1) * n + r];
+            const Wd cs = X[(size_t)j * n + s], ws = X[(size_t)(j + 1) * n + s];
+            X[(size_t)r * n + s] = X[(size_t)r * n + s] + (wr * cs - cr * ws);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d->pf_zero = zero_pf ? 1 : 0;
+        d->pf_logabs = zero_pf ? -INFINITY : la;
+        set_ph(d->pf_ph, zero_pf ? zero<Wd>() : ph);
+    }
+}
+
+// ------------------------------------------------------------------ GJ panel
+template <class Wd, int NB>
+__global__ __launch_bounds__(kT) void gj_panel_kernel(FA a, int j0, int nb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double s_val[kT / 64];
+    __shared__ int s_idx[kT / 64];
+    const int w = blockIdx.x, n = a.n, m = n - j0;
+    Wd *X = wX<Wd>(a, w);
+    Wd *Z = wZ<Wd>(a, w);
+    int *piv = wPiv(a, w);
+    DetAcc *d = wAcc(a, w);
+    Wd *sP = reinterpret_cast<Wd *>(smem);            // [m][nb]
+    Wd *sLinv = sP + (size_t)m * nb;                   // [nb][nb]
+    Wd *sYinv = sLinv + nb * nb;                       // [nb][nb]
+
+    for (int idx = threadIdx.x; idx < m * nb; idx += kT) {
+        const int i = idx / nb, c = idx - i * nb;
+        sP[idx] = X[(size_t)(j0 + i) * n + j0 + c];
+    }
+    __syncthreads();
+    double la = 0.0;
+    Wd ph = one<Wd>();
+    bool sing = false;
+    for (int c = 0; c < nb; ++c) {
+        double bv = -1.0;
+        int bi = -1;
+        for (int i = c + threadIdx.x; i < m; i += kT) {
+            double v = absv(sP[i * nb + c]);
+            if (bi < 0 || v > bv) { bv = v; bi = i; }
+        }
+        const int p = block_argmax(bv, bi, s_val, s_idx);
+        if (p != c) {
+            for (int cc = threadIdx.x; cc < nb; cc += kT) {
+                Wd t = sP[c * nb + cc];
+                sP[c * nb + cc] = sP[p * nb + cc];
+                sP[p * nb + cc] = t;
+            }
+            ph = -ph;
+        }
+        if (threadIdx.x == 0) piv[j0 + c] = j0 + p;
+        __syncthreads();
+        const Wd pv = sP[c * nb + c];
+        if (is_zero(pv)) { sing = true; continue; }
+        la += log(absv(pv));
+        ph = ph * unit(pv);
+        for (int i = c + 1 + threadIdx.x; i < m; i += kT) {
+            const Wd l = divv(sP[i * nb + c], pv);
+            sP[i * nb + c] = l;
+            for (int cc = c + 1; cc < nb; ++cc) sP[i * nb + cc] = fmsc(l, sP[c * nb + cc], sP[i * nb + cc]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (sing) d->singular = 1;
+        d->logabs += la;
+        Wd old = get_ph<Wd>(d->ph);
+        set_ph(d->ph, old * ph);
+    }
+    // L11^-1 (unit lower) and Y_P^-1 = U11^-1 L11^-1, one column per thread,
+    // solved directly in LDS (column e is private to thread e).
+    if (threadIdx.x < nb) {
+        const int e = threadIdx.x;
+        for (int r = 0; r < nb; ++r) {
+            Wd s = (r == e) ? one<Wd>() : zero<Wd>();
+            for (int q = 0; q < r; ++q) s = fmsc(sP[r * nb + q], sLinv[q * nb + e], s);
+            sLinv[r * nb + e] = s;
+        }
+        for (int r = nb - 1; r >= 0; --r) {
+            Wd s = sLinv[r * nb + e];
+            for (int q = r + 1; q < nb; ++q) s = fmsc(sP[r * nb + q], sYinv[q * nb + e], s);
+            const Wd dg = sP[r * nb + r];
+            sYinv[r * nb + e] = is_zero(dg) ? zero<Wd>() : divv(s, dg);
+        }
+    }
+    __syncthreads();
+    // Z rows and the new panel columns of X.
+    for (int i = threadIdx.x; i < n; i += kT) {
+        Wd z[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) z[c] = zero<Wd>();
+        if (i < j0) {
+            for (int q = 0; q < nb; ++q) {
+                const Wd yq = X[(size_t)i * n + j0 + q];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) if (c < nb) z[c] = fmsc(yq, sYinv[q * nb + c], z[c]);
+            }
+        } else if (i < j0 + nb) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c < nb) z[c] = sYinv[(i - j0) * nb + c] - ((i - j0 == c) ? one<Wd>() : zero<Wd>());
+        } else {
+            for (int q = 0; q < nb; ++q) {
+                const Wd lq = sP[(i - j0) * nb + q];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) if (c < nb) z[c] = fmsc(lq, sLinv[q * nb + c], z[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (c < nb) {
+                Z[(size_t)i * nb + c] = z[c];
+                X[(size_t)i * n + j0 + c] = z[c] + ((i == j0 + c) ? one<Wd>() : zero<Wd>());
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ GJ update
+// Every column outside the panel: X_new[i] = X_old[pi(i)] + Z[i] . X_old[pi(P)].
+// One work-group owns a block of CB columns for all rows, so the row
+// permutation stays inside the block.
+template <class Wd, int ROWS, int CB>
+__global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int ncb) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int w = lb / ncb, cb = lb - w * ncb;
+    if (w >= a.W) return;
+    const int n = a.n, others = n - nb;
+    Wd *X = wX<Wd>(a, w);
+    const Wd *Z = wZ<Wd>(a, w);
+    const int *piv = wPiv(a, w);
+    int *perm = reinterpret_cast<int *>(smem);                   // [n]
+    Wd *sXP = reinterpret_cast<Wd *>(smem + ((n * 4 + 15) / 16) * 16);   // [nb][CB]
+    for (int i = threadIdx.x; i < n; i += kT) perm[i] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < nb; ++c) {
+            const int r = j0 + c, p = piv[r];
+            const int t = perm[r]; perm[r] = perm[p]; perm[p] = t;
+        }
+    }
+    __syncthreads();
+    const int x0 = cb * CB;
+    for (int idx = threadIdx.x; idx < nb * CB; idx += kT) {
+        const int c = idx / CB, x = idx - c * CB;
+        const int ci = x0 + x;
+        Wd v = zero<Wd>();
+        if (ci < others) {
+            const int col = ci < j0 ? ci : ci + nb;
+            v = X[(size_t)perm[j0 + c] * n + col];
+        }
+        sXP[idx] = v;
+    }
+    Wd old[ROWS][CB];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int i = threadIdx.x + r * kT;
+#pragma unroll
+        for (int x = 0; x < CB; ++x) {
+            const int ci = x0 + x;
+            Wd v = zero<Wd>();
+            if (i < n && ci < others) {
+                const int col = ci < j0 ? ci : ci + nb;
+                v = X[(size_t)perm[i] * n + col];
+            }
+            old[r][x] = v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int i = threadIdx.x + r * kT;
+        if (i >= n) continue;
+        for (int c = 0; c < nb; ++c) {
+            const Wd zc = Z[(size_t)i * nb + c];
+#pragma unroll
+            for (int x = 0; x < CB; ++x) old[r][x] = fmac(zc, sXP[c * CB + x], old[r][x]);
+        }
+#pragma unroll
+        for (int x = 0; x < CB; ++x) {
+            const int ci = x0 + x;
+            if (ci < others) {
+                const int col = ci < j0 ? ci : ci + nb;
+                X[(size_t)i * n + col] = old[r][x];
+            }
+        }
+    }
+}
+
+// Column source of the final permutation: X (PB)^-1 -> B^-1 = X P, applied as
+// column swaps in reverse pivot order.
+__global__ void src_perm_kernel(FA a) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    const int n = a.n;
+    int *src = wSrc(a, w);
+    const int *piv = wPiv(a, w);
+    for (int c = 0; c < n; ++c) src[c] = c;
+    for (int kx = n - 1; kx >= 0; --kx) {
+        const int p = piv[kx];
+        const int t = src[kx]; src[kx] = src[p]; src[p] = t;
+    }
+}
+
+// ------------------------------------------------------------------ final
+// DET: M[i][c] = X[i][src[c]], cast to the bulk dtype; refresh: drift sums.
+template <class T, class Wd>
+__global__ __launch_bounds__(kT) void final_det_kernel(FA a, int rows_per_block, int bpw) {
+    __shared__ double s_d[kT / 64], s_nrm[kT / 64];
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int w = lb / bpw, rb = lb - w * bpw;
+    if (w >= a.W) return;
+    const int n = a.n;
+    const Wd *X = wX<Wd>(a, w);
+    const int *src = wSrc(a, w);
+    T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
+    double dsq = 0.0, nsq = 0.0;
+    const int q0 = rb * rows_per_block, q1 = min(n, q0 + rows_per_block);
+    for (int i = q0; i < q1; ++i) {
+        for (int c = threadIdx.x; c < n; c += kT) {
+            const Wd v = X[(size_t)i * n + src[c]];
+            if (a.refresh) {
+                const Wd o = conv<Wd>(M[(size_t)i * n + c]);
+                dsq += abs2(o - v);
+                nsq += abs2(v);
+            }
+            M[(size_t)i * n + c] = conv<T>(v);
+        }
+    }
+    if (a.refresh) {
+        dsq = wave_sum(dsq);
+        nsq = wave_sum(nsq);
+        if ((threadIdx.x & 63) == 0) { s_d[threadIdx.x >> 6] = dsq; s_nrm[threadIdx.x >> 6] = nsq; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t0 = 0, t1 = 0;
+            for (int q = 0; q < kT / 64; ++q) { t0 += s_d[q]; t1 += s_nrm[q]; }
+            DetAcc *d = wAcc(a, w);
+            atomicAdd(&d->dsq, t0);
+            atomicAdd(&d->nsq, t1);
+        }
+    }
+}
+
+// PF: X' = X with columns src-permuted (= A^-1); M = (X' - X'^T)/2 on 32x32
+// tile pairs (ti <= tj), writing both triangles so M is exactly skew.
+template <class T, class Wd>
+__global__ __launch_bounds__(kT) void final_pf_kernel(FA a, int tiles) {
+    __shared__ Wd t1[32][33], t2[32][33];
+    __shared__ double s_d[kT / 64], s_nrm[kT / 64];
+    const int pairs = tiles * (tiles + 1) / 2;
+    const int w = blockIdx.x / pairs;
+    int p = blockIdx.x - w * pairs;
+    int ti = 0;
+    while (p >= tiles - ti) { p -= tiles - ti; ++ti; }
+    const int tj = ti + p;
+    const int n = a.n;
+    const Wd *X = wX<Wd>(a, w);
+    const int *src = wSrc(a, w);
+    T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = ti * 32 + r, j = tj * 32 + tx;
+        t1[r][tx] = (i < n && j < n) ? X[(size_t)i * n + src[j]] : zero<Wd>();   // X'[i][j]
+        const int i2 = tj * 32 + r, j2 = ti * 32 + tx;
+        t2[r][tx] = (i2 < n && j2 < n) ? X[(size_t)i2 * n + src[j2]] : zero<Wd>();   // X'[j][i] block
+    }
+    __syncthreads();
+    double dsq = 0.0, nsq = 0.0;
+    for (int r = ty; r < 32; r += 8) {
+        const int i = ti * 32 + r, j = tj * 32 + tx;
+        if (i < n && j < n && (ti < tj || r < tx)) {
+            // upper entry (i, j): (X'[i][j] - X'[j][i]) / 2
+            const Wd h = half_of(t1[r][tx] - t2[tx][r]);
+            const Wd nh = -h;
+            if (a.refresh) {
+                const Wd o1 = conv<Wd>(M[(size_t)i * n + j]);
+                const Wd o2 = conv<Wd>(M[(size_t)j * n + i]);
+                dsq += abs2(o1 - h) + abs2(o2 - nh);
+                nsq += 2.0 * abs2(h);
+            }
+            M[(size_t)i * n + j] = conv<T>(h);
+            M[(size_t)j * n + i] = conv<T>(nh);
+        } else if (i < n && j < n && ti == tj && r == tx) {
+            if (a.refresh) dsq += abs2(conv<Wd>(M[(size_t)i * n + i]));
+            M[(size_t)i * n + i] = zero<T>();
+        }
+    }
+    if (a.refresh) {
+        dsq = wave_sum(dsq);
+        nsq = wave_sum(nsq);
+        if ((threadIdx.x & 63) == 0) { s_d[threadIdx.x >> 6] = dsq; s_nrm[threadIdx.x >> 6] = nsq; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0, s1 = 0;
+            for (int q = 0; q < kT / 64; ++q) { s0 += s_d[q]; s1 += s_nrm[q]; }
+            DetAcc *d = wAcc(a, w);
+            atomicAdd(&d->dsq, s0);
+            atomicAdd(&d->nsq, s1);
+        }
+    }
+}
+
+template <class Wd>
+__global__ void finish_kernel(FA a) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.W) return;
+    const DetAcc *d = wAcc(a, w);
+    Wd *phase = static_cast<Wd *>(a.phase);
+    double la;
+    Wd ph;
+    bool bad;
+    if (a.kind == LRX_DET) {
+        bad = d->singular != 0;
+        la = bad ? -INFINITY : d->logabs;
+        ph = bad ? zero<Wd>() : get_ph<Wd>(d->ph);
+    } else {
+        bad = d->singular != 0 || d->pf_zero != 0;
+        la = d->pf_zero ? -INFINITY : d->pf_logabs;
+        ph = d->pf_zero ? zero<Wd>() : get_ph<Wd>(d->pf_ph);
+    }
+    if (a.report) {
+        const double oldla = a.logabs[w];
+        const Wd oldph = phase[w];
+        a.report[2 * w] = d->nsq > 0 ? sqrt(d->dsq / d->nsq) : 0.0;
+        a.report[2 * w + 1] = fabs(oldla - la) + absdiff(oldph, ph);
+    }
+    a.logabs[w] = la;
+    phase[w] = ph;
+    a.flags[w] = bad ? LRX_FLAG_SINGULAR_A : 0u;
+}
+
+template <class Wd, int ROWS>
+hipError_t launch_update(const FA &fa, int j0, int nb, hipStream_t s) {
+    constexpr int CB = (sizeof(Wd) == 8 ? 32 : 16) / ROWS;
+    const int others = fa.n - nb;
+    if (others <= 0) return hipSuccess;
+    const int ncb = (others + CB - 1) / CB;
+    const size_t lds = ((fa.n * 4 + 15) / 16) * 16 + sizeof(Wd) * (size_t)nb * CB;
+    hipLaunchKernelGGL((gj_update_kernel<Wd, ROWS, CB>), dim3((unsigned)(fa.W * ncb)), dim3(kT), lds, s, fa, j0,
+                       nb, ncb);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
+    using Wd = typename Wide<T>::type;
+    FA a;
+    a.kind = in.kind; a.W = in.W; a.n = in.n; a.sites = in.sites;
+    a.src = in.src; a.occ = in.occ;
+    a.work = static_cast<uint8_t *>(in.work);
+    a.L = work_layout(in.n, sizeof(Wd));
+    a.inv = in.inv; a.logabs = in.logabs; a.phase = in.phase; a.flags = in.flags;
+    a.report = in.report; a.refresh = in.refresh;
+    a.nb = panel_nb(in.n, sizeof(Wd));
+    const int n = in.n, W = in.W;
+    const int tiles = (n + 31) / 32;
+    hipError_t e;
+    hipLaunchKernelGGL(init_acc_kernel<Wd>, dim3((W + 255) / 256), dim3(256), 0, s, a);
+    if (a.kind == LRX_PF) {
+        hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
+        hipLaunchKernelGGL(parlett_reid_kernel<Wd>, dim3(W), dim3(kT), 0, s, a);
+    }
+    hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int j0 = 0; j0 < n; j0 += a.nb) {
+        const int nb = min(a.nb, n - j0);
+        const size_t lds = sizeof(Wd) * ((size_t)(n - j0) * nb + 2 * (size_t)nb * nb);
+        switch (a.nb) {
+            case 32: hipLaunchKernelGGL((gj_panel_kernel<Wd, 32>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
+            case 16: hipLaunchKernelGGL((gj_panel_kernel<Wd, 16>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
+            case 8: hipLaunchKernelGGL((gj_panel_kernel<Wd, 8>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
+            case 4: hipLaunchKernelGGL((gj_panel_kernel<Wd, 4>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
+            case 2: hipLaunchKernelGGL((gj_panel_kernel<Wd, 2>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
+            default: hipLaunchKernelGGL((gj_panel_kernel<Wd, 1>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
+        }
+        if (n <= 256) e = launch_update<Wd, 1>(a, j0, nb, s);
+        else if (n <= 512) e = launch_update<Wd, 2>(a, j0, nb, s);
+        else e = launch_update<Wd, 4>(a, j0, nb, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(src_perm_kernel, dim3((W + 63) / 64), dim3(64), 0, s, a);
+    if (a.kind == LRX_DET) {
+        const int rpb = 8;
+        const int bpw = (n + rpb - 1) / rpb;
+        hipLaunchKernelGGL((final_det_kernel<T, Wd>), dim3((unsigned)(W * bpw)), dim3(kT), 0, s, a, rpb, bpw);
+    } else {
+        const int pairs = tiles * (tiles + 1) / 2;
+        hipLaunchKernelGGL((final_pf_kernel<T, Wd>), dim3((unsigned)(W * pairs)), dim3(kT), 0, s, a, tiles);
+    }
+    hipLaunchKernelGGL(finish_kernel<Wd>, dim3((W + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace lrx {
+
+size_t factor_work_bytes(int kind, int dtype, int W, int n) {
+    (void)kind;
+    return (size_t)W * work_layout(n, wide_bytes(dtype)).stride;
+}
+
+hipError_t factor(const FactorArgs &a, hipStream_t s) {
+    switch (a.dtype) {
+        case LRX_F32: return factor_t<float>(a, s);
+        case LRX_F64: return factor_t<double>(a, s);
+        case LRX_C64: return factor_t<cf32>(a, s);
+        case LRX_C128: return factor_t<cf64>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lrx

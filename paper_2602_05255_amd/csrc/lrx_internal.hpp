@@ -1,0 +1,95 @@
+// Private interface between the C-ABI layer (lrx_capi.cpp) and the kernel
+// translation units.  Host code only; no torch types anywhere.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/lrx.h"
+
+namespace lrx {
+
+struct Layout {                 // byte offsets in one walker's stash
+    uint32_t c, rinv, g, ratio, kslot, ax, stride;
+};
+
+// Element sizes.
+inline size_t bulk_bytes(int dtype) {
+    switch (dtype) {
+        case LRX_F32: return 4;
+        case LRX_F64: return 8;
+        case LRX_C64: return 8;
+        case LRX_C128: return 16;
+    }
+    return 0;
+}
+inline bool is_complex(int dtype) { return dtype == LRX_C64 || dtype == LRX_C128; }
+inline size_t wide_bytes(int dtype) { return is_complex(dtype) ? 16 : 8; }
+
+Layout stash_layout(const lrx_shape &s);
+
+// Common argument block for the per-step kernels.
+struct StepArgs {
+    int W, n, KM, K, tau;
+    int aligned;            // rows of inv start on 16-byte boundaries
+    void *inv, *fa, *fb;
+    uint8_t *stash;
+    Layout L;
+    const int32_t *k, *rows;
+    const void *u;
+    uint8_t *accept;
+    double *logabs;
+    void *phase;
+    uint32_t *flags;
+    void *ratio;
+};
+
+struct HopArgs {
+    int W, n, KM, sites, n_empty;
+    const void *phi;         // wide dtype
+    const int32_t *occ, *empty, *k, *elec, *slot;
+    void *out;               // bulk dtype
+    uint32_t *flags;
+};
+
+// Determinant kernels (lrx_det.hip).
+hipError_t det_build_hop(int dtype, const HopArgs &a, hipStream_t s);
+hipError_t det_propose(int dtype, const StepArgs &a, hipStream_t s);
+hipError_t det_accept(int dtype, const StepArgs &a, hipStream_t s);
+
+// Pfaffian kernels (lrx_pf.hip).
+hipError_t pf_build_hop(int dtype, const HopArgs &a, hipStream_t s);
+hipError_t pf_propose(int dtype, const StepArgs &a, hipStream_t s);
+hipError_t pf_accept(int dtype, const StepArgs &a, hipStream_t s);
+
+// Flush GEMMs (lrx_flush.hip).
+hipError_t det_flush(int dtype, const StepArgs &a, hipStream_t s);
+hipError_t pf_flush(int dtype, const StepArgs &a, hipStream_t s);
+
+// Chain helpers (lrx_det.hip).
+hipError_t metropolis(int dtype, int W, const void *ratio, const double *u01,
+                      uint64_t seed, uint64_t counter, int mode,
+                      const uint32_t *flags, uint8_t *accept, hipStream_t s);
+hipError_t hop_commit(int W, int n, int n_empty, int KM, const int32_t *k,
+                      const int32_t *elec, const int32_t *slot,
+                      const uint8_t *accept, int32_t *occ, int32_t *empty,
+                      hipStream_t s);
+
+// Init / refresh (lrx_factor.hip).
+struct FactorArgs {
+    int kind, dtype, W, n, sites;
+    const void *src;          // phi / f (wide) or dense batch
+    const int32_t *occ;       // NULL -> dense batch
+    void *work;               // workspace (see factor_work_bytes)
+    void *inv;                // bulk out
+    double *logabs;
+    void *phase;
+    uint32_t *flags;
+    double *report;           // refresh report [W][2] or NULL
+    int refresh;              // 1 -> compare with the current state
+};
+size_t factor_work_bytes(int kind, int dtype, int W, int n);
+hipError_t factor(const FactorArgs &a, hipStream_t s);
+
+}  // namespace lrx

@@ -1,0 +1,408 @@
+// Pfaffian low-rank update kernels (Sec. III of the paper), single-electron
+// hops: u = (x, e_i) with x_i = 0 (Eq. pf_rank2), a rank-2 skew update
+// A_t = A_{t-1} - u J u^T.
+//
+// State: M = A^-1 row-major, exactly skew-symmetric.
+//   propose   : col = A_{tau-1}^-1[:, i] = -M0[i,:]^T + sum_t a_t R_t^-1 a_t[i,:]^T,
+//               r = pf R / pf J = R_12 = 1 + x . col          (Eqs. pf_ratio, pf_R)
+//   accept K=0: a_x = M x (pass 1); M += (col a_x^T - a_x col^T)/r (pass 2)   (Eq. pf_inv, k = 1)
+//   accept K>0: a_tau = [A_{tau-1}^-1 x, col], R_tau^-1 = [[0,-1/r],[1/r,0]] (Eq. pf_a, Sec. III.C)
+//
+// Exact skew symmetry of the plain update: entry (q, j) is computed from the
+// ordered pair (min, max) and negated when q > j, so (j, q) receives exactly
+// the negative of (q, j) whatever FMA contraction the compiler applies.
+#include "lrx_common.hpp"
+#include "lrx_internal.hpp"
+
+namespace {
+
+using lrx::StepArgs;
+using lrx::HopArgs;
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / LRX_WAVE;
+constexpr int KA = 2;    // columns of u per hop (k = 1)
+
+// ------------------------------------------------------------------ build hop
+// x[j] = f[s'][occ_j] - f[s][occ_j] (j != i), x[i] = 0.
+template <class T>
+__global__ __launch_bounds__(kThreads) void pf_build_hop_kernel(HopArgs a) {
+    using Wd = typename Wide<T>::type;
+    const int w = blockIdx.x, n = a.n, KM = a.KM;
+    const Wd *f = static_cast<const Wd *>(a.phi);
+    T *x = static_cast<T *>(a.out) + (size_t)w * n;
+    __shared__ int s_i, s_src, s_dst, s_bad;
+    if (threadIdx.x == 0) {
+        int kw = a.k[w];
+        int e = a.elec[w * KM], sl = a.slot[w * KM];
+        int bad = (kw != 1) || e < 0 || e >= n || sl < 0 || sl >= a.n_empty;
+        int src = 0, dst = 0;
+        if (!bad) {
+            src = a.occ[(size_t)w * n + e];
+            dst = a.empty[(size_t)w * a.n_empty + sl];
+            if (src < 0 || src >= a.sites || dst < 0 || dst >= a.sites) bad = 1;
+        }
+        s_i = bad ? -1 : e;
+        s_src = bad ? 0 : src;
+        s_dst = bad ? 0 : dst;
+        s_bad = bad;
+        if (bad) atomicOr(a.flags + w, LRX_FLAG_BADINDEX);
+    }
+    __syncthreads();
+    const Wd *fs = f + (size_t)s_src * a.sites;
+    const Wd *fd = f + (size_t)s_dst * a.sites;
+    const int32_t *occ = a.occ + (size_t)w * n;
+    for (int j = threadIdx.x; j < n; j += kThreads) {
+        T v = zero<T>();
+        if (!s_bad && j != s_i) {
+            const int oj = occ[j];
+            if (oj >= 0 && oj < a.sites) v = conv<T>(fd[oj] - fs[oj]);
+        }
+        x[j] = v;
+    }
+}
+
+// ------------------------------------------------------------------ propose
+template <class T>
+__global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
+    using Wd = typename Wide<T>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int w = blockIdx.x, n = a.n, tau = a.tau, TE = tau * KA;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const T *M = static_cast<const T *>(a.inv) + (size_t)w * n * n;
+    const T *x = static_cast<const T *>(a.u) + (size_t)w * n;
+    const T *fa = static_cast<const T *>(a.fa) + (size_t)w * a.K * KA * n;
+    const T *rinv = static_cast<const T *>(a.fb) + (size_t)w * a.K * KA * KA;
+    uint8_t *st = a.stash + (size_t)w * a.L.stride;
+    T *col = reinterpret_cast<T *>(st + a.L.c);
+    T *h = reinterpret_cast<T *>(st + a.L.g);
+    Wd *ratio_st = reinterpret_cast<Wd *>(st + a.L.ratio);
+
+    T *s_m = reinterpret_cast<T *>(smem);      // [TE] R_t^-1 a_t[i,:]^T
+    T *s_red = s_m + TE;                       // [kWaves]
+    __shared__ int s_i, s_bad;
+    if (tid == 0) {
+        int i = a.rows[w * a.KM];
+        int bad = (a.k[w] != 1) || i < 0 || i >= n;
+        s_i = bad ? 0 : i;
+        s_bad = bad;
+    }
+    __syncthreads();
+    const int i = s_i;
+    for (int te = tid; te < TE; te += kThreads) {
+        const int t = te / KA, s = te - t * KA;
+        T v = zero<T>();
+        for (int sp = 0; sp < KA; ++sp) v = fmac(rinv[(size_t)t * KA * KA + s * KA + sp], fa[(size_t)(t * KA + sp) * n + i], v);
+        s_m[te] = v;
+    }
+    __syncthreads();
+    T part = zero<T>();
+    for (int q = tid; q < n; q += kThreads) {
+        T c = -M[(size_t)i * n + q];
+        for (int te = 0; te < TE; ++te) c = fmac(fa[(size_t)te * n + q], s_m[te], c);
+        col[q] = c;
+        part = fmac(x[q], c, part);
+    }
+    part = wave_sum(part);
+    if (lane == 0) s_red[wv] = part;
+    // h_t = R_t^-1 (a_t^T x): the slot correction of A_{tau-1}^-1 x.
+    if (a.K > 0) {
+        for (int t = wv; t < tau; t += kWaves) {
+            T g[KA];
+#pragma unroll
+            for (int s = 0; s < KA; ++s) g[s] = zero<T>();
+            for (int q = lane; q < n; q += 64)
+#pragma unroll
+                for (int s = 0; s < KA; ++s) g[s] = fmac(fa[(size_t)(t * KA + s) * n + q], x[q], g[s]);
+#pragma unroll
+            for (int s = 0; s < KA; ++s) g[s] = wave_sum(g[s]);
+            if (lane < KA) {
+                T v = zero<T>();
+#pragma unroll
+                for (int sp = 0; sp < KA; ++sp)
+                    v = fmac(rinv[(size_t)t * KA * KA + lane * KA + sp], g[sp], v);
+                h[t * KA + lane] = v;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        T tot = one<T>();
+        for (int q = 0; q < kWaves; ++q) tot = tot + s_red[q];
+        Wd r = conv<Wd>(tot);
+        if (s_bad) r = zero<Wd>();
+        static_cast<Wd *>(a.ratio)[w] = r;
+        *ratio_st = (s_bad || is_zero(r) || !finite_v(r)) ? zero<Wd>() : r;
+        if (s_bad) atomicOr(a.flags + w, LRX_FLAG_BADINDEX);
+    }
+}
+
+// ------------------------------------------------------------------ row dots
+// ax[q] = M[q,:] . x (+ sum_te fa[te][q] h[te] in the delayed form).
+// DELAYED: writes slot tau = [ax, col] and R_tau^-1; else stores ax in the stash.
+template <class T, int NEL, int RB, bool DELAYED>
+__global__ __launch_bounds__(kThreads) void pf_rowdot_kernel(StepArgs a, int rows_per_block, int bpw) {
+    using Wd = typename Wide<T>::type;
+    constexpr int V = vec16<T>();
+    constexpr int NCH = NEL / V;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int w = lb / bpw, rb = lb - w * bpw;
+    if (w >= a.W) return;
+    const int n = a.n, tau = a.tau, TE = tau * KA;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int q0 = rb * rows_per_block, q1 = min(n, q0 + rows_per_block), nq = q1 - q0;
+    const T *M = static_cast<const T *>(a.inv) + (size_t)w * n * n;
+    const T *x = static_cast<const T *>(a.u) + (size_t)w * n;
+    T *fa = static_cast<T *>(a.fa) + (size_t)w * a.K * KA * n;
+    T *rinv = static_cast<T *>(a.fb) + (size_t)w * a.K * KA * KA;
+    uint8_t *st = a.stash + (size_t)w * a.L.stride;
+    const T *col = reinterpret_cast<const T *>(st + a.L.c);
+    const T *h = reinterpret_cast<const T *>(st + a.L.g);
+    T *ax = reinterpret_cast<T *>(st + a.L.ax);
+    int *kslot = reinterpret_cast<int *>(st + a.L.kslot);
+    const Wd ratio = *reinterpret_cast<const Wd *>(st + a.L.ratio);
+    const bool take = a.accept[w] != 0 && a.flags[w] == 0 && !is_zero(ratio);
+
+    if (!take) {
+        if (rb == 0 && tid == 0 && a.accept[w]) a.accept[w] = 0;   // skipped: no occupancy commit
+        if (DELAYED) {
+            for (int q = q0 + tid; q < q1; q += kThreads) {
+                fa[(size_t)(tau * KA) * n + q] = zero<T>();
+                fa[(size_t)(tau * KA + 1) * n + q] = zero<T>();
+            }
+            if (rb == 0 && tid < KA * KA) rinv[(size_t)tau * KA * KA + tid] = zero<T>();
+            if (rb == 0 && tid == 0) kslot[tau] = 0;
+        }
+        return;
+    }
+    if (DELAYED && rb == 0) {
+        if (tid == 0) {
+            accum_logphase(ratio, a.logabs + w, static_cast<Wd *>(a.phase) + w);
+            kslot[tau] = 1;
+        }
+        if (tid < KA * KA) {
+            // R = [[0, r], [-r, 0]]  ->  R^-1 = [[0, -1/r], [1/r, 0]]
+            const Wd ir = divv(one<Wd>(), ratio);
+            T v = zero<T>();
+            if (tid == 1) v = conv<T>(-ir);
+            if (tid == 2) v = conv<T>(ir);
+            rinv[(size_t)tau * KA * KA + tid] = v;
+        }
+    }
+    const int npad = NCH * V * 64;
+    T *s_x = reinterpret_cast<T *>(smem);        // [npad]
+    T *s_corr = s_x + npad;                      // [rows_per_block]
+    for (int j = tid; j < npad; j += kThreads) s_x[j] = j < n ? x[j] : zero<T>();
+    for (int q = q0 + tid; q < q1; q += kThreads) {
+        T c = zero<T>();
+        if (DELAYED)
+            for (int te = 0; te < TE; ++te) c = fmac(fa[(size_t)te * n + q], h[te], c);
+        s_corr[q - q0] = c;
+    }
+    __syncthreads();
+    const bool vec_ok = a.aligned != 0;
+    for (int qb = q0 + wv * RB; qb < q1; qb += kWaves * RB) {
+        T p[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) p[r] = zero<T>();
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int j0 = ch * V * 64 + lane * V;
+            T xv[V];
+            ld16<T>(s_x + j0, xv);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int q = qb + r;
+                const T *row = M + (size_t)q * n;
+                T tmp[V];
+                if (q < q1 && vec_ok && j0 + V <= n) {
+                    ld16<T>(row + j0, tmp);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) tmp[v] = (q < q1 && j0 + v < n) ? row[j0 + v] : zero<T>();
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) p[r] = fmac(tmp[v], xv[v], p[r]);
+            }
+        }
+        T tot = wave_sum_multi<T, RB>(p);
+        // lane r (< RB) holds the dot of row qb + r
+        if (lane < RB) {
+            const int q = qb + lane;
+            if (q < q1) {
+                const T v = tot + s_corr[q - q0];
+                if (DELAYED) {
+                    fa[(size_t)(tau * KA) * n + q] = v;
+                    fa[(size_t)(tau * KA + 1) * n + q] = col[q];
+                } else {
+                    ax[q] = v;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ plain pass 2
+// M[q][j] += (col_q ax_j - ax_q col_j)/r, computed on the ordered pair.
+template <class T, int NEL, int RB>
+__global__ __launch_bounds__(kThreads) void pf_update_kernel(StepArgs a, int rows_per_block, int bpw) {
+    using Wd = typename Wide<T>::type;
+    constexpr int V = vec16<T>();
+    constexpr int NCH = NEL / V;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int w = lb / bpw, rb = lb - w * bpw;
+    if (w >= a.W) return;
+    const int n = a.n;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int q0 = rb * rows_per_block, q1 = min(n, q0 + rows_per_block);
+    T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
+    uint8_t *st = a.stash + (size_t)w * a.L.stride;
+    const T *col = reinterpret_cast<const T *>(st + a.L.c);
+    const T *ax = reinterpret_cast<const T *>(st + a.L.ax);
+    const Wd ratio = *reinterpret_cast<const Wd *>(st + a.L.ratio);
+    const bool take = a.accept[w] != 0 && a.flags[w] == 0 && !is_zero(ratio);
+    if (!take) return;
+    if (rb == 0 && tid == 0) accum_logphase(ratio, a.logabs + w, static_cast<Wd *>(a.phase) + w);
+    const T ir = conv<T>(divv(one<Wd>(), ratio));
+    const int npad = NCH * V * 64;
+    T *s_c = reinterpret_cast<T *>(smem);
+    T *s_a = s_c + npad;
+    for (int j = tid; j < npad; j += kThreads) {
+        s_c[j] = j < n ? col[j] : zero<T>();
+        s_a[j] = j < n ? ax[j] : zero<T>();
+    }
+    __syncthreads();
+    const bool vec_ok = a.aligned != 0;
+    for (int qb = q0 + wv * RB; qb < q1; qb += kWaves * RB) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int q = qb + r;
+            if (q >= q1) continue;
+            T *row = M + (size_t)q * n;
+            const T cq = s_c[q], aq = s_a[q];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int j0 = ch * V * 64 + lane * V;
+                T tmp[V], cj[V], aj[V];
+                ld16<T>(s_c + j0, cj);
+                ld16<T>(s_a + j0, aj);
+                const bool full = vec_ok && j0 + V <= n;
+                if (full) ld16<T>(row + j0, tmp);
+                else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) tmp[v] = (j0 + v < n) ? row[j0 + v] : zero<T>();
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int j = j0 + v;
+                    const bool up = q < j;
+                    const T c_lo = up ? cq : cj[v], a_lo = up ? aq : aj[v];
+                    const T c_hi = up ? cj[v] : cq, a_hi = up ? aj[v] : aq;
+                    const T g = (c_lo * a_hi - a_lo * c_hi) * ir;
+                    T d = up ? g : -g;
+                    if (q == j) d = zero<T>();
+                    tmp[v] = tmp[v] + d;
+                }
+                if (full) st16<T>(row + j0, tmp);
+                else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) if (j0 + v < n) row[j0 + v] = tmp[v];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+template <class T> hipError_t build_hop_t(const HopArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(pf_build_hop_kernel<T>, dim3(a.W), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T> hipError_t propose_t(const StepArgs &a, hipStream_t s) {
+    size_t lds = sizeof(T) * ((size_t)a.tau * KA + kWaves);
+    hipLaunchKernelGGL(pf_propose_kernel<T>, dim3(a.W), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <class T, int NEL> constexpr int pf_rb() {
+    constexpr int per_row = NEL * (int)sizeof(T);
+    return 8 * per_row <= 512 ? 8 : (4 * per_row <= 512 ? 4 : (2 * per_row <= 512 ? 2 : 1));
+}
+
+inline void block_shape(int W, int n, int rows_min, int &rpb, int &bpw) {
+    rpb = rows_min;
+    long long blocks = (long long)W * ((n + rpb - 1) / rpb);
+    while (rpb < n && blocks > 8 * 256 * 4) {
+        rpb *= 2;
+        blocks = (long long)W * ((n + rpb - 1) / rpb);
+    }
+    bpw = (n + rpb - 1) / rpb;
+}
+
+template <class T, int NEL> hipError_t accept_nel(const StepArgs &a, hipStream_t s) {
+    constexpr int RB = pf_rb<T, NEL>();
+    constexpr int V = vec16<T>();
+    const int npad = (NEL / V) * V * 64;
+    int rpb, bpw;
+    block_shape(a.W, a.n, kWaves * RB, rpb, bpw);
+    const dim3 grid((unsigned)(a.W * bpw));
+    const size_t lds1 = sizeof(T) * ((size_t)npad + rpb);
+    if (a.K > 0) {
+        hipLaunchKernelGGL((pf_rowdot_kernel<T, NEL, RB, true>), grid, dim3(kThreads), lds1, s, a, rpb, bpw);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((pf_rowdot_kernel<T, NEL, RB, false>), grid, dim3(kThreads), lds1, s, a, rpb, bpw);
+    const size_t lds2 = sizeof(T) * 2 * (size_t)npad;
+    hipLaunchKernelGGL((pf_update_kernel<T, NEL, RB>), grid, dim3(kThreads), lds2, s, a, rpb, bpw);
+    return hipGetLastError();
+}
+
+template <class T> hipError_t accept_t(const StepArgs &a, hipStream_t s) {
+    constexpr int V = vec16<T>();
+    const int nch = (a.n + V * 64 - 1) / (V * 64);
+    if (nch <= 1) return accept_nel<T, V>(a, s);
+    if (nch <= 2) return accept_nel<T, 2 * V>(a, s);
+    if (nch <= 4) return accept_nel<T, 4 * V>(a, s);
+    if constexpr (V <= 2) { if (nch <= 8) return accept_nel<T, 8 * V>(a, s); }
+    if constexpr (V == 1) { if (nch <= 16) return accept_nel<T, 16>(a, s); }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+namespace lrx {
+
+hipError_t pf_build_hop(int dtype, const HopArgs &a, hipStream_t s) {
+    switch (dtype) {
+        case LRX_F32: return build_hop_t<float>(a, s);
+        case LRX_F64: return build_hop_t<double>(a, s);
+        case LRX_C64: return build_hop_t<cf32>(a, s);
+        case LRX_C128: return build_hop_t<cf64>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t pf_propose(int dtype, const StepArgs &a, hipStream_t s) {
+    switch (dtype) {
+        case LRX_F32: return propose_t<float>(a, s);
+        case LRX_F64: return propose_t<double>(a, s);
+        case LRX_C64: return propose_t<cf32>(a, s);
+        case LRX_C128: return propose_t<cf64>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t pf_accept(int dtype, const StepArgs &a, hipStream_t s) {
+    switch (dtype) {
+        case LRX_F32: return accept_t<float>(a, s);
+        case LRX_F64: return accept_t<double>(a, s);
+        case LRX_C64: return accept_t<cf32>(a, s);
+        case LRX_C128: return accept_t<cf64>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lrx

@@ -77,6 +77,24 @@ def hop_draws(rng: np.random.Generator, walkers: int, n: int, n_empty: int,
     return k, elec, slot
 
 
+def hop_draws_batch(rng: np.random.Generator, steps: int, walkers: int, n: int, n_empty: int,
+                    ranks, k_max: int):
+    """``steps`` steps of proposal draws at once (same distribution as hop_draws).
+
+    Distinct electrons / empty-list slots come from the first k entries of a
+    random permutation (argsort of iid uniforms).  Returns int32 arrays
+    k [steps][W], elec [steps][W][k_max], slot [steps][W][k_max].
+    """
+    ranks = np.asarray(ranks, dtype=np.int32)
+    k = ranks[rng.integers(0, len(ranks), size=(steps, walkers))].astype(np.int32)
+    elec = np.argsort(rng.random((steps, walkers, n)), axis=2)[:, :, :k_max].astype(np.int32)
+    slot = np.argsort(rng.random((steps, walkers, n_empty)), axis=2)[:, :, :k_max].astype(np.int32)
+    pad = np.arange(k_max)[None, None, :] >= k[:, :, None]
+    elec = np.where(pad, elec[:, :, :1], elec)
+    slot = np.where(pad, slot[:, :, :1], slot)
+    return k, elec.astype(np.int32), slot.astype(np.int32)
+
+
 def uniforms(rng: np.random.Generator, walkers: int):
     return rng.random(walkers)
 

@@ -1,0 +1,301 @@
+"""Python binding of liblrx (ctypes).  Argument marshalling only.
+
+Every function here has the name of the C entry point it wraps (see
+``include/lrx.h``), takes torch tensors that already live on the GPU, checks
+their dtype/shape/contiguity, and passes raw device pointers plus the current
+HIP stream.  All arithmetic runs in the HIP kernels of ``liblrx.so``; there is
+no fallback: importing this module raises if the library is missing.
+
+``State`` allocates the caller-owned device buffers of one walker batch with
+torch (the library itself never allocates) and keeps the C ``lrx_state``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"liblrx.so not built at {LIB_PATH}: run `python -m paper_2602_05255_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# Constants mirrored from lrx.h.
+LRX_OK, LRX_EINVAL, LRX_EUNSUPPORTED, LRX_ESHAPE, LRX_ENEEDFLUSH, LRX_EODD, LRX_EHIP, LRX_EKIND = range(8)
+LRX_DET, LRX_PF = 0, 1
+LRX_F32, LRX_F64, LRX_C64, LRX_C128 = 0, 1, 2, 3
+LRX_FLAG_SINGULAR_R, LRX_FLAG_NONFINITE, LRX_FLAG_SINGULAR_A, LRX_FLAG_BADINDEX = 1, 2, 4, 8
+LRX_MH_UNIFORMS, LRX_MH_DEVICE_RNG, LRX_MH_FORCE = 0, 1, 2
+LRX_MAX_N, LRX_MAX_KMAX_DET, LRX_MAX_KMAX_PF, LRX_MAX_DELAY = 1024, 8, 1, 64
+
+DTYPE_CODE = {torch.float32: LRX_F32, torch.float64: LRX_F64,
+              torch.complex64: LRX_C64, torch.complex128: LRX_C128}
+CODE_DTYPE = {v: k for k, v in DTYPE_CODE.items()}
+WIDE = {LRX_F32: torch.float64, LRX_F64: torch.float64,
+        LRX_C64: torch.complex128, LRX_C128: torch.complex128}
+
+
+class lrx_shape(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("walkers", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("k_max", ctypes.c_int32), ("delay", ctypes.c_int32)]
+
+
+class lrx_sizes(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_size_t) for f in
+                ("inv", "fa", "fb", "stash", "logabs", "phase", "flags", "work", "stash_stride")]
+
+
+class lrx_state(ctypes.Structure):
+    _fields_ = [("shape", lrx_shape), ("slot", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("inv", ctypes.c_void_p), ("fa", ctypes.c_void_p), ("fb", ctypes.c_void_p),
+                ("stash", ctypes.c_void_p), ("logabs", ctypes.c_void_p), ("phase", ctypes.c_void_p),
+                ("flags", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_SIGS = {
+    "lrx_version": ([], ctypes.c_int),
+    "lrx_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "lrx_state_sizes": ([ctypes.POINTER(lrx_shape), ctypes.POINTER(lrx_sizes)], ctypes.c_int),
+    "lrx_validate": ([ctypes.POINTER(lrx_state)], ctypes.c_int),
+    "lrx_det_init_inverse": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P], ctypes.c_int),
+    "lrx_det_refresh": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _P], ctypes.c_int),
+    "lrx_det_build_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_det_propose_ratio": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_det_accept_update": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_det_flush_delayed": ([ctypes.POINTER(lrx_state), _P], ctypes.c_int),
+    "lrx_pf_init_inverse": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P], ctypes.c_int),
+    "lrx_pf_refresh": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _P], ctypes.c_int),
+    "lrx_pf_build_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_pf_propose_ratio": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_pf_accept_update": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_pf_flush_delayed": ([ctypes.POINTER(lrx_state), _P], ctypes.c_int),
+    "lrx_metropolis": ([ctypes.POINTER(lrx_state), _P, _P, ctypes.c_uint64, ctypes.c_uint64, _I, _P, _P],
+                       ctypes.c_int),
+    "lrx_hop_commit": ([_I, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class LrxError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {lrx_strerror(code)} (code {code})")
+
+
+def _check(rc, where):
+    if rc != LRX_OK:
+        raise LrxError(rc, where)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name, dtype=None, shape=None, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------
+def lrx_version() -> int:
+    return int(_lib.lrx_version())
+
+
+def lrx_strerror(code: int) -> str:
+    return _lib.lrx_strerror(int(code)).decode()
+
+
+def lrx_state_sizes(kind, dtype, walkers, n, k_max, delay):
+    """Byte sizes of the state buffers (host only; raises LrxError for bad shapes)."""
+    shp = lrx_shape(kind, dtype, walkers, n, k_max, delay)
+    out = lrx_sizes()
+    _check(_lib.lrx_state_sizes(ctypes.byref(shp), ctypes.byref(out)), "lrx_state_sizes")
+    return {f: getattr(out, f) for f, _ in lrx_sizes._fields_}
+
+
+class State:
+    """Device buffers of one walker batch plus the C state (caller-owned memory)."""
+
+    def __init__(self, kind, dtype, walkers, n, k_max=1, delay=0, device="cuda"):
+        code = DTYPE_CODE[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+        self.sizes = lrx_state_sizes(kind, code, walkers, n, k_max, delay)
+        self.kind, self.code, self.dtype = kind, code, CODE_DTYPE[code]
+        self.walkers, self.n, self.k_max, self.delay = walkers, n, k_max, delay
+        dev = torch.device(device)
+        self.buffers = {}
+        for name in ("inv", "fa", "fb", "stash", "logabs", "phase", "flags", "work"):
+            nbytes = max(int(self.sizes[name]), 256)
+            self.buffers[name] = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.buffers["flags"].zero_()
+        ptr = {k: ctypes.c_void_p(v.data_ptr()) for k, v in self.buffers.items()}
+        self.c = lrx_state(lrx_shape(kind, code, walkers, n, k_max, delay), 0, 0,
+                           ptr["inv"], ptr["fa"], ptr["fb"], ptr["stash"], ptr["logabs"], ptr["phase"],
+                           ptr["flags"], ptr["work"])
+        _check(_lib.lrx_validate(ctypes.byref(self.c)), "lrx_validate")
+
+    # Typed views of the device state.
+    @property
+    def inv(self):
+        return self.buffers["inv"][: self.sizes["inv"]].view(self.dtype).view(self.walkers, self.n, self.n)
+
+    @property
+    def logabs(self):
+        return self.buffers["logabs"][: self.sizes["logabs"]].view(torch.float64)
+
+    @property
+    def phase(self):
+        return self.buffers["phase"][: self.sizes["phase"]].view(WIDE[self.code])
+
+    @property
+    def flags(self):
+        return self.buffers["flags"][: self.sizes["flags"]].view(torch.int32)
+
+    @property
+    def slot(self):
+        return int(self.c.slot)
+
+    @property
+    def wide(self):
+        return WIDE[self.code]
+
+    def ptr(self):
+        return ctypes.byref(self.c)
+
+
+def _kvec(st, k, rows, name="rows"):
+    _dev(k, "k", torch.int32, (st.walkers,))
+    _dev(rows, name, torch.int32, (st.walkers, st.k_max))
+
+
+# ------------------------------------------------------------------ DET
+def lrx_det_init_inverse(st: State, phi, sites, occ, stream=None):
+    pocc = _dev(occ, "occ", torch.int32, (st.walkers, st.n), allow_none=True)
+    pphi = _dev(phi, "phi", st.wide)
+    _check(_lib.lrx_det_init_inverse(st.ptr(), pphi, int(sites), pocc, _stream(stream)), "lrx_det_init_inverse")
+
+
+def lrx_det_refresh(st: State, phi, sites, occ, report=None, stream=None):
+    pocc = _dev(occ, "occ", torch.int32, (st.walkers, st.n), allow_none=True)
+    prep = _dev(report, "report", torch.float64, (st.walkers, 2), allow_none=True)
+    _check(_lib.lrx_det_refresh(st.ptr(), _dev(phi, "phi", st.wide), int(sites), pocc, prep, _stream(stream)),
+           "lrx_det_refresh")
+
+
+def lrx_det_build_hop(st: State, phi, sites, occ, empty, n_empty, k, elec, slot, u, stream=None):
+    _dev(occ, "occ", torch.int32, (st.walkers, st.n))
+    _dev(empty, "empty", torch.int32, (st.walkers, n_empty))
+    _kvec(st, k, elec, "elec")
+    _dev(slot, "slot", torch.int32, (st.walkers, st.k_max))
+    _dev(u, "u", st.dtype, (st.walkers, st.k_max, st.n))
+    _check(_lib.lrx_det_build_hop(st.ptr(), _dev(phi, "phi", st.wide), int(sites), _dev(occ, "occ"),
+                                  _dev(empty, "empty"), int(n_empty), _dev(k, "k"), _dev(elec, "elec"),
+                                  _dev(slot, "slot"), _dev(u, "u"), _stream(stream)), "lrx_det_build_hop")
+
+
+def lrx_det_propose_ratio(st: State, k, rows, u, ratio, stream=None):
+    _kvec(st, k, rows)
+    _dev(u, "u", st.dtype, (st.walkers, st.k_max, st.n))
+    _dev(ratio, "ratio", st.wide, (st.walkers,))
+    _check(_lib.lrx_det_propose_ratio(st.ptr(), _dev(k, "k"), _dev(rows, "rows"), _dev(u, "u"),
+                                      _dev(ratio, "ratio"), _stream(stream)), "lrx_det_propose_ratio")
+
+
+def lrx_det_accept_update(st: State, k, rows, u, accept, stream=None):
+    _kvec(st, k, rows)
+    _dev(u, "u", st.dtype, (st.walkers, st.k_max, st.n))
+    _dev(accept, "accept", torch.uint8, (st.walkers,))
+    _check(_lib.lrx_det_accept_update(st.ptr(), _dev(k, "k"), _dev(rows, "rows"), _dev(u, "u"),
+                                      _dev(accept, "accept"), _stream(stream)), "lrx_det_accept_update")
+
+
+def lrx_det_flush_delayed(st: State, stream=None):
+    _check(_lib.lrx_det_flush_delayed(st.ptr(), _stream(stream)), "lrx_det_flush_delayed")
+
+
+# ------------------------------------------------------------------ PF
+def lrx_pf_init_inverse(st: State, f, sites, occ, stream=None):
+    pocc = _dev(occ, "occ", torch.int32, (st.walkers, st.n), allow_none=True)
+    _check(_lib.lrx_pf_init_inverse(st.ptr(), _dev(f, "f", st.wide), int(sites), pocc, _stream(stream)),
+           "lrx_pf_init_inverse")
+
+
+def lrx_pf_refresh(st: State, f, sites, occ, report=None, stream=None):
+    pocc = _dev(occ, "occ", torch.int32, (st.walkers, st.n), allow_none=True)
+    prep = _dev(report, "report", torch.float64, (st.walkers, 2), allow_none=True)
+    _check(_lib.lrx_pf_refresh(st.ptr(), _dev(f, "f", st.wide), int(sites), pocc, prep, _stream(stream)),
+           "lrx_pf_refresh")
+
+
+def lrx_pf_build_hop(st: State, f, sites, occ, empty, n_empty, k, elec, slot, x, stream=None):
+    _dev(occ, "occ", torch.int32, (st.walkers, st.n))
+    _dev(empty, "empty", torch.int32, (st.walkers, n_empty))
+    _kvec(st, k, elec, "elec")
+    _dev(slot, "slot", torch.int32, (st.walkers, st.k_max))
+    _dev(x, "x", st.dtype, (st.walkers, st.n))
+    _check(_lib.lrx_pf_build_hop(st.ptr(), _dev(f, "f", st.wide), int(sites), _dev(occ, "occ"),
+                                 _dev(empty, "empty"), int(n_empty), _dev(k, "k"), _dev(elec, "elec"),
+                                 _dev(slot, "slot"), _dev(x, "x"), _stream(stream)), "lrx_pf_build_hop")
+
+
+def lrx_pf_propose_ratio(st: State, k, cols, x, ratio, stream=None):
+    _kvec(st, k, cols, "cols")
+    _dev(x, "x", st.dtype, (st.walkers, st.n))
+    _dev(ratio, "ratio", st.wide, (st.walkers,))
+    _check(_lib.lrx_pf_propose_ratio(st.ptr(), _dev(k, "k"), _dev(cols, "cols"), _dev(x, "x"),
+                                     _dev(ratio, "ratio"), _stream(stream)), "lrx_pf_propose_ratio")
+
+
+def lrx_pf_accept_update(st: State, k, cols, x, accept, stream=None):
+    _kvec(st, k, cols, "cols")
+    _dev(x, "x", st.dtype, (st.walkers, st.n))
+    _dev(accept, "accept", torch.uint8, (st.walkers,))
+    _check(_lib.lrx_pf_accept_update(st.ptr(), _dev(k, "k"), _dev(cols, "cols"), _dev(x, "x"),
+                                     _dev(accept, "accept"), _stream(stream)), "lrx_pf_accept_update")
+
+
+def lrx_pf_flush_delayed(st: State, stream=None):
+    _check(_lib.lrx_pf_flush_delayed(st.ptr(), _stream(stream)), "lrx_pf_flush_delayed")
+
+
+# ------------------------------------------------------------------ chain helpers
+def lrx_metropolis(st: State, ratio, u01, seed, counter, mode, accept, stream=None):
+    _dev(ratio, "ratio", st.wide, (st.walkers,))
+    pu = _dev(u01, "u01", torch.float64, (st.walkers,), allow_none=True)
+    _dev(accept, "accept", torch.uint8, (st.walkers,))
+    _check(_lib.lrx_metropolis(st.ptr(), _dev(ratio, "ratio"), pu, ctypes.c_uint64(seed),
+                               ctypes.c_uint64(counter), int(mode), _dev(accept, "accept"), _stream(stream)),
+           "lrx_metropolis")
+
+
+def lrx_hop_commit(walkers, n, n_empty, k_max, k, elec, slot, accept, occ, empty, stream=None):
+    _dev(k, "k", torch.int32, (walkers,))
+    _dev(elec, "elec", torch.int32, (walkers, k_max))
+    _dev(slot, "slot", torch.int32, (walkers, k_max))
+    _dev(accept, "accept", torch.uint8, (walkers,))
+    _dev(occ, "occ", torch.int32, (walkers, n))
+    _dev(empty, "empty", torch.int32, (walkers, n_empty))
+    _check(_lib.lrx_hop_commit(int(walkers), int(n), int(n_empty), int(k_max), _dev(k, "k"), _dev(elec, "elec"),
+                               _dev(slot, "slot"), _dev(accept, "accept"), _dev(occ, "occ"),
+                               _dev(empty, "empty"), _stream(stream)), "lrx_hop_commit")

@@ -1,0 +1,166 @@
+"""The C-ABI library loads, exports every symbol lrx.h declares, and rejects bad
+arguments on the host (no GPU needed: every path here returns before any HIP call)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lrx.h")
+
+lrx = pytest.importorskip("paper_2602_05255_amd.lrx", reason="liblrx.so not built")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lrx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for required in ("lrx_det_init_inverse", "lrx_det_propose_ratio", "lrx_det_accept_update",
+                     "lrx_det_flush_delayed", "lrx_det_refresh", "lrx_pf_init_inverse",
+                     "lrx_pf_propose_ratio", "lrx_pf_accept_update", "lrx_pf_flush_delayed",
+                     "lrx_pf_refresh"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(lrx.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lrx.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (lrx_[a-z0-9_]+)\b", out))
+    assert set(header_functions()) <= exported
+    # the binding wraps exactly the declared entry points
+    assert set(lrx.EXPORTED) == set(header_functions())
+
+
+def test_version_and_strerror():
+    assert lrx.lrx_version() == 1
+    assert "flush" in lrx.lrx_strerror(lrx.LRX_ENEEDFLUSH)
+    assert lrx.lrx_strerror(999) == "unknown error"
+
+
+def test_state_sizes_det():
+    s = lrx.lrx_state_sizes(lrx.LRX_DET, lrx.LRX_F64, 1024, 256, 4, 16)
+    assert s["inv"] == 1024 * 256 * 256 * 8
+    assert s["fa"] == 1024 * 16 * 4 * 256 * 8
+    assert s["fb"] == 1024 * 256 * 16 * 4 * 8
+    assert s["logabs"] == 1024 * 8 and s["phase"] == 1024 * 8 and s["flags"] == 1024 * 4
+    assert s["stash_stride"] % 256 == 0 and s["stash"] == 1024 * s["stash_stride"]
+    assert s["work"] >= 1024 * 256 * 256 * 8
+    c = lrx.lrx_state_sizes(lrx.LRX_DET, lrx.LRX_C64, 2, 32, 1, 0)
+    assert c["inv"] == 2 * 32 * 32 * 8 and c["fa"] == 0 and c["phase"] == 2 * 16
+
+
+def test_state_sizes_pf():
+    s = lrx.lrx_state_sizes(lrx.LRX_PF, lrx.LRX_C64, 256, 512, 1, 32)
+    assert s["fa"] == 256 * 32 * 2 * 512 * 8
+    assert s["fb"] == 256 * 32 * 4 * 8
+    assert s["work"] >= 256 * 512 * 512 * 16
+
+
+@pytest.mark.parametrize("args,code", [
+    ((lrx.LRX_DET, lrx.LRX_F64, 0, 8, 1, 0), lrx.LRX_ESHAPE),
+    ((lrx.LRX_DET, lrx.LRX_F64, 4, 0, 1, 0), lrx.LRX_ESHAPE),
+    ((lrx.LRX_DET, lrx.LRX_F64, 4, 1025, 1, 0), lrx.LRX_ESHAPE),
+    ((lrx.LRX_DET, lrx.LRX_F64, 4, 8, 3, 0), lrx.LRX_ESHAPE),
+    ((lrx.LRX_DET, lrx.LRX_F64, 4, 8, 16, 0), lrx.LRX_ESHAPE),
+    ((lrx.LRX_DET, lrx.LRX_F64, 4, 4, 8, 0), lrx.LRX_ESHAPE),          # k_max > n
+    ((lrx.LRX_DET, lrx.LRX_F64, 4, 8, 1, 65), lrx.LRX_ESHAPE),
+    ((lrx.LRX_DET, lrx.LRX_F64, 4, 64, 8, 64), lrx.LRX_ESHAPE),        # K * k_max > 256
+    ((lrx.LRX_DET, 9, 4, 8, 1, 0), lrx.LRX_EUNSUPPORTED),
+    ((5, lrx.LRX_F64, 4, 8, 1, 0), lrx.LRX_EUNSUPPORTED),
+    ((lrx.LRX_DET, lrx.LRX_C128, 4, 1024, 8, 0), lrx.LRX_EUNSUPPORTED),  # LDS panel limit
+    ((lrx.LRX_PF, lrx.LRX_C64, 4, 7, 1, 0), lrx.LRX_EODD),
+    ((lrx.LRX_PF, lrx.LRX_C64, 4, 8, 2, 0), lrx.LRX_EUNSUPPORTED),
+])
+def test_state_sizes_rejects(args, code):
+    with pytest.raises(lrx.LrxError) as e:
+        lrx.lrx_state_sizes(*args)
+    assert e.value.code == code
+
+
+def fake_state(kind=lrx.LRX_DET, dtype=lrx.LRX_F64, W=4, n=8, k_max=1, delay=0, slot=0, null=()):
+    p = {f: ctypes.c_void_p(0x10000 + 0x1000 * i) for i, f in
+         enumerate(("inv", "fa", "fb", "stash", "logabs", "phase", "flags", "work"))}
+    for f in null:
+        p[f] = ctypes.c_void_p(0)
+    return lrx.lrx_state(lrx.lrx_shape(kind, dtype, W, n, k_max, delay), slot, 0, p["inv"], p["fa"], p["fb"],
+                         p["stash"], p["logabs"], p["phase"], p["flags"], p["work"])
+
+
+P = ctypes.c_void_p(0x20000)
+
+
+def test_validate():
+    lib = lrx._lib
+    assert lib.lrx_validate(ctypes.byref(fake_state())) == lrx.LRX_OK
+    assert lib.lrx_validate(None) == lrx.LRX_EINVAL
+    for f in ("inv", "stash", "logabs", "phase", "flags", "work"):
+        assert lib.lrx_validate(ctypes.byref(fake_state(null=(f,)))) == lrx.LRX_EINVAL
+    # slot buffers are only required with a delay
+    assert lib.lrx_validate(ctypes.byref(fake_state(null=("fa", "fb")))) == lrx.LRX_OK
+    assert lib.lrx_validate(ctypes.byref(fake_state(delay=4, null=("fa",)))) == lrx.LRX_EINVAL
+    assert lib.lrx_validate(ctypes.byref(fake_state(delay=4, slot=5))) == lrx.LRX_EINVAL
+    assert lib.lrx_validate(ctypes.byref(fake_state(delay=4, slot=-1))) == lrx.LRX_EINVAL
+
+
+def test_kind_mismatch():
+    lib = lrx._lib
+    pf = fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64)
+    det = fake_state()
+    assert lib.lrx_det_propose_ratio(ctypes.byref(pf), P, P, P, P, None) == lrx.LRX_EKIND
+    assert lib.lrx_det_flush_delayed(ctypes.byref(pf), None) == lrx.LRX_EKIND
+    assert lib.lrx_pf_accept_update(ctypes.byref(det), P, P, P, P, None) == lrx.LRX_EKIND
+    assert lib.lrx_pf_init_inverse(ctypes.byref(det), P, 8, P, None) == lrx.LRX_EKIND
+
+
+def test_null_arguments():
+    lib = lrx._lib
+    st = fake_state()
+    assert lib.lrx_det_propose_ratio(ctypes.byref(st), None, P, P, P, None) == lrx.LRX_EINVAL
+    assert lib.lrx_det_propose_ratio(ctypes.byref(st), P, P, None, P, None) == lrx.LRX_EINVAL
+    assert lib.lrx_det_accept_update(ctypes.byref(st), P, P, P, None, None) == lrx.LRX_EINVAL
+    assert lib.lrx_det_init_inverse(ctypes.byref(st), None, 8, P, None) == lrx.LRX_EINVAL
+    assert lib.lrx_det_build_hop(ctypes.byref(st), P, 16, P, None, 8, P, P, P, P, None) == lrx.LRX_EINVAL
+    assert lib.lrx_det_build_hop(ctypes.byref(st), P, 4, P, P, 8, P, P, P, P, None) == lrx.LRX_ESHAPE
+
+
+def test_delay_window_bookkeeping():
+    lib = lrx._lib
+    full = fake_state(delay=4, slot=4)
+    assert lib.lrx_det_propose_ratio(ctypes.byref(full), P, P, P, P, None) == lrx.LRX_ENEEDFLUSH
+    assert lib.lrx_det_accept_update(ctypes.byref(full), P, P, P, P, None) == lrx.LRX_ENEEDFLUSH
+    pending = fake_state(delay=4, slot=2)
+    assert lib.lrx_det_refresh(ctypes.byref(pending), P, 16, P, None, None) == lrx.LRX_ENEEDFLUSH
+    pf_full = fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64, delay=2, slot=2)
+    assert lib.lrx_pf_accept_update(ctypes.byref(pf_full), P, P, P, P, None) == lrx.LRX_ENEEDFLUSH
+    # flushing an empty window is a no-op that never touches the GPU
+    empty = fake_state(delay=4, slot=0)
+    assert lib.lrx_det_flush_delayed(ctypes.byref(empty), None) == lrx.LRX_OK
+    plain = fake_state(delay=0, slot=0)
+    assert lib.lrx_det_flush_delayed(ctypes.byref(plain), None) == lrx.LRX_OK
+
+
+def test_metropolis_and_commit_validation():
+    lib = lrx._lib
+    st = fake_state()
+    assert lib.lrx_metropolis(ctypes.byref(st), P, None, 1, 0, 7, P, None) == lrx.LRX_EINVAL
+    assert lib.lrx_metropolis(ctypes.byref(st), P, None, 1, 0, lrx.LRX_MH_UNIFORMS, P, None) == lrx.LRX_EINVAL
+    assert lib.lrx_metropolis(ctypes.byref(st), None, P, 1, 0, lrx.LRX_MH_FORCE, P, None) == lrx.LRX_EINVAL
+    assert lib.lrx_hop_commit(0, 8, 8, 1, P, P, P, P, P, P, None) == lrx.LRX_ESHAPE
+    assert lib.lrx_hop_commit(4, 8, 8, 9, P, P, P, P, P, P, None) == lrx.LRX_ESHAPE
+    assert lib.lrx_hop_commit(4, 8, 8, 1, P, P, P, P, None, P, None) == lrx.LRX_EINVAL
+
+
+def test_pf_refresh_sites_check():
+    lib = lrx._lib
+    st = fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64, n=8)
+    assert lib.lrx_pf_refresh(ctypes.byref(st), P, 4, P, None, None) == lrx.LRX_ESHAPE

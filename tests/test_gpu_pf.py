@@ -1,0 +1,126 @@
+"""Pfaffian path on the GPU vs the full-recompute oracle (Sec. III, Appendix A)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from gpu_util import rel_err, run_chain, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as orc  # noqa: E402
+from paper_2602_05255_amd import inputs as gen  # noqa: E402
+from paper_2602_05255_amd import lrx  # noqa: E402
+from paper_2602_05255_amd.walkers import Walkers  # noqa: E402
+
+DT = {"f64": torch.float64, "f32": torch.float32, "c64": torch.complex64, "c128": torch.complex128}
+
+
+def pf_inputs(seed, L, n, W, cplx):
+    g = gen.generator(seed)
+    f = gen.skew_from(gen.normal(g, (L, L), cplx))
+    occ, emp = gen.occupancy(g, W, L, n)
+    return g, f, occ, emp
+
+
+@pytest.mark.parametrize("dt", ["c128", "f64", "c64"])
+@pytest.mark.parametrize("n", [2, 8, 34, 100, 256])
+def test_pf_init_matches_oracle(dt, n):
+    say(f"pf init dt={dt} n={n}")
+    cplx = dt.startswith("c")
+    g, f, occ, emp = pf_inputs(300 + n, 2 * n, n, 4, cplx)
+    wk = Walkers(lrx.LRX_PF, DT[dt], f, occ, emp)
+    torch.cuda.synchronize()
+    a = orc.pairing_matrices(f, occ)
+    la, ph = orc.slogpf(a)
+    inv = orc.skew_inverse(a)
+    np.testing.assert_allclose(wk.st.logabs.cpu().numpy(), la, rtol=0, atol=1e-9 * n)
+    np.testing.assert_allclose(wk.st.phase.cpu().numpy(), ph, rtol=0, atol=1e-9 * n)
+    m = wk.st.inv.cpu().numpy()
+    assert np.array_equal(m, -np.swapaxes(m, 1, 2)), "state must be exactly skew"
+    tol = 1e-10 if dt in ("f64", "c128") else 1e-5
+    cond = np.linalg.cond(a)
+    em = rel_err(m.astype(inv.dtype), inv, axis=(1, 2))
+    assert np.all(em <= np.maximum(tol, 64 * cond * (1e-16 if tol < 1e-8 else 6e-8))), em
+    assert (wk.st.flags.cpu().numpy() == 0).all()
+
+
+@pytest.mark.parametrize("dt,n,K,W,steps", [
+    ("c128", 64, 0, 6, 25),
+    ("c128", 64, 5, 6, 23),
+    ("f64", 50, 4, 5, 15),       # ragged n
+    ("c128", 128, 32, 3, 36),    # the Pfaffian workload's delay length
+])
+def test_pf_chain(dt, n, K, W, steps):
+    say(f"pf chain dt={dt} n={n} K={K}")
+    cplx = dt.startswith("c")
+    g, f, occ, emp = pf_inputs(400 + n + K, 2 * n, n, W, cplx)
+    draws = [gen.hop_draws(g, W, n, n, (1,), 1) for _ in range(steps)]
+    u01 = [gen.uniforms(g, W) for _ in range(steps)]
+    wk = Walkers(lrx.LRX_PF, DT[dt], f, occ, emp, 1, K)
+    chain = orc.PfChain(f, occ, emp)
+    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=4, tol_ratio=1e-10, tol_inv=1e-10)
+    say(f"  max rel err ratio {worst_r:.2e} inverse {worst_m:.2e}")
+    np.testing.assert_allclose(la, chain.logabs, atol=1e-8)
+    np.testing.assert_allclose(ph, chain.phase, atol=1e-8)
+    m = wk.st.inv.cpu().numpy()
+    assert np.array_equal(m, -np.swapaxes(m, 1, 2)), "updates and flushes keep M exactly skew"
+
+
+def test_pf_c64_bulk_error_is_bounded():
+    say("pf c64 chain")
+    g, f, occ, emp = pf_inputs(500, 256, 128, 4, True)
+    steps = 40
+    draws = [gen.hop_draws(g, 4, 128, 128, (1,), 1) for _ in range(steps)]
+    u01 = [gen.uniforms(g, 4) for _ in range(steps)]
+    wk = Walkers(lrx.LRX_PF, torch.complex64, f, occ, emp, 1, 8, refresh_period=20)
+    chain = orc.PfChain(f, occ, emp)
+    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=10, tol_ratio=5e-3, tol_inv=5e-3)
+    say(f"  c64: max rel err ratio {worst_r:.2e} inverse {worst_m:.2e}")
+
+
+def test_pf_refresh_report():
+    say("pf refresh")
+    g, f, occ, emp = pf_inputs(600, 64, 32, 3, True)
+    wk = Walkers(lrx.LRX_PF, torch.complex128, f, occ, emp)
+    rep = wk.refresh().cpu().numpy()
+    assert rep[:, 0].max() < 1e-13 and rep[:, 1].max() < 1e-12
+    wk.st.logabs.add_(0.25)
+    rep = wk.refresh().cpu().numpy()
+    np.testing.assert_allclose(rep[:, 1], 0.25, atol=1e-10)
+
+
+def test_pfaffian_workload_full_size_sampled():
+    """F = (G - G^T)/2 with G 1024x1024 CN(0,1), n = 512, 256 walkers, complex64 bulk,
+    K = 32, at full size; sampled walkers recomputed by the complex128 oracle."""
+    wl = gen.WORKLOADS["pfaffian_n512_c64"]
+    say(f"full-size {wl.name}")
+    f, occ, emp, g = gen.pairing_inputs(wl)
+    wk = Walkers(lrx.LRX_PF, torch.complex64, f, occ, emp, 1, wl.delay)
+    book = orc.Occupancy(occ, emp)
+    sample = np.array([0, 77, 255])
+    steps = wl.delay + 3
+    worst = 0.0
+    for t in range(steps):
+        k, elec, slot = gen.hop_draws(g, wl.walkers, wl.n, wl.sites - wl.n, (1,), 1)
+        wk.set_draws(k, elec, slot)
+        r = wk.propose().cpu().numpy()
+        if t in (0, wl.delay - 1, steps - 1):
+            prop = book.proposed(k, elec, slot)
+            la0, ph0 = orc.slogpf(orc.pairing_matrices(f, book.occ[sample]))
+            la1, ph1 = orc.slogpf(orc.pairing_matrices(f, prop[sample]))
+            ref = orc.ratio(la1, ph1, la0, ph0)
+            worst = max(worst, float(rel_err(r[sample], ref).max()))
+        mask = np.ones(wl.walkers, bool)
+        wk.decide(mask=mask)
+        wk.apply()
+        book.commit(k, elec, slot, mask)
+    say(f"  c64 sampled ratio error {worst:.2e}")
+    assert worst < 1e-2
+    np.testing.assert_array_equal(wk.occ.cpu().numpy(), book.occ)
+    m = wk.st.inv.cpu().numpy()
+    assert np.array_equal(m, -np.swapaxes(m, 1, 2))
