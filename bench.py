@@ -81,16 +81,18 @@ class Run:
         """One refresh period: P steps with forced accept, flushes every K, then refresh."""
         wk, lrx = self.wk, self.lrx
         for t in range(self.P):
-            wk.use_draws(self.k[t], self.e[t], self.s[t])
-            wk.propose()
-            wk.decide(mode=lrx.LRX_MH_FORCE)
+            k, e, s = self.k[t], self.e[t], self.s[t]
             if timer is not None:
+                timer.begin("propose", wk.st.slot)
+            lrx.lrx_det_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
+                                    wk.ratio)
+            if timer is not None:
+                timer.end("propose")
                 timer.begin("accept", wk.st.slot)
-            lrx.lrx_det_accept_update(wk.st, wk._k, wk._elec, wk.u, wk.accept)
+            lrx.lrx_det_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
+                                   wk.empty, wk.n_empty)
             if timer is not None:
                 timer.end("accept")
-            lrx.lrx_hop_commit(wk.W, wk.n, wk.n_empty, wk.k_max, wk._k, wk._elec, wk._slot, wk.accept,
-                               wk.occ, wk.empty)
             if wk.delay and wk.st.slot == wk.delay:
                 if timer is not None:
                     timer.begin("flush", wk.st.slot)

@@ -221,6 +221,30 @@ int lrx_det_accept_update(lrx_state *st, const int32_t *k, const int32_t *rows,
                           const void *u, uint8_t *accept, void *stream);
 
 /*
+ * lrx_det_build_hop followed by lrx_det_propose_ratio in one launch: the hop
+ * vectors u = phi[s'] - phi[s] are built inside the ratio kernel (and written
+ * to u for the accept that follows).  Arguments as for the two calls; rows are
+ * the electron labels elec.
+ */
+int lrx_det_propose_hop(lrx_state *st, const void *phi, int32_t sites,
+                        const int32_t *occ, const int32_t *empty, int32_t n_empty,
+                        const int32_t *k, const int32_t *elec, const int32_t *slot,
+                        void *u, void *ratio, void *stream);
+
+/*
+ * lrx_metropolis, lrx_det_accept_update and lrx_hop_commit in one launch:
+ * every block of a walker takes the same Metropolis decision from the stashed
+ * ratio (mode LRX_MH_UNIFORMS with u01, LRX_MH_DEVICE_RNG with seed/counter,
+ * or LRX_MH_FORCE), applies the update, and one block commits the occupancy.
+ *   accept: uint8 [W] out (the decision actually applied).
+ */
+int lrx_det_accept_hop(lrx_state *st, const int32_t *k, const int32_t *elec,
+                       const int32_t *slot, const void *u, int32_t mode,
+                       const double *u01, uint64_t seed, uint64_t counter,
+                       uint8_t *accept, int32_t *occ, int32_t *empty,
+                       int32_t n_empty, void *stream);
+
+/*
  * Flush the delay window (Eq. delayed_Ainv): M0 -= sum_{t<tau} b_t a_t^T as one
  * batched MFMA GEMM with inner dimension tau*k_max, then zero the slots and
  * set st->slot = 0.  A no-op when st->slot == 0 or K == 0.

@@ -16,7 +16,10 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblrx.so")
 
-SOURCES = ["lrx_capi.cpp", "lrx_det.hip", "lrx_pf.hip", "lrx_flush.hip", "lrx_factor.hip"]
+# (source, object name, extra flags); the determinant kernels build once per bulk dtype.
+SOURCES = [("lrx_capi.cpp", "lrx_capi", []), ("lrx_pf.hip", "lrx_pf", []), ("lrx_flush.hip", "lrx_flush", []),
+           ("lrx_factor.hip", "lrx_factor", [])] + \
+          [("lrx_det.hip", f"lrx_det_{i}", [f"-DLRX_DT={i}"]) for i in range(4)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -28,11 +31,12 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(item) -> str:
+    src, name, extra = item
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC, "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, "-x", "hip", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -83,6 +83,7 @@ static StepArgs step_args(const lrx_state *st) {
     a.logabs = st->logabs;
     a.phase = st->phase;
     a.flags = st->flags;
+    a.mh_mode = -1;
     return a;
 }
 
@@ -257,6 +258,56 @@ int lrx_det_accept_update(lrx_state *st, const int32_t *k, const int32_t *rows, 
     a.rows = rows;
     a.u = u;
     a.accept = accept;
+    rc = hip_rc(det_accept(st->shape.dtype, a, as_stream(stream)));
+    if (rc == LRX_OK && st->shape.delay > 0) st->slot += 1;
+    return rc;
+}
+
+int lrx_det_propose_hop(lrx_state *st, const void *phi, int32_t sites, const int32_t *occ, const int32_t *empty,
+                        int32_t n_empty, const int32_t *k, const int32_t *elec, const int32_t *slot, void *u,
+                        void *ratio, void *stream) {
+    int rc = check_kind(st, LRX_DET);
+    if (rc) return rc;
+    if (!phi || !occ || !empty || !k || !elec || !slot || !u || !ratio) return LRX_EINVAL;
+    if (sites < st->shape.n || n_empty < 1) return LRX_ESHAPE;
+    if (st->shape.delay > 0 && st->slot >= st->shape.delay) return LRX_ENEEDFLUSH;
+    StepArgs a = step_args(st);
+    a.k = k;
+    a.rows = elec;
+    a.u = u;
+    a.ratio = ratio;
+    a.hop_table = phi;
+    a.sites = sites;
+    a.n_empty = n_empty;
+    a.occ = const_cast<int32_t *>(occ);
+    a.empty = const_cast<int32_t *>(empty);
+    a.slot = slot;
+    return hip_rc(det_propose(st->shape.dtype, a, as_stream(stream)));
+}
+
+int lrx_det_accept_hop(lrx_state *st, const int32_t *k, const int32_t *elec, const int32_t *slot, const void *u,
+                       int32_t mode, const double *u01, uint64_t seed, uint64_t counter, uint8_t *accept,
+                       int32_t *occ, int32_t *empty, int32_t n_empty, void *stream) {
+    int rc = check_kind(st, LRX_DET);
+    if (rc) return rc;
+    if (!k || !elec || !slot || !u || !accept || !occ || !empty) return LRX_EINVAL;
+    if (mode != LRX_MH_UNIFORMS && mode != LRX_MH_DEVICE_RNG && mode != LRX_MH_FORCE) return LRX_EINVAL;
+    if (mode == LRX_MH_UNIFORMS && !u01) return LRX_EINVAL;
+    if (n_empty < 1) return LRX_ESHAPE;
+    if (st->shape.delay > 0 && st->slot >= st->shape.delay) return LRX_ENEEDFLUSH;
+    StepArgs a = step_args(st);
+    a.k = k;
+    a.rows = elec;
+    a.u = u;
+    a.accept = accept;
+    a.slot = slot;
+    a.occ = occ;
+    a.empty = empty;
+    a.n_empty = n_empty;
+    a.mh_mode = mode;
+    a.u01 = u01;
+    a.seed = seed;
+    a.counter = counter;
     rc = hip_rc(det_accept(st->shape.dtype, a, as_stream(stream)));
     if (rc == LRX_OK && st->shape.delay > 0) st->slot += 1;
     return rc;

@@ -237,3 +237,43 @@ __device__ __forceinline__ void st16(T *p, const T (&o)[vec16<T>()]) {
     __builtin_memcpy(&raw, &o[0], 16);
     *reinterpret_cast<uint4 *>(p) = raw;
 }
+
+// ---------------------------------------------------------------- RNG
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0..c3), key
+// (k0, k1), ten rounds of two 32x32->64 multiplies with a Weyl key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)M0 * c[0];
+        uint64_t p1 = (uint64_t)M1 * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += W0; k1 += W1;
+    }
+}
+
+// Uniform double in [0, 1) with 53 random bits for walker w at step counter ctr.
+__device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t ctr, uint32_t w) {
+    uint32_t c[4] = {w, (uint32_t)ctr, (uint32_t)(ctr >> 32), 0u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t bits = ((uint64_t)(c[0] >> 5) << 26) | (uint64_t)(c[1] >> 6);
+    return (double)bits * 0x1.0p-53;
+}
+
+__device__ __forceinline__ double abs2_wide(double r) { return r * r; }
+__device__ __forceinline__ double abs2_wide(cf64 r) { return r.x * r.x + r.y * r.y; }
+
+// Metropolis rule on |r|^2 (zero / non-finite ratios and flagged walkers rejected).
+template <class Wd>
+__device__ __forceinline__ uint8_t mh_decide(Wd r, uint32_t flags, int mode, double u01, uint64_t seed,
+                                             uint64_t ctr, uint32_t w) {
+    const double p = abs2_wide(r);
+    if (flags != 0 || !isfinite(p) || !(p > 0.0)) return 0;
+    if (mode == LRX_MH_FORCE) return 1;
+    const double uu = mode == LRX_MH_UNIFORMS ? u01 : philox_uniform(seed, ctr, w);
+    return uu < fmin(1.0, p) ? 1 : 0;
+}

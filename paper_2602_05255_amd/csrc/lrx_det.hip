@@ -67,17 +67,31 @@ __global__ __launch_bounds__(kThreads) void det_build_hop_kernel(HopArgs a) {
 }
 
 // ------------------------------------------------------------------ propose
-// One work-group per walker.  Cost O(n k + tau n k) per walker: rows I of M0,
-// the a-slots (only their live columns) and b-slot rows I.
-template <class T, int KM>
-__global__ __launch_bounds__(kThreads) void det_propose_kernel(StepArgs a) {
+// One work-group per walker; thread t owns rows i = t + 256 ii of the columns.
+// Cost O(n k + tau n k) per walker: rows I of M0, the live columns of the
+// a-slots (read once), b-slot rows I and u.
+//   C[c][i]  = M0[I_c][i] - sum_{live te} a_te[i] b_te[I_c]     (A_{tau-1}^-1[:, I])
+//   G[te][c] = a_te . u_c   (reduced in groups with the multi-value butterfly)
+//   R        = I + u^T C,   r = det R
+// With a hop table the update vectors u = Phi[s'] - Phi[s] are built here too.
+template <class T> constexpr int prop_nv() { return sizeof(T) <= 4 ? 32 : (sizeof(T) == 8 ? 16 : 8); }
+
+// NW waves per walker (one work-group); each thread owns NI entries i = t + 64 NW ii.
+// With NW = 1 every reduction stays inside the wave and no block barrier sits on
+// the critical path.
+template <class T, int KM, int NW, int NI>
+__global__ __launch_bounds__(64 * NW) void det_propose_kernel(StepArgs a) {
     using Wd = typename Wide<T>::type;
+    constexpr int NT = 64 * NW;
+    constexpr int NVG = prop_nv<T>() >= KM ? prop_nv<T>() : KM;   // values per group reduction
+    constexpr int GS0 = NVG / KM;
+    constexpr int GS = (GS0 * NI <= 32) ? GS0 : (32 / NI > 0 ? 32 / NI : 1);   // slot columns per group
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & (LRX_WAVE - 1), wv = tid / LRX_WAVE;
     const int n = a.n, tau = a.tau, KK = a.K * KM, TE = tau * KM;
     const T *M = static_cast<const T *>(a.inv) + (size_t)w * n * n;
-    const T *u = static_cast<const T *>(a.u) + (size_t)w * KM * n;
+    T *u = const_cast<T *>(static_cast<const T *>(a.u)) + (size_t)w * KM * n;
     const T *fa = static_cast<const T *>(a.fa) + (size_t)w * KK * n;
     const T *fb = static_cast<const T *>(a.fb) + (size_t)w * n * KK;
     uint8_t *st = a.stash + (size_t)w * a.L.stride;
@@ -88,115 +102,161 @@ __global__ __launch_bounds__(kThreads) void det_propose_kernel(StepArgs a) {
     const int *kslot = reinterpret_cast<const int *>(st + a.L.kslot);
 
     T *s_fbI = reinterpret_cast<T *>(smem);                 // [KM][TE]
-    T *s_red = s_fbI + (size_t)KM * TE;                     // [kWaves][KM*KM]
-    __shared__ int s_rows[KM];
-    __shared__ int s_k;
-    __shared__ int s_bad;
+    T *s_red = s_fbI + (size_t)KM * TE;                     // [NW][64]
+    int *s_live = reinterpret_cast<int *>(s_red + NW * 64);   // [TE]
+    int *s_ks = s_live + TE;                                   // [tau]
+    __shared__ int s_rows[KM], s_src[KM], s_dst[KM];
+    __shared__ int s_k, s_bad, s_nl;
 
-    if (tid == 0) {
-        int kw = a.k[w];
-        int bad = (kw < 1 || kw > KM);
-        s_k = bad ? 1 : kw;
-        s_bad = bad;
-    }
-    __syncthreads();
-    const int k = s_k;
+    const bool fused = a.hop_table != nullptr;
+    for (int t = tid; t < tau; t += NT) s_ks[t] = min(max(kslot[t], 0), KM);
     if (tid < KM) {
+        int kw = a.k[w];
+        const int bad = (kw < 1 || kw > KM);
+        kw = bad ? 1 : kw;
         int r = a.rows[w * KM + tid];
-        if (tid < k && (r < 0 || r >= n)) { atomicOr(&s_bad, 1); r = 0; }
-        s_rows[tid] = (tid < k) ? r : 0;
+        int src = 0, dst = 0, b = bad;
+        if (tid < kw) {
+            if (r < 0 || r >= n) { b = 1; r = 0; }
+            if (fused) {
+                const int sl = a.slot[w * KM + tid];
+                if (sl < 0 || sl >= a.n_empty) {
+                    b = 1;
+                } else {
+                    src = a.occ[(size_t)w * n + r];
+                    dst = a.empty[(size_t)w * a.n_empty + sl];
+                    if (src < 0 || src >= a.sites || dst < 0 || dst >= a.sites) { b = 1; src = dst = 0; }
+                }
+            }
+        }
+        s_rows[tid] = (tid < kw) ? r : 0;
+        s_src[tid] = src;
+        s_dst[tid] = dst;
+        if (tid == 0) { s_k = kw; s_bad = 0; }
+        __builtin_amdgcn_wave_barrier();
+        if (b) atomicOr(&s_bad, 1);
     }
+    for (int idx = tid; idx < TE * KM; idx += NT) G[idx] = zero<T>();
     __syncthreads();
-    // b-slot rows I (only needed for the delayed form).
-    for (int idx = tid; idx < KM * TE; idx += kThreads) {
+    if (tid == 0) {
+        int nl = 0;
+        for (int t = 0; t < tau; ++t)
+            for (int e = 0; e < s_ks[t]; ++e) s_live[nl++] = t * KM + e;
+        s_nl = nl;
+    }
+    const int k = s_k;
+    const bool bad = s_bad != 0;
+    for (int idx = tid; idx < KM * TE; idx += NT) {
         int c = idx / TE, te = idx - c * TE;
         s_fbI[idx] = (c < k) ? fb[(size_t)s_rows[c] * KK + te] : zero<T>();
     }
-    __syncthreads();
 
-    // C[c][i] = M0[I_c][i] - sum_{t<tau, e<k_t} a_t[i][e] b_t[I_c][e]
-    for (int i = tid; i < n; i += kThreads) {
-        T cv[KM];
+    T uv[NI][KM], cv[NI][KM];
+    const Wd *tab = static_cast<const Wd *>(a.hop_table);
 #pragma unroll
-        for (int c = 0; c < KM; ++c) cv[c] = (c < k) ? M[(size_t)s_rows[c] * n + i] : zero<T>();
-        for (int t = 0; t < tau; ++t) {
-            const int kt = min(max(kslot[t], 0), KM);
-            for (int e = 0; e < kt; ++e) {
-                const int te = t * KM + e;
-                const T av = fa[(size_t)te * n + i];
+    for (int ii = 0; ii < NI; ++ii) {
+        const int i = tid + ii * NT;
+        const bool valid = i < n;
 #pragma unroll
-                for (int c = 0; c < KM; ++c)
-                    if (c < k) cv[c] = fmsc(av, s_fbI[c * TE + te], cv[c]);
+        for (int c = 0; c < KM; ++c) {
+            T uu = zero<T>(), cc = zero<T>();
+            if (valid && c < k) {
+                if (fused) uu = bad ? zero<T>() : conv<T>(tab[(size_t)s_dst[c] * n + i] - tab[(size_t)s_src[c] * n + i]);
+                else uu = u[(size_t)c * n + i];
+                cc = M[(size_t)s_rows[c] * n + i];
+            }
+            if (fused && valid) u[(size_t)c * n + i] = uu;
+            uv[ii][c] = uu;
+            cv[ii][c] = cc;
+        }
+    }
+    __syncthreads();
+    const int nl = s_nl;
+    for (int g0 = 0; g0 < nl; g0 += GS) {
+        T gp[GS * KM];
+#pragma unroll
+        for (int q = 0; q < GS * KM; ++q) gp[q] = zero<T>();
+        T av[GS][NI];
+#pragma unroll
+        for (int gi = 0; gi < GS; ++gi) {
+            const int te = (g0 + gi < nl) ? s_live[g0 + gi] : -1;
+#pragma unroll
+            for (int ii = 0; ii < NI; ++ii) {
+                const int i = tid + ii * NT;
+                av[gi][ii] = (te >= 0 && i < n) ? fa[(size_t)te * n + i] : zero<T>();
             }
         }
 #pragma unroll
-        for (int c = 0; c < KM; ++c) C[(size_t)c * n + i] = cv[c];
-    }
-    __threadfence_block();
-    __syncthreads();
-
-    // R[c][d] = delta_cd + sum_i u[c][i] C[d][i]
-    for (int c = 0; c < k; ++c) {
-        T p[KM];
+        for (int gi = 0; gi < GS; ++gi) {
+            const int te = (g0 + gi < nl) ? s_live[g0 + gi] : 0;
 #pragma unroll
-        for (int d = 0; d < KM; ++d) p[d] = zero<T>();
-        for (int i = tid; i < n; i += kThreads) {
-            const T uc = u[(size_t)c * n + i];
+            for (int ii = 0; ii < NI; ++ii)
 #pragma unroll
-            for (int d = 0; d < KM; ++d) p[d] = fmac(uc, C[(size_t)d * n + i], p[d]);
-        }
-        T tot = wave_sum_multi<T, KM>(p);
-        if (lane < KM) s_red[wv * KM * KM + c * KM + lane] = tot;
-    }
-
-    // G[te][c] = a_te . u_c  (te < tau*KM), used by the delayed accept.
-    if (a.K > 0) {
-        for (int te = wv; te < TE; te += kWaves) {
-            const int t = te / KM, e = te - t * KM;
-            const bool live = e < min(max(kslot[t], 0), KM);
-            T p[KM];
-#pragma unroll
-            for (int c = 0; c < KM; ++c) p[c] = zero<T>();
-            if (live) {
-                for (int i = lane; i < n; i += LRX_WAVE) {
-                    const T av = fa[(size_t)te * n + i];
-#pragma unroll
-                    for (int c = 0; c < KM; ++c)
-                        if (c < k) p[c] = fmac(av, u[(size_t)c * n + i], p[c]);
+                for (int c = 0; c < KM; ++c) {
+                    cv[ii][c] = fmsc(av[gi][ii], s_fbI[c * TE + te], cv[ii][c]);
+                    gp[gi * KM + c] = fmac(av[gi][ii], uv[ii][c], gp[gi * KM + c]);
                 }
+        }
+        const T tot = wave_sum_multi<T, GS * KM>(gp);      // lane l: value l (gi = l / KM, c = l % KM)
+        if constexpr (NW == 1) {
+            if (lane < GS * KM && g0 + lane / KM < nl) {
+                const int c = lane % KM;
+                G[(size_t)s_live[g0 + lane / KM] * KM + c] = (c < k) ? tot : zero<T>();
             }
-            T tot = wave_sum_multi<T, KM>(p);
-            if (lane < KM) G[(size_t)te * KM + lane] = (live && lane < k) ? tot : zero<T>();
+        } else {
+            if (lane < GS * KM) s_red[wv * 64 + lane] = tot;
+            __syncthreads();
+            if (tid < GS * KM && g0 + tid / KM < nl) {
+                T sum = zero<T>();
+#pragma unroll
+                for (int q = 0; q < NW; ++q) sum = sum + s_red[q * 64 + tid];
+                const int c = tid % KM;
+                G[(size_t)s_live[g0 + tid / KM] * KM + c] = (c < k) ? sum : zero<T>();
+            }
+            __syncthreads();
         }
     }
+    // C, and R[c][d] = delta_cd + sum_i u[c][i] C[d][i]
+    T rp[KM * KM];
+#pragma unroll
+    for (int q = 0; q < KM * KM; ++q) rp[q] = zero<T>();
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+        const int i = tid + ii * NT;
+        if (i < n) {
+#pragma unroll
+            for (int c = 0; c < KM; ++c) C[(size_t)c * n + i] = cv[ii][c];
+        }
+#pragma unroll
+        for (int c = 0; c < KM; ++c)
+#pragma unroll
+            for (int d = 0; d < KM; ++d) rp[c * KM + d] = fmac(uv[ii][c], cv[ii][d], rp[c * KM + d]);
+    }
+    const T rt = wave_sum_multi<T, KM * KM>(rp);
+    if (lane < KM * KM) s_red[wv * 64 + lane] = rt;
     __syncthreads();
 
     if (tid == 0) {
         T r[KM * KM], ri[KM * KM];
         for (int c = 0; c < KM; ++c)
             for (int d = 0; d < KM; ++d) {
-                T s = (c == d) ? one<T>() : zero<T>();
+                T sacc = (c == d) ? one<T>() : zero<T>();
                 if (c < k && d < k)
-                    for (int q = 0; q < kWaves; ++q) s = s + s_red[q * KM * KM + c * KM + d];
-                r[c * KM + d] = s;
+                    for (int q = 0; q < NW; ++q) sacc = sacc + s_red[q * 64 + c * KM + d];
+                r[c * KM + d] = sacc;
                 ri[c * KM + d] = zero<T>();
             }
         Wd det;
         bool sing;
         small_lu_det_inv<T, KM>(r, k, ri, det, sing);
         for (int c = 0; c < KM * KM; ++c) Rinv[c] = ri[c];
-        if (s_bad) det = zero<Wd>();
+        if (bad) det = zero<Wd>();
         *ratio_st = det;
         static_cast<Wd *>(a.ratio)[w] = det;
-        uint32_t f = 0;
-        if (s_bad) f |= LRX_FLAG_BADINDEX;
-        if (!finite_v(det)) f |= LRX_FLAG_NONFINITE;
-        if (sing || is_zero(det) || !finite_v(det)) f |= LRX_FLAG_SINGULAR_R;
-        // SINGULAR_R / NONFINITE describe only this proposal: they are kept in
-        // the stash copy of the ratio (zero => accept is a no-op) rather than
-        // in the sticky walker flags.  Bad indices are sticky.
-        if (f & LRX_FLAG_BADINDEX) flag_or(a.flags, w, LRX_FLAG_BADINDEX);
-        if (f & (LRX_FLAG_SINGULAR_R | LRX_FLAG_NONFINITE)) *ratio_st = zero<Wd>();
+        // A zero or non-finite ratio makes the update impossible (Sec. II.A): the
+        // stash copy is zeroed so accept skips the walker.  Bad indices are sticky.
+        if (bad) atomicOr(a.flags + w, LRX_FLAG_BADINDEX);
+        if (sing || is_zero(det) || !finite_v(det)) *ratio_st = zero<Wd>();
     }
 }
 
@@ -204,17 +264,175 @@ __global__ __launch_bounds__(kThreads) void det_propose_kernel(StepArgs a) {
 // Row-streaming pass.  A work-group handles `rows_per_block` rows of one
 // walker; each wave takes RB rows at a time, each lane holding NEL elements of
 // every row (16-byte vectors, coalesced).  u and C live in LDS, shared by all
-// rows of the block.
+// rows of the block.  The row loop is specialised on KC, the walker's rank
+// rounded up to a power of two: the padded columns of u and C are zero and the
+// padded rows/columns of R^-1 are zero, so padding is exact.
 //
-// DELAYED = false: Sherman-Morrison/Woodbury in place (Eq. det_inv).
-// DELAYED = true : b_tau rows and a_tau columns written to slot tau (Sec. II.C).
-template <class T, int KM, int NEL, int RB, bool DELAYED>
+// Per row batch: dots p[r][c] = M[q_r,:] . u_c (minus the slot correction),
+// one multi-value butterfly reduction (lane l then holds w[r][c] with
+// l = r*KC + c), z[r][c] = sum_d R^-1[c][d] w[r][d] on that lane, then
+//   DELAYED = false: M[q_r,:] -= sum_c z[r][c] C[:, c]^T  (Eq. det_inv)
+//   DELAYED = true : b_tau[q_r][c] = z[r][c]               (Eq. det_b)
+template <class T>
+__device__ __forceinline__ T lane_bcast(T v, int src) {     // src: wave-uniform
+    static_assert(sizeof(T) % 4 == 0, "");
+    constexpr int NW = sizeof(T) / 4;
+    int w[NW];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = __builtin_amdgcn_readlane(w[i], src);
+    T o;
+    __builtin_memcpy(&o, w, sizeof(T));
+    return o;
+}
+__device__ __forceinline__ float shfl_any(float v, int src) { return __shfl(v, src, LRX_WAVE); }
+__device__ __forceinline__ double shfl_any(double v, int src) { return __shfl(v, src, LRX_WAVE); }
+__device__ __forceinline__ cf32 shfl_any(cf32 v, int src) { return {__shfl(v.x, src, LRX_WAVE), __shfl(v.y, src, LRX_WAVE)}; }
+__device__ __forceinline__ cf64 shfl_any(cf64 v, int src) { return {__shfl(v.x, src, LRX_WAVE), __shfl(v.y, src, LRX_WAVE)}; }
+
+template <class T>
+struct AcceptCtx {
+    T *M, *fa, *fb;
+    const T *G;
+    const T *s_u, *s_c, *s_ri;
+    int n, KK, tau, TE, q0, q1, npad, wv, lane;
+    bool vec_ok;
+};
+
+template <class T, int KC, int KM, int NEL, int RB, int MG, bool DELAYED>
+__device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
+    constexpr int V = vec16<T>();
+    constexpr int NCH = NEL / V;
+    constexpr int NV = RB * KC;
+    const int lane = c.lane;
+    const int my_r = (lane % NV) / KC, my_c = lane % KC;
+    T rrow[KC];
+#pragma unroll
+    for (int d = 0; d < KC; ++d) rrow[d] = c.s_ri[my_c * KM + d];
+    // Slot products G[te][c] (= a_te . u_c) for the slot columns this lane owns, te = lane + 64 m.
+    T g[MG][KC];
+#pragma unroll
+    for (int m = 0; m < MG; ++m)
+#pragma unroll
+        for (int cc = 0; cc < KC; ++cc) {
+            const int te = lane + m * LRX_WAVE;
+            g[m][cc] = (DELAYED && te < c.TE) ? c.G[(size_t)te * KM + cc] : zero<T>();
+        }
+    const int n = c.n;
+    // Software pipeline: the rows of the next batch are requested before the
+    // current batch is reduced, so two batches of loads are in flight per wave.
+    auto load_rows = [&](int qb, T (&x)[RB][NEL]) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int q = qb + r;
+            const T *row = c.M + (size_t)q * n;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int j0 = ch * V * LRX_WAVE + lane * V;
+                T tmp[V];
+                if (q < c.q1 && c.vec_ok && j0 + V <= n) {
+                    ld16<T>(row + j0, tmp);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) tmp[v] = (q < c.q1 && j0 + v < n) ? row[j0 + v] : zero<T>();
+                }
+#pragma unroll
+                for (int v = 0; v < V; ++v) x[r][ch * V + v] = tmp[v];
+            }
+        }
+    };
+    const int qstep = kWaves * RB;
+    T xn[RB][NEL];
+    load_rows(c.q0 + c.wv * RB, xn);
+    for (int qb = c.q0 + c.wv * RB; qb < c.q1; qb += qstep) {
+        T x[RB][NEL];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < NEL; ++e) x[r][e] = xn[r][e];
+        if (qb + qstep < c.q1) load_rows(qb + qstep, xn);
+        T p[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) p[i] = zero<T>();
+#pragma unroll
+        for (int cc = 0; cc < KC; ++cc) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                T uv[V];
+                ld16<T>(c.s_u + (size_t)cc * c.npad + ch * V * LRX_WAVE + lane * V, uv);
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) p[r * KC + cc] = fmac(x[r][ch * V + v], uv[v], p[r * KC + cc]);
+            }
+        }
+        if (DELAYED) {
+            // - sum_t b_t[q][:] (a_t^T u): this lane owns slot columns te = lane + 64 m
+#pragma unroll
+            for (int m = 0; m < MG; ++m) {
+                if (m * LRX_WAVE < c.TE) {
+                    const int te = lane + m * LRX_WAVE;
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        const int q = qb + r;
+                        const T bv = (te < c.TE && q < c.q1) ? c.fb[(size_t)q * c.KK + te] : zero<T>();
+#pragma unroll
+                        for (int cc = 0; cc < KC; ++cc) p[r * KC + cc] = fmsc(bv, g[m][cc], p[r * KC + cc]);
+                    }
+                }
+            }
+        }
+        const T w = wave_sum_multi<T, NV>(p);     // lane l: w[r][c], l mod NV = r*KC + c
+        T z = zero<T>();
+#pragma unroll
+        for (int d = 0; d < KC; ++d) z = fmac(rrow[d], shfl_any(w, my_r * KC + d), z);
+        if (DELAYED) {
+            const int q = qb + my_r;
+            if (lane < NV && q < c.q1) c.fb[(size_t)q * c.KK + c.tau * KM + my_c] = z;
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < KC; ++cc) {
+                T zr[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) zr[r] = lane_bcast(z, r * KC + cc);
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    T cv[V];
+                    ld16<T>(c.s_c + (size_t)cc * c.npad + ch * V * LRX_WAVE + lane * V, cv);
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+#pragma unroll
+                        for (int v = 0; v < V; ++v) x[r][ch * V + v] = fmsc(zr[r], cv[v], x[r][ch * V + v]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int q = qb + r;
+                if (q >= c.q1) continue;
+                T *row = c.M + (size_t)q * n;
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int j0 = ch * V * LRX_WAVE + lane * V;
+                    T tmp[V];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) tmp[v] = x[r][ch * V + v];
+                    if (c.vec_ok && j0 + V <= n) {
+                        st16<T>(row + j0, tmp);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) if (j0 + v < n) row[j0 + v] = tmp[v];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <class T, int KM, int NEL, int RB, int MG, bool DELAYED>
 __global__ __launch_bounds__(kThreads) void det_accept_kernel(StepArgs a, int rows_per_block, int blocks_per_walker) {
     using Wd = typename Wide<T>::type;
     constexpr int V = vec16<T>();
-    constexpr int NCH = NEL / V;                 // 16-byte chunks per lane per row
-    constexpr int NV = RB * KM;                  // reduced values per row batch
-    constexpr int MG = 4;                        // max slot columns per lane (TE <= 256)
+    constexpr int NCH = NEL / V;
     extern __shared__ __align__(16) unsigned char smem[];
 
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -239,10 +457,32 @@ __global__ __launch_bounds__(kThreads) void det_accept_kernel(StepArgs a, int ro
 
     int k = a.k[w];
     k = (k < 1 || k > KM) ? 1 : k;
-    const bool take = a.accept[w] != 0 && a.flags[w] == 0 && !is_zero(ratio);
+    const uint32_t fl = a.flags[w];
+    uint8_t acc;
+    if (a.mh_mode >= 0) {   // fused Metropolis decision (identical in every block of the walker)
+        acc = mh_decide<Wd>(ratio, fl, a.mh_mode, a.mh_mode == LRX_MH_UNIFORMS ? a.u01[w] : 0.0, a.seed,
+                            a.counter, (uint32_t)w);
+    } else {
+        acc = a.accept[w];
+    }
+    const bool take = acc != 0 && fl == 0 && !is_zero(ratio);
+    const int kc = k == 1 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
+    if (rb == 0 && tid == 0) {
+        if (a.mh_mode >= 0 || (!take && acc)) a.accept[w] = take ? 1 : 0;   // skipped: no occupancy commit
+        if (take && a.occ) {   // fused occupancy commit
+            for (int c = 0; c < k; ++c) {
+                const int e = a.rows[w * KM + c], sl = a.slot[w * KM + c];
+                if (e < 0 || e >= n || sl < 0 || sl >= a.n_empty) continue;
+                int32_t *po = a.occ + (size_t)w * n + e;
+                int32_t *pe = a.empty + (size_t)w * a.n_empty + sl;
+                const int32_t t = *po;
+                *po = *pe;
+                *pe = t;
+            }
+        }
+    }
 
     if (!take) {
-        if (rb == 0 && tid == 0 && a.accept[w]) a.accept[w] = 0;   // skipped: no occupancy commit
         if (DELAYED) {   // a rejected walker's slot contributes nothing
             for (int idx = tid; idx < KM * (q1 - q0); idx += kThreads) {
                 int c = idx / (q1 - q0), q = q0 + idx - c * (q1 - q0);
@@ -262,202 +502,45 @@ __global__ __launch_bounds__(kThreads) void det_accept_kernel(StepArgs a, int ro
     T *s_u = reinterpret_cast<T *>(smem);       // [KM][npad]
     T *s_c = s_u + (size_t)KM * npad;           // [KM][npad]
     T *s_ri = s_c + (size_t)KM * npad;          // [KM*KM]
-    T *s_w = s_ri + KM * KM;                    // [kWaves][NV]
-    for (int idx = tid; idx < KM * npad; idx += kThreads) {
+    for (int idx = tid; idx < kc * npad; idx += kThreads) {
         int c = idx / npad, j = idx - c * npad;
         bool ok = c < k && j < n;
         s_u[idx] = ok ? u[(size_t)c * n + j] : zero<T>();
-        s_c[idx] = ok ? C[(size_t)c * n + j] : zero<T>();
+        if (!DELAYED) s_c[idx] = ok ? C[(size_t)c * n + j] : zero<T>();
     }
-    if (tid < KM * KM) s_ri[tid] = Rinv[tid];
-    if (DELAYED) {   // a_tau = C, written for this block's rows
+    if (tid < KM * KM) {
+        const int c = tid / KM, d = tid - c * KM;
+        s_ri[tid] = (c < k && d < k) ? Rinv[tid] : zero<T>();
+    }
+    if (DELAYED) {   // a_tau = C for this block's rows; b_tau columns beyond kc are zero
         for (int idx = tid; idx < KM * (q1 - q0); idx += kThreads) {
             int c = idx / (q1 - q0), q = q0 + idx - c * (q1 - q0);
             fa[(size_t)(tau * KM + c) * n + q] = (c < k) ? C[(size_t)c * n + q] : zero<T>();
+            if (c >= kc) fb[(size_t)q * KK + tau * KM + c] = zero<T>();
         }
-    }
-    // Slot products G[te][c] for the slot columns this lane owns (te = lane + 64 m).
-    T g[MG][KM];
-    if (DELAYED) {
-#pragma unroll
-        for (int m = 0; m < MG; ++m)
-#pragma unroll
-            for (int c = 0; c < KM; ++c) {
-                int te = lane + m * LRX_WAVE;
-                g[m][c] = (te < TE) ? G[(size_t)te * KM + c] : zero<T>();
-            }
     }
     __syncthreads();
 
-    const bool vec_ok = a.aligned != 0;
-    for (int qb = q0 + wv * RB; qb < q1; qb += kWaves * RB) {
-        T x[RB][NEL];
-        // Load RB rows.
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int q = qb + r;
-            const T *row = M + (size_t)q * n;
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                const int j0 = ch * V * LRX_WAVE + lane * V;
-                T tmp[V];
-                if (q < q1 && vec_ok && j0 + V <= n) {
-                    ld16<T>(row + j0, tmp);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) tmp[v] = (q < q1 && j0 + v < n) ? row[j0 + v] : zero<T>();
-                }
-#pragma unroll
-                for (int v = 0; v < V; ++v) x[r][ch * V + v] = tmp[v];
-            }
-        }
-        // w[r][c] = M[q_r,:] . u_c  (minus the delayed-slot correction)
-        T p[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) p[i] = zero<T>();
-#pragma unroll
-        for (int c = 0; c < KM; ++c) {
-            if (c < k) {
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    T uv[V];
-                    ld16<T>(s_u + (size_t)c * npad + ch * V * LRX_WAVE + lane * V, uv);
-#pragma unroll
-                    for (int r = 0; r < RB; ++r)
-#pragma unroll
-                        for (int v = 0; v < V; ++v) p[r * KM + c] = fmac(x[r][ch * V + v], uv[v], p[r * KM + c]);
-                }
-            }
-        }
-        if (DELAYED) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const int q = qb + r;
-                if (q >= q1) continue;
-#pragma unroll
-                for (int m = 0; m < MG; ++m) {
-                    const int te = lane + m * LRX_WAVE;
-                    if (te < TE) {
-                        const T bv = fb[(size_t)q * KK + te];
-#pragma unroll
-                        for (int c = 0; c < KM; ++c) p[r * KM + c] = fmsc(bv, g[m][c], p[r * KM + c]);
-                    }
-                }
-            }
-        }
-        T tot = wave_sum_multi<T, NV>(p);
-        if (lane < NV) s_w[wv * NV + lane] = tot;
-        __builtin_amdgcn_wave_barrier();
-        // z[r] = R^-1 w[r]
-        T z[RB][KM];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int c = 0; c < KM; ++c) {
-                T s = zero<T>();
-#pragma unroll
-                for (int d = 0; d < KM; ++d)
-                    if (c < k && d < k) s = fmac(s_ri[c * KM + d], s_w[wv * NV + r * KM + d], s);
-                z[r][c] = s;
-            }
-        __builtin_amdgcn_wave_barrier();
-        if (!DELAYED) {
-            // M[q,:] -= sum_c z[c] C[:, c]^T
-#pragma unroll
-            for (int c = 0; c < KM; ++c) {
-                if (c < k) {
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch) {
-                        T cv[V];
-                        ld16<T>(s_c + (size_t)c * npad + ch * V * LRX_WAVE + lane * V, cv);
-#pragma unroll
-                        for (int r = 0; r < RB; ++r)
-#pragma unroll
-                            for (int v = 0; v < V; ++v) x[r][ch * V + v] = fmsc(z[r][c], cv[v], x[r][ch * V + v]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const int q = qb + r;
-                if (q >= q1) continue;
-                T *row = M + (size_t)q * n;
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    const int j0 = ch * V * LRX_WAVE + lane * V;
-                    T tmp[V];
-#pragma unroll
-                    for (int v = 0; v < V; ++v) tmp[v] = x[r][ch * V + v];
-                    if (vec_ok && j0 + V <= n) {
-                        st16<T>(row + j0, tmp);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < V; ++v) if (j0 + v < n) row[j0 + v] = tmp[v];
-                    }
-                }
-            }
-        } else {
-            // b_tau[q][c] = z[c]
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const int q = qb + r;
-                if (q < q1) {
-#pragma unroll
-                    for (int c = 0; c < KM; ++c)
-                        if (lane == c) fb[(size_t)q * KK + tau * KM + c] = z[r][c];
-                }
-            }
-        }
+    AcceptCtx<T> ctx{M, fa, fb, G, s_u, s_c, s_ri, n, KK, tau, TE, q0, q1, npad, wv, lane, a.aligned != 0};
+    if (kc == 1) {
+        accept_rows<T, 1, KM, NEL, RB, MG, DELAYED>(ctx);
+    } else if (kc == 2) {
+        if constexpr (KM >= 2) accept_rows<T, 2, KM, NEL, RB, MG, DELAYED>(ctx);
+    } else if (kc == 4) {
+        if constexpr (KM >= 4) accept_rows<T, 4, KM, NEL, RB, MG, DELAYED>(ctx);
+    } else {
+        if constexpr (KM >= 8) accept_rows<T, 8, KM, NEL, RB, MG, DELAYED>(ctx);
     }
 }
 
 // ------------------------------------------------------------------ Metropolis
-// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0..c3), key
-// (k0, k1), ten rounds of two 32x32->64 multiplies with a Weyl key schedule.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint64_t p0 = (uint64_t)M0 * c[0];
-        uint64_t p1 = (uint64_t)M1 * c[2];
-        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
-        k0 += W0; k1 += W1;
-    }
-}
-
-__device__ __forceinline__ double abs2_wide(double r) { return r * r; }
-__device__ __forceinline__ double abs2_wide(cf64 r) { return r.x * r.x + r.y * r.y; }
-
 template <class Wd>
 __global__ void metropolis_kernel(int W, const Wd *ratio, const double *u01, uint64_t seed,
                                   uint64_t counter, int mode, const uint32_t *flags, uint8_t *accept) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= W) return;
-    const Wd r = ratio[w];
-    const double p = abs2_wide(r);
-    bool ok = flags[w] == 0 && isfinite(p) && p > 0.0;
-    uint8_t acc = 0;
-    if (ok) {
-        if (mode == LRX_MH_FORCE) {
-            acc = 1;
-        } else {
-            double uu;
-            if (mode == LRX_MH_UNIFORMS) {
-                uu = u01[w];
-            } else {
-                uint32_t c[4] = {(uint32_t)w, (uint32_t)counter, (uint32_t)(counter >> 32), 0u};
-                philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-                uint64_t bits = ((uint64_t)(c[0] >> 5) << 26) | (uint64_t)(c[1] >> 6);  // 53 bits
-                uu = (double)bits * 0x1.0p-53;
-            }
-            acc = uu < fmin(1.0, p) ? 1 : 0;
-        }
-    }
-    accept[w] = acc;
+    accept[w] = mh_decide<Wd>(ratio[w], flags[w], mode, mode == LRX_MH_UNIFORMS ? u01[w] : 0.0, seed, counter,
+                              (uint32_t)w);
 }
 
 __global__ void hop_commit_kernel(int W, int n, int n_empty, int KM, const int32_t *k, const int32_t *elec,
@@ -483,19 +566,39 @@ template <class T> hipError_t build_hop_t(const HopArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class T, int KM> hipError_t propose_t(const StepArgs &a, hipStream_t s) {
+template <class T, int KM, int NW, int NI> hipError_t propose_t(const StepArgs &a, hipStream_t s) {
     const int TE = a.tau * KM;
-    size_t lds = sizeof(T) * ((size_t)KM * TE + (size_t)kWaves * KM * KM);
-    hipLaunchKernelGGL((det_propose_kernel<T, KM>), dim3(a.W), dim3(kThreads), lds, s, a);
+    size_t lds = sizeof(T) * ((size_t)KM * TE + (size_t)NW * 64) + sizeof(int) * ((size_t)TE + a.tau);
+    hipLaunchKernelGGL((det_propose_kernel<T, KM, NW, NI>), dim3(a.W), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
+}
+
+// One wave per walker while the per-thread column slices (2 NI KM values) fit
+// in about 64 VGPRs; otherwise four waves.
+template <class T, int KM> hipError_t propose_n(const StepArgs &a, hipStream_t s) {
+    const int ni1 = (a.n + 63) / 64;
+    if ((size_t)ni1 * KM * sizeof(T) <= 128) {
+        if (ni1 <= 1) return propose_t<T, KM, 1, 1>(a, s);
+        if (ni1 <= 2) return propose_t<T, KM, 1, 2>(a, s);
+        if constexpr (KM * sizeof(T) <= 32) { if (ni1 <= 4) return propose_t<T, KM, 1, 4>(a, s); }
+        if constexpr (KM * sizeof(T) <= 16) { if (ni1 <= 8) return propose_t<T, KM, 1, 8>(a, s); }
+        if constexpr (KM * sizeof(T) <= 8) { if (ni1 <= 16) return propose_t<T, KM, 1, 16>(a, s); }
+    }
+    const int ni4 = (a.n + 255) / 256;
+    if (ni4 <= 1) return propose_t<T, KM, 4, 1>(a, s);
+    if constexpr (KM * sizeof(T) <= 64) {   // larger panels imply n <= 256 (LDS rule of the C ABI)
+        if (ni4 <= 2) return propose_t<T, KM, 4, 2>(a, s);
+        return propose_t<T, KM, 4, 4>(a, s);   // n <= LRX_MAX_N = 1024
+    }
+    return hipErrorInvalidValue;
 }
 
 template <class T> hipError_t propose_k(const StepArgs &a, hipStream_t s) {
     switch (a.KM) {
-        case 1: return propose_t<T, 1>(a, s);
-        case 2: return propose_t<T, 2>(a, s);
-        case 4: return propose_t<T, 4>(a, s);
-        case 8: return propose_t<T, 8>(a, s);
+        case 1: return propose_n<T, 1>(a, s);
+        case 2: return propose_n<T, 2>(a, s);
+        case 4: return propose_n<T, 4>(a, s);
+        case 8: return propose_n<T, 8>(a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -508,6 +611,10 @@ template <class T, int NEL, int KM> constexpr int rows_per_batch() {
 }
 
 template <class T, int KM, int NEL, bool D> hipError_t accept_t(const StepArgs &a, hipStream_t s) {
+    // u and C panels must fit the 64 KiB the C ABI allows (lrx_state_sizes rejects larger shapes)
+    if constexpr (2 * KM * NEL * LRX_WAVE * sizeof(T) > 65536) {
+        return hipErrorInvalidValue;
+    } else {
     constexpr int RB = rows_per_batch<T, NEL, KM>();
     // Rows per block: enough blocks to fill 256 CUs several times over.
     const int n = a.n;
@@ -519,10 +626,14 @@ template <class T, int KM, int NEL, bool D> hipError_t accept_t(const StepArgs &
     }
     const int bpw = (n + rpb - 1) / rpb;
     const int npad = (NEL / vec16<T>()) * vec16<T>() * LRX_WAVE;
-    size_t lds = sizeof(T) * ((size_t)2 * KM * npad + KM * KM + (size_t)kWaves * RB * KM);
-    hipLaunchKernelGGL((det_accept_kernel<T, KM, NEL, RB, D>), dim3((unsigned)(a.W * bpw)), dim3(kThreads),
-                       lds, s, a, rpb, bpw);
+    size_t lds = sizeof(T) * ((size_t)2 * KM * npad + KM * KM);
+    const dim3 grid((unsigned)(a.W * bpw)), block(kThreads);
+    if (!D || a.K * KM <= LRX_WAVE)   // one slot column per lane
+        hipLaunchKernelGGL((det_accept_kernel<T, KM, NEL, RB, 1, D>), grid, block, lds, s, a, rpb, bpw);
+    else
+        hipLaunchKernelGGL((det_accept_kernel<T, KM, NEL, RB, 4, D>), grid, block, lds, s, a, rpb, bpw);
     return hipGetLastError();
+    }
 }
 
 template <class T, int KM, bool D> hipError_t accept_n(const StepArgs &a, hipStream_t s) {
@@ -553,38 +664,33 @@ template <class T> hipError_t accept_d(const StepArgs &a, hipStream_t s) {
 
 }  // namespace
 
+// One object per bulk dtype (LRX_DT = 0..3, set by the build), so the four
+// instantiation sets compile in parallel.  Metropolis and occupancy commit are
+// dtype independent and live in the LRX_DT = 0 object.
+#if !defined(LRX_DT)
+#error "compile lrx_det.hip with -DLRX_DT=0..3"
+#endif
+#if LRX_DT == 0
+using TT = float;
+#define LRX_SFX(x) x##_f32
+#elif LRX_DT == 1
+using TT = double;
+#define LRX_SFX(x) x##_f64
+#elif LRX_DT == 2
+using TT = cf32;
+#define LRX_SFX(x) x##_c64
+#else
+using TT = cf64;
+#define LRX_SFX(x) x##_c128
+#endif
+
 namespace lrx {
 
-hipError_t det_build_hop(int dtype, const HopArgs &a, hipStream_t s) {
-    switch (dtype) {
-        case LRX_F32: return build_hop_t<float>(a, s);
-        case LRX_F64: return build_hop_t<double>(a, s);
-        case LRX_C64: return build_hop_t<cf32>(a, s);
-        case LRX_C128: return build_hop_t<cf64>(a, s);
-    }
-    return hipErrorInvalidValue;
-}
+hipError_t LRX_SFX(det_build_hop)(const HopArgs &a, hipStream_t s) { return build_hop_t<TT>(a, s); }
+hipError_t LRX_SFX(det_propose)(const StepArgs &a, hipStream_t s) { return propose_k<TT>(a, s); }
+hipError_t LRX_SFX(det_accept)(const StepArgs &a, hipStream_t s) { return accept_d<TT>(a, s); }
 
-hipError_t det_propose(int dtype, const StepArgs &a, hipStream_t s) {
-    switch (dtype) {
-        case LRX_F32: return propose_k<float>(a, s);
-        case LRX_F64: return propose_k<double>(a, s);
-        case LRX_C64: return propose_k<cf32>(a, s);
-        case LRX_C128: return propose_k<cf64>(a, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t det_accept(int dtype, const StepArgs &a, hipStream_t s) {
-    switch (dtype) {
-        case LRX_F32: return accept_d<float>(a, s);
-        case LRX_F64: return accept_d<double>(a, s);
-        case LRX_C64: return accept_d<cf32>(a, s);
-        case LRX_C128: return accept_d<cf64>(a, s);
-    }
-    return hipErrorInvalidValue;
-}
-
+#if LRX_DT == 0
 hipError_t metropolis(int dtype, int W, const void *ratio, const double *u01, uint64_t seed,
                       uint64_t counter, int mode, const uint32_t *flags, uint8_t *accept, hipStream_t s) {
     dim3 grid((W + 255) / 256), block(256);
@@ -604,5 +710,6 @@ hipError_t hop_commit(int W, int n, int n_empty, int KM, const int32_t *k, const
                        slot, accept, occ, empty);
     return hipGetLastError();
 }
+#endif
 
 }  // namespace lrx

@@ -50,9 +50,10 @@ struct WorkLayout {
 };
 
 inline int panel_nb(int n, size_t ws) {
-    // Largest power of two <= 32 with n * nb * ws <= 64 KiB of LDS.
+    // Largest power of two <= 32 whose padded panel (n x (nb+1)) plus the two
+    // nb x nb triangular inverses fit in 96 KiB of LDS.
     int nb = 32;
-    while (nb > 1 && (size_t)n * nb * ws > 65536) nb >>= 1;
+    while (nb > 1 && ((size_t)n * (nb + 1) + 2 * (size_t)nb * nb) * ws > 98304) nb >>= 1;
     return nb;
 }
 
@@ -276,13 +277,14 @@ __global__ __launch_bounds__(kT) void gj_panel_kernel(FA a, int j0, int nb) {
     Wd *Z = wZ<Wd>(a, w);
     int *piv = wPiv(a, w);
     DetAcc *d = wAcc(a, w);
-    Wd *sP = reinterpret_cast<Wd *>(smem);            // [m][nb]
-    Wd *sLinv = sP + (size_t)m * nb;                   // [nb][nb]
+    const int ps = nb + 1;                             // padded row stride (bank spread)
+    Wd *sP = reinterpret_cast<Wd *>(smem);            // [m][ps]
+    Wd *sLinv = sP + (size_t)m * ps;                   // [nb][nb]
     Wd *sYinv = sLinv + nb * nb;                       // [nb][nb]
 
     for (int idx = threadIdx.x; idx < m * nb; idx += kT) {
         const int i = idx / nb, c = idx - i * nb;
-        sP[idx] = X[(size_t)(j0 + i) * n + j0 + c];
+        sP[i * ps + c] = X[(size_t)(j0 + i) * n + j0 + c];
     }
     __syncthreads();
     double la = 0.0;
@@ -292,28 +294,28 @@ __global__ __launch_bounds__(kT) void gj_panel_kernel(FA a, int j0, int nb) {
         double bv = -1.0;
         int bi = -1;
         for (int i = c + threadIdx.x; i < m; i += kT) {
-            double v = absv(sP[i * nb + c]);
+            double v = absv(sP[i * ps + c]);
             if (bi < 0 || v > bv) { bv = v; bi = i; }
         }
         const int p = block_argmax(bv, bi, s_val, s_idx);
         if (p != c) {
             for (int cc = threadIdx.x; cc < nb; cc += kT) {
-                Wd t = sP[c * nb + cc];
-                sP[c * nb + cc] = sP[p * nb + cc];
-                sP[p * nb + cc] = t;
+                Wd t = sP[c * ps + cc];
+                sP[c * ps + cc] = sP[p * ps + cc];
+                sP[p * ps + cc] = t;
             }
             ph = -ph;
         }
         if (threadIdx.x == 0) piv[j0 + c] = j0 + p;
         __syncthreads();
-        const Wd pv = sP[c * nb + c];
+        const Wd pv = sP[c * ps + c];
         if (is_zero(pv)) { sing = true; continue; }
         la += log(absv(pv));
         ph = ph * unit(pv);
         for (int i = c + 1 + threadIdx.x; i < m; i += kT) {
-            const Wd l = divv(sP[i * nb + c], pv);
-            sP[i * nb + c] = l;
-            for (int cc = c + 1; cc < nb; ++cc) sP[i * nb + cc] = fmsc(l, sP[c * nb + cc], sP[i * nb + cc]);
+            const Wd l = divv(sP[i * ps + c], pv);
+            sP[i * ps + c] = l;
+            for (int cc = c + 1; cc < nb; ++cc) sP[i * ps + cc] = fmsc(l, sP[c * ps + cc], sP[i * ps + cc]);
         }
         __syncthreads();
     }
@@ -329,13 +331,13 @@ __global__ __launch_bounds__(kT) void gj_panel_kernel(FA a, int j0, int nb) {
         const int e = threadIdx.x;
         for (int r = 0; r < nb; ++r) {
             Wd s = (r == e) ? one<Wd>() : zero<Wd>();
-            for (int q = 0; q < r; ++q) s = fmsc(sP[r * nb + q], sLinv[q * nb + e], s);
+            for (int q = 0; q < r; ++q) s = fmsc(sP[r * ps + q], sLinv[q * nb + e], s);
             sLinv[r * nb + e] = s;
         }
         for (int r = nb - 1; r >= 0; --r) {
             Wd s = sLinv[r * nb + e];
-            for (int q = r + 1; q < nb; ++q) s = fmsc(sP[r * nb + q], sYinv[q * nb + e], s);
-            const Wd dg = sP[r * nb + r];
+            for (int q = r + 1; q < nb; ++q) s = fmsc(sP[r * ps + q], sYinv[q * nb + e], s);
+            const Wd dg = sP[r * ps + r];
             sYinv[r * nb + e] = is_zero(dg) ? zero<Wd>() : divv(s, dg);
         }
     }
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(kT) void gj_panel_kernel(FA a, int j0, int nb) {
                 if (c < nb) z[c] = sYinv[(i - j0) * nb + c] - ((i - j0 == c) ? one<Wd>() : zero<Wd>());
         } else {
             for (int q = 0; q < nb; ++q) {
-                const Wd lq = sP[(i - j0) * nb + q];
+                const Wd lq = sP[(i - j0) * ps + q];
 #pragma unroll
                 for (int c = 0; c < NB; ++c) if (c < nb) z[c] = fmsc(lq, sLinv[q * nb + c], z[c]);
             }
@@ -374,21 +376,29 @@ __global__ __launch_bounds__(kT) void gj_panel_kernel(FA a, int j0, int nb) {
 
 // ------------------------------------------------------------------ GJ update
 // Every column outside the panel: X_new[i] = X_old[pi(i)] + Z[i] . X_old[pi(P)].
-// One work-group owns a block of CB columns for all rows, so the row
-// permutation stays inside the block.
-template <class Wd, int ROWS, int CB>
+// A work-group owns 64 of those columns (one per lane) for all rows.  Rows
+// moved by the panel's pivoting (at most 2 nb) and the pivot rows are staged
+// in LDS first, so every other row is read and written in place by one lane.
+// Z[i][:] is wave-uniform and is read through the scalar cache.
+template <class Wd, int NB>
 __global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int ncb) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int w = lb / ncb, cb = lb - w * ncb;
     if (w >= a.W) return;
     const int n = a.n, others = n - nb;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Wd *X = wX<Wd>(a, w);
     const Wd *Z = wZ<Wd>(a, w);
     const int *piv = wPiv(a, w);
-    int *perm = reinterpret_cast<int *>(smem);                   // [n]
-    Wd *sXP = reinterpret_cast<Wd *>(smem + ((n * 4 + 15) / 16) * 16);   // [nb][CB]
-    for (int i = threadIdx.x; i < n; i += kT) perm[i] = i;
+    int *perm = reinterpret_cast<int *>(smem);                         // [n]
+    int *sslot = perm + n;                                             // [n]
+    int *s_cnt = sslot + n;                                            // [1]
+    Wd *sXP = reinterpret_cast<Wd *>(smem + (((2 * n + 1) * 4 + 15) / 16) * 16);   // [nb][64]
+    Wd *sS = sXP + (size_t)nb * 64;                                    // [2 nb][64]
+    for (int i = threadIdx.x; i < n; i += kT) { perm[i] = i; sslot[i] = -1; }
+    if (threadIdx.x == 0) *s_cnt = 0;
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int c = 0; c < nb; ++c) {
@@ -397,66 +407,74 @@ __global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int
         }
     }
     __syncthreads();
-    const int x0 = cb * CB;
-    for (int idx = threadIdx.x; idx < nb * CB; idx += kT) {
-        const int c = idx / CB, x = idx - c * CB;
-        const int ci = x0 + x;
-        Wd v = zero<Wd>();
-        if (ci < others) {
-            const int col = ci < j0 ? ci : ci + nb;
-            v = X[(size_t)perm[j0 + c] * n + col];
-        }
-        sXP[idx] = v;
-    }
-    Wd old[ROWS][CB];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int i = threadIdx.x + r * kT;
-#pragma unroll
-        for (int x = 0; x < CB; ++x) {
-            const int ci = x0 + x;
-            Wd v = zero<Wd>();
-            if (i < n && ci < others) {
-                const int col = ci < j0 ? ci : ci + nb;
-                v = X[(size_t)perm[i] * n + col];
-            }
-            old[r][x] = v;
-        }
+    for (int i = j0 + threadIdx.x; i < n; i += kT)
+        if (perm[i] != i) sslot[i] = atomicAdd(s_cnt, 1);
+    __syncthreads();
+    const int ci = cb * 64 + lane;
+    const bool live = ci < others;
+    const int col = ci < j0 ? ci : ci + nb;
+    // pivot rows and moved rows, from the pre-update matrix
+    for (int c = wv; c < nb; c += kT / 64)
+        sXP[c * 64 + lane] = live ? X[(size_t)perm[j0 + c] * n + col] : zero<Wd>();
+    for (int i = j0 + wv; i < n; i += kT / 64) {
+        const int sl = sslot[i];
+        if (sl >= 0) sS[sl * 64 + lane] = live ? X[(size_t)perm[i] * n + col] : zero<Wd>();
     }
     __syncthreads();
+    Wd xp[NB];
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int i = threadIdx.x + r * kT;
-        if (i >= n) continue;
-        for (int c = 0; c < nb; ++c) {
-            const Wd zc = Z[(size_t)i * nb + c];
+    for (int c = 0; c < NB; ++c) xp[c] = (c < nb) ? sXP[c * 64 + lane] : zero<Wd>();
+    // Rows in chunks of 64: the chunk's Z rows are staged in LDS (read back as
+    // broadcasts), each wave issues its 16 row loads together.
+    Wd *sZ = sS + (size_t)2 * nb * 64;                                 // [64][nb]
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        __syncthreads();
+        const int rows = min(64, n - i0);
+        for (int idx = threadIdx.x; idx < rows * nb; idx += kT) sZ[idx] = Z[(size_t)i0 * nb + idx];
+        __syncthreads();
+        Wd v[16];
 #pragma unroll
-            for (int x = 0; x < CB; ++x) old[r][x] = fmac(zc, sXP[c * CB + x], old[r][x]);
+        for (int r = 0; r < 16; ++r) {
+            const int i = i0 + wv * 16 + r;
+            v[r] = zero<Wd>();
+            if (live && i < n) {
+                const int sl = sslot[i];
+                v[r] = sl >= 0 ? sS[sl * 64 + lane] : X[(size_t)i * n + col];
+            }
         }
 #pragma unroll
-        for (int x = 0; x < CB; ++x) {
-            const int ci = x0 + x;
-            if (ci < others) {
-                const int col = ci < j0 ? ci : ci + nb;
-                X[(size_t)i * n + col] = old[r][x];
-            }
+        for (int r = 0; r < 16; ++r) {
+            const Wd *zr = sZ + (wv * 16 + r) * nb;
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c < nb) v[r] = fmac(zr[c], xp[c], v[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = i0 + wv * 16 + r;
+            if (live && i < n) X[(size_t)i * n + col] = v[r];
         }
     }
 }
 
 // Column source of the final permutation: X (PB)^-1 -> B^-1 = X P, applied as
-// column swaps in reverse pivot order.
-__global__ void src_perm_kernel(FA a) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.W) return;
-    const int n = a.n;
+// column swaps in reverse pivot order (done in LDS by one thread per walker).
+__global__ __launch_bounds__(kT) void src_perm_kernel(FA a) {
+    extern __shared__ int s_src[];
+    const int w = blockIdx.x, n = a.n;
     int *src = wSrc(a, w);
     const int *piv = wPiv(a, w);
-    for (int c = 0; c < n; ++c) src[c] = c;
-    for (int kx = n - 1; kx >= 0; --kx) {
-        const int p = piv[kx];
-        const int t = src[kx]; src[kx] = src[p]; src[p] = t;
+    int *s_piv = s_src + n;
+    for (int c = threadIdx.x; c < n; c += kT) { s_src[c] = c; s_piv[c] = piv[c]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int kx = n - 1; kx >= 0; --kx) {
+            const int p = s_piv[kx];
+            const int t = s_src[kx]; s_src[kx] = s_src[p]; s_src[p] = t;
+        }
     }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += kT) src[c] = s_src[c];
 }
 
 // ------------------------------------------------------------------ final
@@ -464,12 +482,16 @@ __global__ void src_perm_kernel(FA a) {
 template <class T, class Wd>
 __global__ __launch_bounds__(kT) void final_det_kernel(FA a, int rows_per_block, int bpw) {
     __shared__ double s_d[kT / 64], s_nrm[kT / 64];
+    extern __shared__ int s_src[];
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int w = lb / bpw, rb = lb - w * bpw;
     if (w >= a.W) return;
     const int n = a.n;
     const Wd *X = wX<Wd>(a, w);
-    const int *src = wSrc(a, w);
+    const int *gsrc = wSrc(a, w);
+    for (int c = threadIdx.x; c < n; c += kT) s_src[c] = gsrc[c];
+    __syncthreads();
+    const int *src = s_src;
     T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
     double dsq = 0.0, nsq = 0.0;
     const int q0 = rb * rows_per_block, q1 = min(n, q0 + rows_per_block);
@@ -587,15 +609,21 @@ __global__ void finish_kernel(FA a) {
     a.flags[w] = bad ? LRX_FLAG_SINGULAR_A : 0u;
 }
 
-template <class Wd, int ROWS>
+template <class Wd>
 hipError_t launch_update(const FA &fa, int j0, int nb, hipStream_t s) {
-    constexpr int CB = (sizeof(Wd) == 8 ? 32 : 16) / ROWS;
     const int others = fa.n - nb;
     if (others <= 0) return hipSuccess;
-    const int ncb = (others + CB - 1) / CB;
-    const size_t lds = ((fa.n * 4 + 15) / 16) * 16 + sizeof(Wd) * (size_t)nb * CB;
-    hipLaunchKernelGGL((gj_update_kernel<Wd, ROWS, CB>), dim3((unsigned)(fa.W * ncb)), dim3(kT), lds, s, fa, j0,
-                       nb, ncb);
+    const int ncb = (others + 63) / 64;
+    const size_t lds = (((2 * fa.n + 1) * 4 + 15) / 16) * 16 + sizeof(Wd) * (size_t)4 * nb * 64;
+    const dim3 grid((unsigned)(fa.W * ncb)), block(kT);
+    switch (fa.nb) {
+        case 32: hipLaunchKernelGGL((gj_update_kernel<Wd, 32>), grid, block, lds, s, fa, j0, nb, ncb); break;
+        case 16: hipLaunchKernelGGL((gj_update_kernel<Wd, 16>), grid, block, lds, s, fa, j0, nb, ncb); break;
+        case 8: hipLaunchKernelGGL((gj_update_kernel<Wd, 8>), grid, block, lds, s, fa, j0, nb, ncb); break;
+        case 4: hipLaunchKernelGGL((gj_update_kernel<Wd, 4>), grid, block, lds, s, fa, j0, nb, ncb); break;
+        case 2: hipLaunchKernelGGL((gj_update_kernel<Wd, 2>), grid, block, lds, s, fa, j0, nb, ncb); break;
+        default: hipLaunchKernelGGL((gj_update_kernel<Wd, 1>), grid, block, lds, s, fa, j0, nb, ncb); break;
+    }
     return hipGetLastError();
 }
 
@@ -622,7 +650,7 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int j0 = 0; j0 < n; j0 += a.nb) {
         const int nb = min(a.nb, n - j0);
-        const size_t lds = sizeof(Wd) * ((size_t)(n - j0) * nb + 2 * (size_t)nb * nb);
+        const size_t lds = sizeof(Wd) * ((size_t)(n - j0) * (nb + 1) + 2 * (size_t)nb * nb);
         switch (a.nb) {
             case 32: hipLaunchKernelGGL((gj_panel_kernel<Wd, 32>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
             case 16: hipLaunchKernelGGL((gj_panel_kernel<Wd, 16>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
@@ -631,16 +659,15 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
             case 2: hipLaunchKernelGGL((gj_panel_kernel<Wd, 2>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
             default: hipLaunchKernelGGL((gj_panel_kernel<Wd, 1>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
         }
-        if (n <= 256) e = launch_update<Wd, 1>(a, j0, nb, s);
-        else if (n <= 512) e = launch_update<Wd, 2>(a, j0, nb, s);
-        else e = launch_update<Wd, 4>(a, j0, nb, s);
+        e = launch_update<Wd>(a, j0, nb, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(src_perm_kernel, dim3((W + 63) / 64), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(src_perm_kernel, dim3(W), dim3(kT), sizeof(int) * 2 * (size_t)n, s, a);
     if (a.kind == LRX_DET) {
         const int rpb = 8;
         const int bpw = (n + rpb - 1) / rpb;
-        hipLaunchKernelGGL((final_det_kernel<T, Wd>), dim3((unsigned)(W * bpw)), dim3(kT), 0, s, a, rpb, bpw);
+        hipLaunchKernelGGL((final_det_kernel<T, Wd>), dim3((unsigned)(W * bpw)), dim3(kT), sizeof(int) * (size_t)n, s,
+                           a, rpb, bpw);
     } else {
         const int pairs = tiles * (tiles + 1) / 2;
         hipLaunchKernelGGL((final_pf_kernel<T, Wd>), dim3((unsigned)(W * pairs)), dim3(kT), 0, s, a, tiles);

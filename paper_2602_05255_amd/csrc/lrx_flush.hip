@@ -70,10 +70,19 @@ __device__ __forceinline__ void mac(T a, T b, typename Acc<typename Real<T>::typ
 }
 
 // ------------------------------------------------------------------ DET
+// Panels are staged in LDS in chunks of 256 bytes of slot columns per row
+// (32 KiB of LDS per work-group for every dtype) with coalesced 16-byte loads;
+// rows are padded by one element to spread the fragment reads over the banks.
 template <class T>
 __global__ __launch_bounds__(256) void det_flush_kernel(StepArgs a, int tiles_per_dim) {
     using R = typename Real<T>::type;
     using A4 = typename Acc<R>::type;
+    constexpr int V = vec16<T>();
+    constexpr int kChunk = 256 / (int)sizeof(T);
+    constexpr int SB = kChunk + 1;        // padded stride of the b panel rows
+    constexpr int SA = 64 + 1;            // padded stride of the a panel rows
+    __shared__ T s_b[64 * SB];            // b rows q0..q0+63, slot columns of the chunk
+    __shared__ T s_a[kChunk * SA];        // a columns (slot te) over j0..j0+63
     const int n = a.n, KM = a.KM, KK = a.K * KM, TE = a.tau * KM;
     const int tiles = tiles_per_dim * tiles_per_dim;
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -81,18 +90,16 @@ __global__ __launch_bounds__(256) void det_flush_kernel(StepArgs a, int tiles_pe
     if (w >= a.W) return;
     const int tile = lb - w * tiles;
     const int ti = tile / tiles_per_dim, tj = tile - ti * tiles_per_dim;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int qa = ti * 64 + wv * 16 + (lane & 15);        // A-fragment row
-    const int kq = lane >> 4;                              // inner index within a step
-    const int j0 = tj * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int q0 = ti * 64, j0 = tj * 64;
+    const int kq = lane >> 4;                 // inner index within a 4-deep step
 
     T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
     const T *fa = static_cast<const T *>(a.fa) + (size_t)w * KK * n;
     const T *fb = static_cast<const T *>(a.fb) + (size_t)w * n * KK;
 
     A4 re[4], im[4];
-    // Accumulators start from M0 (lane holds column lane%16 of rows acc_row(lane, r)).
-    const int rbase = ti * 64 + wv * 16;
+    const int rbase = q0 + wv * 16;
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
         const int j = j0 + jb * 16 + (lane & 15);
@@ -104,17 +111,48 @@ __global__ __launch_bounds__(256) void det_flush_kernel(StepArgs a, int tiles_pe
             im[jb][r] = im_(v);
         }
     }
-    for (int te0 = 0; te0 < TE; te0 += 4) {
-        const int te = te0 + kq;
-        const bool tin = te < TE;
-        // -b (so that acc += (-b) a^T accumulates M0 - B A^T)
-        T bv = (tin && qa < n) ? fb[(size_t)qa * KK + te] : zero<T>();
-        bv = make_<T>(-re_(bv), -im_(bv));
+    const bool vec_b = (KK % V) == 0;         // b rows start on 16-byte boundaries
+    const bool vec_a = (n % V) == 0;
+    for (int c0 = 0; c0 < TE; c0 += kChunk) {
+        const int cw = min(kChunk, TE - c0);
+        __syncthreads();
+        // b panel: 64 rows x cw slot columns (row-contiguous in fb)
+        for (int idx = tid; idx < 64 * (kChunk / V); idx += 256) {
+            const int r = idx / (kChunk / V), cv = (idx - r * (kChunk / V)) * V;
+            const int q = q0 + r;
+            T tmp[V];
+            if (q < n && vec_b && cv + V <= cw) {
+                ld16<T>(fb + (size_t)q * KK + c0 + cv, tmp);
+            } else {
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const int j = j0 + jb * 16 + (lane & 15);
-            T av = (tin && j < n) ? fa[(size_t)te * n + j] : zero<T>();
-            mac<T>(bv, av, re[jb], im[jb]);
+                for (int v = 0; v < V; ++v) tmp[v] = (q < n && cv + v < cw) ? fb[(size_t)q * KK + c0 + cv + v] : zero<T>();
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) s_b[r * SB + cv + v] = tmp[v];
+        }
+        // a panel: cw slot columns x 64 (column-contiguous in fa)
+        for (int idx = tid; idx < kChunk * (64 / V); idx += 256) {
+            const int t = idx / (64 / V), jv = (idx - t * (64 / V)) * V;
+            const int j = j0 + jv;
+            T tmp[V];
+            if (t < cw && vec_a && j + V <= n) {
+                ld16<T>(fa + (size_t)(c0 + t) * n + j, tmp);
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) tmp[v] = (t < cw && j + v < n) ? fa[(size_t)(c0 + t) * n + j + v] : zero<T>();
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) s_a[t * SA + jv + v] = tmp[v];
+        }
+        __syncthreads();
+        for (int t0 = 0; t0 < cw; t0 += 4) {
+            T bv = s_b[(wv * 16 + (lane & 15)) * SB + t0 + kq];
+            bv = make_<T>(-re_(bv), -im_(bv));      // acc += (-b) a^T accumulates M0 - B A^T
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const T av = s_a[(t0 + kq) * SA + jb * 16 + (lane & 15)];
+                mac<T>(bv, av, re[jb], im[jb]);
+            }
         }
     }
 #pragma unroll

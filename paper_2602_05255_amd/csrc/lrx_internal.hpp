@@ -43,6 +43,17 @@ struct StepArgs {
     void *phase;
     uint32_t *flags;
     void *ratio;
+    // Optional fusions.  propose: build the hop vectors in the same launch
+    // (hop_table != NULL: u = table[s'] - table[s], written to u).  accept:
+    // take the Metropolis decision and commit the occupancy in the same
+    // launch (mh_mode >= 0; otherwise `accept` holds the caller's decision).
+    const void *hop_table;
+    int sites, n_empty;
+    int32_t *occ, *empty;
+    const int32_t *slot;
+    int mh_mode;
+    const double *u01;
+    uint64_t seed, counter;
 };
 
 struct HopArgs {
@@ -53,10 +64,29 @@ struct HopArgs {
     uint32_t *flags;
 };
 
-// Determinant kernels (lrx_det.hip).
-hipError_t det_build_hop(int dtype, const HopArgs &a, hipStream_t s);
-hipError_t det_propose(int dtype, const StepArgs &a, hipStream_t s);
-hipError_t det_accept(int dtype, const StepArgs &a, hipStream_t s);
+// Determinant kernels (lrx_det.hip, one object per bulk dtype).
+#define LRX_DECL_DET(sfx)                                                    \
+    hipError_t det_build_hop_##sfx(const HopArgs &a, hipStream_t s);        \
+    hipError_t det_propose_##sfx(const StepArgs &a, hipStream_t s);         \
+    hipError_t det_accept_##sfx(const StepArgs &a, hipStream_t s);
+LRX_DECL_DET(f32)
+LRX_DECL_DET(f64)
+LRX_DECL_DET(c64)
+LRX_DECL_DET(c128)
+#undef LRX_DECL_DET
+
+#define LRX_DISPATCH(fn, dtype, ...)                                         \
+    switch (dtype) {                                                         \
+        case LRX_F32: return fn##_f32(__VA_ARGS__);                          \
+        case LRX_F64: return fn##_f64(__VA_ARGS__);                          \
+        case LRX_C64: return fn##_c64(__VA_ARGS__);                          \
+        case LRX_C128: return fn##_c128(__VA_ARGS__);                        \
+    }                                                                        \
+    return hipErrorInvalidValue;
+
+inline hipError_t det_build_hop(int dtype, const HopArgs &a, hipStream_t s) { LRX_DISPATCH(det_build_hop, dtype, a, s) }
+inline hipError_t det_propose(int dtype, const StepArgs &a, hipStream_t s) { LRX_DISPATCH(det_propose, dtype, a, s) }
+inline hipError_t det_accept(int dtype, const StepArgs &a, hipStream_t s) { LRX_DISPATCH(det_accept, dtype, a, s) }
 
 // Pfaffian kernels (lrx_pf.hip).
 hipError_t pf_build_hop(int dtype, const HopArgs &a, hipStream_t s);

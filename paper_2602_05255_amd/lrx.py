@@ -68,6 +68,9 @@ _SIGS = {
     "lrx_det_propose_ratio": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _P], ctypes.c_int),
     "lrx_det_accept_update": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _P], ctypes.c_int),
     "lrx_det_flush_delayed": ([ctypes.POINTER(lrx_state), _P], ctypes.c_int),
+    "lrx_det_propose_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_det_accept_hop": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _I, _P, ctypes.c_uint64, ctypes.c_uint64,
+                            _P, _P, _P, _I, _P], ctypes.c_int),
     "lrx_pf_init_inverse": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P], ctypes.c_int),
     "lrx_pf_refresh": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _P], ctypes.c_int),
     "lrx_pf_build_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -228,6 +231,34 @@ def lrx_det_accept_update(st: State, k, rows, u, accept, stream=None):
     _dev(accept, "accept", torch.uint8, (st.walkers,))
     _check(_lib.lrx_det_accept_update(st.ptr(), _dev(k, "k"), _dev(rows, "rows"), _dev(u, "u"),
                                       _dev(accept, "accept"), _stream(stream)), "lrx_det_accept_update")
+
+
+def lrx_det_propose_hop(st: State, phi, sites, occ, empty, n_empty, k, elec, slot, u, ratio, stream=None):
+    _dev(occ, "occ", torch.int32, (st.walkers, st.n))
+    _dev(empty, "empty", torch.int32, (st.walkers, n_empty))
+    _kvec(st, k, elec, "elec")
+    _dev(slot, "slot", torch.int32, (st.walkers, st.k_max))
+    _dev(u, "u", st.dtype, (st.walkers, st.k_max, st.n))
+    _dev(ratio, "ratio", st.wide, (st.walkers,))
+    _check(_lib.lrx_det_propose_hop(st.ptr(), _dev(phi, "phi", st.wide), int(sites), _dev(occ, "occ"),
+                                    _dev(empty, "empty"), int(n_empty), _dev(k, "k"), _dev(elec, "elec"),
+                                    _dev(slot, "slot"), _dev(u, "u"), _dev(ratio, "ratio"), _stream(stream)),
+           "lrx_det_propose_hop")
+
+
+def lrx_det_accept_hop(st: State, k, elec, slot, u, mode, u01, seed, counter, accept, occ, empty, n_empty,
+                       stream=None):
+    _kvec(st, k, elec, "elec")
+    _dev(slot, "slot", torch.int32, (st.walkers, st.k_max))
+    _dev(u, "u", st.dtype, (st.walkers, st.k_max, st.n))
+    pu = _dev(u01, "u01", torch.float64, (st.walkers,), allow_none=True)
+    _dev(accept, "accept", torch.uint8, (st.walkers,))
+    _dev(occ, "occ", torch.int32, (st.walkers, st.n))
+    _dev(empty, "empty", torch.int32, (st.walkers, n_empty))
+    _check(_lib.lrx_det_accept_hop(st.ptr(), _dev(k, "k"), _dev(elec, "elec"), _dev(slot, "slot"), _dev(u, "u"),
+                                   int(mode), pu, ctypes.c_uint64(seed), ctypes.c_uint64(counter),
+                                   _dev(accept, "accept"), _dev(occ, "occ"), _dev(empty, "empty"), int(n_empty),
+                                   _stream(stream)), "lrx_det_accept_hop")
 
 
 def lrx_det_flush_delayed(st: State, stream=None):

@@ -4,7 +4,7 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-from gpu_util import fp64_tol, rel_err, run_chain, say
+from gpu_util import EPS64, det_bound_fn, det_ratio_bound, fp64_tol, ratio_err, rel_err, run_chain, say
 from test_rng_host import philox4x32_10
 
 pytestmark = pytest.mark.gpu
@@ -75,7 +75,8 @@ def test_slater_n32_fp64_every_step():
     draws, u01 = draws_for(g, wl.steps, wl.walkers, wl.n, wl.sites - wl.n, wl.ranks, wl.k_max)
     wk = Walkers(lrx.LRX_DET, torch.float64, phi, occ, emp, wl.k_max, wl.delay)
     chain = orc.DetChain(phi, occ, emp)
-    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, tol_ratio=1e-10, tol_inv=1e-10)
+    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, tol_ratio=1e-10, tol_inv=1e-10,
+                                         bound_fn=det_bound_fn(phi))
     say(f"  max rel err ratio {worst_r:.2e} inverse {worst_m:.2e}")
     np.testing.assert_allclose(la, chain.logabs, atol=1e-9)
     np.testing.assert_allclose(ph, chain.phase, atol=1e-12)
@@ -96,7 +97,8 @@ def test_delayed_det_chain_fp64(n, k_max, ranks, K, W, steps):
     draws, u01 = draws_for(g, steps, W, n, L - n, ranks, k_max)
     wk = Walkers(lrx.LRX_DET, torch.float64, phi, occ, emp, k_max, K)
     chain = orc.DetChain(phi, occ, emp)
-    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=3, tol_ratio=1e-10, tol_inv=1e-10)
+    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=3, tol_ratio=1e-10, tol_inv=1e-10,
+                                         bound_fn=det_bound_fn(phi))
     say(f"  max rel err ratio {worst_r:.2e} inverse {worst_m:.2e}")
     np.testing.assert_allclose(la, chain.logabs, atol=1e-8)
 
@@ -112,7 +114,8 @@ def test_complex_det_chain(dt):
     wk = Walkers(lrx.LRX_DET, DT[dt], phi, occ, emp, 2, K)
     chain = orc.DetChain(phi, occ, emp)
     tol = 1e-10 if dt == "c128" else 2e-3
-    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=2, tol_ratio=tol, tol_inv=tol)
+    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=2, tol_ratio=tol, tol_inv=tol,
+                                         bound_fn=det_bound_fn(phi) if dt == "c128" else None)
     say(f"  {dt}: max rel err ratio {worst_r:.2e} inverse {worst_m:.2e}")
     np.testing.assert_allclose(ph, chain.phase, atol=1e-8 if dt == "c128" else 1e-3)
 
@@ -220,10 +223,13 @@ def test_scale_workload_full_size_sampled():
         wk.set_draws(k, elec, slot)
         r = wk.propose().cpu().numpy()
         prop = book.proposed(k, elec, slot)
-        la0, ph0, _ = orc.slogdet(orc.slater_matrices(phi, book.occ[sample]), want_inv=False)
+        la0, ph0, inv0 = orc.slogdet(orc.slater_matrices(phi, book.occ[sample]))
         la1, ph1, _ = orc.slogdet(orc.slater_matrices(phi, prop[sample]), want_inv=False)
         ref = orc.ratio(la1, ph1, la0, ph0)
-        assert rel_err(r[sample], ref).max() <= 1e-10, t
+        err = ratio_err(r[sample], ref)
+        tol = np.maximum(1e-10, 8 * EPS64 * det_ratio_bound(phi, book.occ[sample], prop[sample], inv0,
+                                                            k[sample], elec[sample]))
+        assert np.all(err <= tol), (t, err, tol)
         mask = np.ones(wl.walkers, bool)
         wk.decide(mask=mask)
         wk.apply()
@@ -258,3 +264,33 @@ def test_metropolis_modes():
         c = philox4x32_10([w, ctr & 0xFFFFFFFF, ctr >> 32, 0], (seed & 0xFFFFFFFF, seed >> 32))
         uu[w] = (((c[0] >> 5) << 26) | (c[1] >> 6)) * 2.0 ** -53
     np.testing.assert_array_equal(acc.cpu().numpy().astype(bool), orc.metropolis(ratio, uu))
+
+
+@pytest.mark.parametrize("K", [0, 4])
+def test_fused_hop_step_matches_oracle(K):
+    """propose_hop + accept_hop (device Metropolis with the given uniforms, fused
+    occupancy commit) follow the oracle's chain."""
+    say(f"fused hop step K={K}")
+    g = gen.generator(500 + K)
+    n, W, L, steps = 40, 12, 90, 21
+    phi = gen.normal(g, (L, n))
+    occ, emp = gen.occupancy(g, W, L, n)
+    wk = Walkers(lrx.LRX_DET, torch.float64, phi, occ, emp, 4, K)
+    chain = orc.DetChain(phi, occ, emp)
+    u01 = torch.zeros(W, dtype=torch.float64, device="cuda")
+    for t in range(steps):
+        k, elec, slot = gen.hop_draws(g, W, n, L - n, (1, 2, 4), 4)
+        u = gen.uniforms(g, W)
+        wk.set_draws(k, elec, slot)
+        u01.copy_(torch.as_tensor(u))
+        wk.step_device(mode=lrx.LRX_MH_UNIFORMS, u01=u01)
+        r_gpu = wk.ratio.cpu().numpy()
+        r_orc = chain.propose(k, elec, slot)
+        assert ratio_err(r_gpu, r_orc).max() <= 1e-10, t
+        mask = orc.metropolis(r_orc, u)
+        np.testing.assert_array_equal(wk.accept.cpu().numpy().astype(bool), mask)
+        chain.accept(k, elec, slot, mask)
+    np.testing.assert_array_equal(wk.occ.cpu().numpy(), chain.book.occ)
+    inv = wk.inverse().cpu().numpy()
+    assert rel_err(inv, chain.inv, axis=(1, 2)).max() <= 1e-10
+    np.testing.assert_allclose(wk.st.logabs.cpu().numpy(), chain.logabs, atol=1e-9)

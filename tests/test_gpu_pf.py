@@ -4,7 +4,7 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-from gpu_util import rel_err, run_chain, say
+from gpu_util import ratio_err, rel_err, run_chain, say
 
 pytestmark = pytest.mark.gpu
 
@@ -114,7 +114,7 @@ def test_pfaffian_workload_full_size_sampled():
             la0, ph0 = orc.slogpf(orc.pairing_matrices(f, book.occ[sample]))
             la1, ph1 = orc.slogpf(orc.pairing_matrices(f, prop[sample]))
             ref = orc.ratio(la1, ph1, la0, ph0)
-            worst = max(worst, float(rel_err(r[sample], ref).max()))
+            worst = max(worst, float(ratio_err(r[sample], ref).max()))
         mask = np.ones(wl.walkers, bool)
         wk.decide(mask=mask)
         wk.apply()
