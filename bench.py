@@ -63,7 +63,10 @@ class Run:
         from paper_2602_05255_amd.walkers import Walkers
         self.torch, self.lrx = torch, lrx
         self.wl = wl
-        phi, occ, emp, g = gen.slater_inputs(wl, walkers=walkers, seed_offset=seed_offset)
+        if wl.kind == "det":
+            phi, occ, emp, g = gen.slater_inputs(wl, walkers=walkers, seed_offset=seed_offset)
+        else:
+            phi, occ, emp, g = gen.pairing_inputs(wl, walkers=walkers, seed_offset=seed_offset)
         self.phi = phi
         self.W = walkers
         self.P = wl.refresh
@@ -74,7 +77,8 @@ class Run:
         self.k = torch.as_tensor(k).to(dev)
         self.e = torch.as_tensor(e).to(dev)
         self.s = torch.as_tensor(s).to(dev)
-        self.wk = Walkers(lrx.LRX_DET, dtype, phi, occ, emp, wl.k_max, wl.delay, refresh_period=0)
+        kind = lrx.LRX_DET if wl.kind == "det" else lrx.LRX_PF
+        self.wk = Walkers(kind, dtype, phi, occ, emp, wl.k_max, wl.delay, refresh_period=0)
         self.graph = None
 
     def period(self, timer=None):
@@ -84,13 +88,22 @@ class Run:
             k, e, s = self.k[t], self.e[t], self.s[t]
             if timer is not None:
                 timer.begin("propose", wk.st.slot)
-            lrx.lrx_det_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
-                                    wk.ratio)
+            if wk.kind == lrx.LRX_DET:
+                lrx.lrx_det_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
+                                        wk.ratio)
+            else:
+                wk.use_draws(k, e, s)
+                wk.propose()
+                lrx.lrx_metropolis(wk.st, wk.ratio, None, 0, t, lrx.LRX_MH_FORCE, wk.accept)
             if timer is not None:
                 timer.end("propose")
                 timer.begin("accept", wk.st.slot)
-            lrx.lrx_det_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
-                                   wk.empty, wk.n_empty)
+            if wk.kind == lrx.LRX_DET:
+                lrx.lrx_det_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
+                                       wk.empty, wk.n_empty)
+            else:
+                lrx.lrx_pf_accept_update(wk.st, k, e, wk.u, wk.accept)
+                lrx.lrx_hop_commit(wk.W, wk.n, wk.n_empty, wk.k_max, k, e, s, wk.accept, wk.occ, wk.empty)
             if timer is not None:
                 timer.end("accept")
             if wk.delay and wk.st.slot == wk.delay:
@@ -154,10 +167,14 @@ class EventTimer:
 
 
 def accept_bytes(wl, s, W, tau):
-    """Algorithmic HBM bytes of one delayed accept launch (all walkers accepted):
-    read A_0^-1 (n^2), read the tau live b-slot rows (n * tau * k_max), read
-    u and C (2 n k_max), write slot tau of a and b (2 n k_max)."""
+    """Algorithmic HBM bytes of one delayed accept launch (all walkers accepted).
+    DET: read A_0^-1 (n^2), the tau live b-slot rows (n k_max tau), u and C
+    (2 n k_max); write slot tau of a and b (2 n k_max).
+    PF: read A_0^-1 (n^2), x, col and the 2 tau a-slot columns; write the two
+    new a-slot columns."""
     n, km = wl.n, wl.k_max
+    if wl.kind == "pf":
+        return W * s * (n * n + 2 * n * tau + 4 * n)
     return W * s * (n * n + n * km * tau + 4 * n * km)
 
 
@@ -192,15 +209,22 @@ def measure(wl, dtype, walkers, args, torch, label):
     gpu = e0.elapsed_time(e1) * 1e-3
     T = max(wall, gpu)
     value = walkers * run.P * args.steps / T
-    # flush roofline: algorithmic flops 2 n^2 K k_max per walker; bytes RW of M0 + panels
+    # flush roofline: algorithmic flops per walker 2 n^2 K k_max (DET, real), 8 n^2 2K / 2
+    # (PF complex, upper half); bytes RW of M0 + the slot panels
     n, K, km = wl.n, wl.delay, wl.k_max
     flush = None
     if flush_t:
-        fflops = walkers * 2.0 * n * n * K * km
-        fbytes = walkers * elem * (2 * n * n + 2 * n * K * km)
+        if wl.kind == "pf":
+            fflops = walkers * 8.0 * n * n * 2 * K / 2
+            fbytes = walkers * elem * (1.5 * n * n + 2 * n * K)
+            elem_peak = FP32_PEAK_TFS if elem <= 8 else FP64_PEAK_TFS
+        else:
+            fflops = walkers * 2.0 * n * n * K * km * (4 if elem == 16 else 1)
+            fbytes = walkers * elem * (2 * n * n + 2 * n * K * km)
+            elem_peak = FP64_PEAK_TFS if elem == 8 else FP32_PEAK_TFS
         flush = {"avg_us": flush_t * 1e6, "tflops": fflops / flush_t / 1e12,
                  "gbs": fbytes / flush_t / 1e9,
-                 "mfma_frac": fflops / flush_t / 1e12 / (FP64_PEAK_TFS if elem == 8 else FP32_PEAK_TFS),
+                 "mfma_frac": fflops / flush_t / 1e12 / elem_peak,
                  "hbm_frac": fbytes / flush_t / 1e9 / HBM_PEAK_GBS}
     log(f"  [{label}] {value:.4g} walker-steps/s, {T / args.steps * 1e3:.3f} ms per period; accept "
         f"{t_tot / len(acc) * 1e6:.1f} us avg, {bytes_tot / t_tot / 1e9:.0f} GB/s; refresh {refresh_t * 1e3:.2f} ms")
@@ -213,13 +237,18 @@ def measure(wl, dtype, walkers, args, torch, label):
 
 
 def rel_error(run, torch, sample):
-    """Max relative error of the GPU inverse and log|det| against the oracle on sampled walkers."""
+    """Max relative error of the GPU inverse and log|det| (log|pf|) against the oracle on sampled walkers."""
     import oracle as orc
     orc.build(force=False)
     wk = run.wk
     inv = wk.inverse()[sample].cpu().numpy()
     occ = wk.occ[sample].cpu().numpy()
-    la, ph, oinv = orc.slogdet(orc.slater_matrices(run.phi, occ))
+    if run.wl.kind == "pf":
+        a = orc.pairing_matrices(run.phi, occ)
+        la, ph = orc.slogpf(a)
+        oinv = orc.skew_inverse(a)
+    else:
+        la, ph, oinv = orc.slogdet(orc.slater_matrices(run.phi, occ))
     e_inv = np.linalg.norm(inv - oinv, axis=(1, 2)) / np.linalg.norm(oinv, axis=(1, 2))
     e_la = np.abs(wk.st.logabs[sample].cpu().numpy() - la)
     return {"inverse_max": float(e_inv.max()), "logdet_abs_max": float(e_la.max()), "walkers": len(sample)}
@@ -275,6 +304,57 @@ def recompute(wl, run, torch, reps=5):
     return out
 
 
+def bench_secondary(wl, args, torch, dtype):
+    """A secondary workload (e.g. the Pfaffian one): same timing, no CPU/recompute legs."""
+    W = args.walkers or wl.walkers
+    log(f"workload {wl.name}: W={W} n={wl.n} L={wl.sites} K={wl.delay} refresh={wl.refresh}")
+    run, r = measure(wl, dtype, W, args, torch, str(dtype).replace("torch.", ""))
+    err = rel_error(run, torch, np.linspace(0, W - 1, 4).astype(int))
+    log(f"  error vs oracle: {err}")
+    return {"metric": METRIC, "value": r["value"], "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": str(dtype).replace("torch.", ""), "data": "synthetic",
+            "config": {"workload": wl.name, "walkers": W, "n": wl.n, "sites": wl.sites, "delay": wl.delay,
+                       "refresh_every": wl.refresh, "mode": "forced-accept"},
+            "accept_avg_us": r["accept_avg_us"], "accept_gbs": r["accept_gbs"], "refresh_ms": r["refresh_ms"],
+            "flush": r["flush"], "rel_error": err}
+
+
+def bench_adjoint(wl, args, torch):
+    """Forward + hand-written backward of log det(Phi[occ] + B C^T) for all samples."""
+    from paper_2602_05255_amd import inputs as gen
+    from paper_2602_05255_amd.adjoint import lowrank_logdet
+    phi, occ, b, c, w = gen.lowrank_inputs(wl)
+    dev = "cuda"
+    P = torch.tensor(phi, dtype=torch.complex128, device=dev, requires_grad=True)
+    B = torch.tensor(b, dtype=torch.complex64, device=dev, requires_grad=True)
+    C = torch.tensor(c, dtype=torch.complex64, device=dev, requires_grad=True)
+    occ_t = torch.as_tensor(occ, dtype=torch.int32, device=dev)
+    wt = torch.as_tensor(w, dtype=torch.complex128, device=dev)
+
+    def one():
+        ld, _ = lowrank_logdet(P, B, C, occ_t, torch.complex64)
+        loss = (wt * ld).real.sum()
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    S, n = occ.shape
+    return {"metric": "samples/s (log det + hand-written backward)", "value": S / dt, "unit": "samples/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+            "data": "synthetic", "config": {"workload": wl.name, "samples": S, "n": n, "sites": phi.shape[0],
+                                            "rank": b.shape[-1]},
+            "note": "includes the complex128 factorisation of every A_s = Phi[occ_s] (init) in each step"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -288,6 +368,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     wl = gen.WORKLOADS[args.workload]
+    if wl.name == "logpsi_grad_n512_c64":
+        print(json.dumps(bench_adjoint(wl, args, torch)), flush=True)
+        return
+    if wl.kind == "pf":
+        print(json.dumps(bench_secondary(wl, args, torch, torch.complex64)), flush=True)
+        return
     assert wl.kind == "det" and wl.n > 0, "the default benchmark drives a uniform-n determinant workload"
     W = args.walkers or wl.walkers
     log(f"workload {wl.name}: W={W} n={wl.n} L={wl.sites} ranks={wl.ranks} K={wl.delay} refresh={wl.refresh}")

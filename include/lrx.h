@@ -252,6 +252,45 @@ int lrx_det_accept_hop(lrx_state *st, const int32_t *k, const int32_t *elec,
 int lrx_det_flush_delayed(lrx_state *st, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Low-rank log-determinant and its adjoint                                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * log det M_w for M_w = A_w + B_w C_w^T, with A_w^-T the state's inverse
+ * (flushed: st->slot == 0, else LRX_ENEEDFLUSH).  By the matrix determinant
+ * lemma (Sec. II.A with dense u = C, v = B):
+ *   log det M = log det A + log det R,  R = I_r + C^T P,  P = A^-1 B,
+ * computed in one pass over A^-T per walker.
+ *   r: rank, 1..8.  B, C: bulk [W][n][r].  P, Q (= A^-T C): bulk [W][n][r] out;
+ *   Rinv: bulk [W][r][r] out; logabs: double [W] out; phase: wide [W] out
+ *   (zero phase and -inf logabs when R is singular).
+ */
+int lrx_det_lowrank_fwd(const lrx_state *st, int32_t r, const void *B, const void *C,
+                        void *P, void *Q, void *Rinv, double *logabs, void *phase,
+                        void *stream);
+
+/* Workspace bytes of lrx_det_lowrank_bwd (host only). */
+int lrx_det_lowrank_work_bytes(const lrx_shape *shape, int32_t r, int32_t sites, size_t *out);
+
+/*
+ * Adjoint of lrx_det_lowrank_fwd.  g: wide [W], the cotangent of log det M_w in
+ * torch's convention (gradients of a real loss are returned conjugate-weighted).
+ * With M^-T = A^-T - Q R^-T P^T (Woodbury, Eq. det_inv):
+ *   dB   = g conj(M^-T C) = g conj(Q R^-T)          bulk [W][n][r]
+ *   dC   = g conj(M^-1 B) = g conj(P R^-1)          bulk [W][n][r]
+ *   dphi[s][:] = sum over (w, i) with occ[w][i] = s of g_w conj(M_w^-T[i][:])
+ *                                                   bulk [sites][n] (overwritten)
+ * (the gradient with respect to the orbital matrix through A_w = phi[occ_w]).
+ * The first term of dphi is gathered site by site; the correction
+ * sum g conj(Q R^-T P^T) is one dense GEMM on MFMA with inner dimension W r.
+ *   work: device workspace of lrx_det_lowrank_work_bytes bytes.
+ */
+int lrx_det_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int32_t sites,
+                        const void *P, const void *Q, const void *Rinv, const void *g,
+                        void *dphi, void *dB, void *dC, void *work, size_t work_bytes,
+                        void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Pfaffians (Sec. III)                                                     */
 /* ------------------------------------------------------------------------ */
 

@@ -323,6 +323,80 @@ int lrx_det_flush_delayed(lrx_state *st, void *stream) {
     return rc;
 }
 
+static int lowrank_check(const lrx_state *st, int32_t r) {
+    int rc = check_kind(st, LRX_DET);
+    if (rc) return rc;
+    if (r < 1 || r > 8 || r > st->shape.n) return LRX_ESHAPE;
+    if (st->shape.delay > 0 && st->slot != 0) return LRX_ENEEDFLUSH;
+    // forward kernel keeps C and the P accumulation in LDS
+    if (2 * (size_t)8 * padded_n(st->shape.n, bulk_bytes(st->shape.dtype)) * bulk_bytes(st->shape.dtype) > 163840)
+        return LRX_EUNSUPPORTED;
+    return LRX_OK;
+}
+
+int lrx_det_lowrank_fwd(const lrx_state *st, int32_t r, const void *B, const void *C, void *P, void *Q,
+                        void *Rinv, double *logabs, void *phase, void *stream) {
+    int rc = lowrank_check(st, r);
+    if (rc) return rc;
+    if (!B || !C || !P || !Q || !Rinv || !logabs || !phase) return LRX_EINVAL;
+    LowRankArgs a;
+    memset(&a, 0, sizeof(a));
+    a.dtype = st->shape.dtype;
+    a.W = st->shape.walkers;
+    a.n = st->shape.n;
+    a.r = r;
+    a.inv = st->inv;
+    a.B = B;
+    a.C = C;
+    a.P = P;
+    a.Q = Q;
+    a.Rinv = Rinv;
+    a.logabs = logabs;
+    a.phase = phase;
+    a.state_logabs = st->logabs;
+    a.state_phase = st->phase;
+    return hip_rc(lowrank_fwd(a, as_stream(stream)));
+}
+
+int lrx_det_lowrank_work_bytes(const lrx_shape *shape, int32_t r, int32_t sites, size_t *out) {
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    if (!out) return LRX_EINVAL;
+    if (shape->kind != LRX_DET) return LRX_EKIND;
+    if (r < 1 || r > 8 || sites < shape->n) return LRX_ESHAPE;
+    *out = lowrank_work_bytes(shape->dtype, shape->walkers, shape->n, r, sites);
+    return LRX_OK;
+}
+
+int lrx_det_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int32_t sites, const void *P,
+                        const void *Q, const void *Rinv, const void *g, void *dphi, void *dB, void *dC,
+                        void *work, size_t work_bytes, void *stream) {
+    int rc = lowrank_check(st, r);
+    if (rc) return rc;
+    if (!occ || !P || !Q || !Rinv || !g || !dphi || !dB || !dC || !work) return LRX_EINVAL;
+    if (sites < st->shape.n) return LRX_ESHAPE;
+    if (work_bytes < lowrank_work_bytes(st->shape.dtype, st->shape.walkers, st->shape.n, r, sites))
+        return LRX_EINVAL;
+    LowRankArgs a;
+    memset(&a, 0, sizeof(a));
+    a.dtype = st->shape.dtype;
+    a.W = st->shape.walkers;
+    a.n = st->shape.n;
+    a.r = r;
+    a.sites = sites;
+    a.inv = st->inv;
+    a.P = const_cast<void *>(P);
+    a.Q = const_cast<void *>(Q);
+    a.Rinv = const_cast<void *>(Rinv);
+    a.g = g;
+    a.occ = occ;
+    a.dphi = dphi;
+    a.dB = dB;
+    a.dC = dC;
+    lowrank_bind_work(a, work);
+    return hip_rc(lowrank_bwd(a, as_stream(stream)));
+}
+
 int lrx_pf_propose_ratio(lrx_state *st, const int32_t *k, const int32_t *cols, const void *x, void *ratio,
                          void *stream) {
     int rc = check_kind(st, LRX_PF);

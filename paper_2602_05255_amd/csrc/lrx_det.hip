@@ -10,555 +10,13 @@
 //   accept K>0: a_tau = C, b_tau = (M_{tau-1} u) R^-T              (Eqs. det_a, det_b, Sec. II.C)
 //
 // All kernels are HBM-streaming; MFMA is used only by the delayed flush.
-#include "lrx_common.hpp"
-#include "lrx_internal.hpp"
+#include "lrx_det_impl.hpp"
 
 namespace {
 
+using namespace lrxdet;
 using lrx::StepArgs;
 using lrx::HopArgs;
-
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / LRX_WAVE;
-
-__device__ __forceinline__ void flag_or(uint32_t *flags, int w, uint32_t bit) {
-    atomicOr(flags + w, bit);
-}
-
-// ------------------------------------------------------------------ build hop
-template <class T>
-__global__ __launch_bounds__(kThreads) void det_build_hop_kernel(HopArgs a) {
-    using Wd = typename Wide<T>::type;
-    const int w = blockIdx.x;
-    const int n = a.n, KM = a.KM;
-    const Wd *phi = static_cast<const Wd *>(a.phi);
-    T *u = static_cast<T *>(a.out) + (size_t)w * KM * n;
-    int kw = a.k[w];
-    bool bad = kw < 1 || kw > KM;
-    __shared__ int s_src[LRX_MAX_KMAX_DET], s_dst[LRX_MAX_KMAX_DET];
-    __shared__ int s_bad;
-    if (threadIdx.x == 0) s_bad = bad ? 1 : 0;
-    __syncthreads();
-    if (threadIdx.x < KM) {
-        const int c = threadIdx.x;
-        int e = a.elec[w * KM + c], sl = a.slot[w * KM + c];
-        int src = 0, dst = 0;
-        if (!bad && c < kw) {
-            if (e < 0 || e >= n || sl < 0 || sl >= a.n_empty) atomicOr(&s_bad, 1);
-            else {
-                src = a.occ[(size_t)w * n + e];
-                dst = a.empty[(size_t)w * a.n_empty + sl];
-                if (src < 0 || src >= a.sites || dst < 0 || dst >= a.sites) { atomicOr(&s_bad, 1); src = dst = 0; }
-            }
-        }
-        s_src[c] = src;
-        s_dst[c] = dst;
-    }
-    __syncthreads();
-    const bool fail = s_bad != 0;
-    if (fail && threadIdx.x == 0) flag_or(a.flags, w, LRX_FLAG_BADINDEX);
-    if (fail) kw = 0;
-    for (int c = 0; c < KM; ++c) {
-        const Wd *ps = phi + (size_t)s_src[c] * n;
-        const Wd *pd = phi + (size_t)s_dst[c] * n;
-        for (int j = threadIdx.x; j < n; j += kThreads)
-            u[(size_t)c * n + j] = (c < kw) ? conv<T>(pd[j] - ps[j]) : zero<T>();
-    }
-}
-
-// ------------------------------------------------------------------ propose
-// One work-group per walker; thread t owns rows i = t + 256 ii of the columns.
-// Cost O(n k + tau n k) per walker: rows I of M0, the live columns of the
-// a-slots (read once), b-slot rows I and u.
-//   C[c][i]  = M0[I_c][i] - sum_{live te} a_te[i] b_te[I_c]     (A_{tau-1}^-1[:, I])
-//   G[te][c] = a_te . u_c   (reduced in groups with the multi-value butterfly)
-//   R        = I + u^T C,   r = det R
-// With a hop table the update vectors u = Phi[s'] - Phi[s] are built here too.
-template <class T> constexpr int prop_nv() { return sizeof(T) <= 4 ? 32 : (sizeof(T) == 8 ? 16 : 8); }
-
-// NW waves per walker (one work-group); each thread owns NI entries i = t + 64 NW ii.
-// With NW = 1 every reduction stays inside the wave and no block barrier sits on
-// the critical path.
-template <class T, int KM, int NW, int NI>
-__global__ __launch_bounds__(64 * NW) void det_propose_kernel(StepArgs a) {
-    using Wd = typename Wide<T>::type;
-    constexpr int NT = 64 * NW;
-    constexpr int NVG = prop_nv<T>() >= KM ? prop_nv<T>() : KM;   // values per group reduction
-    constexpr int GS0 = NVG / KM;
-    constexpr int GS = (GS0 * NI <= 32) ? GS0 : (32 / NI > 0 ? 32 / NI : 1);   // slot columns per group
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int w = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & (LRX_WAVE - 1), wv = tid / LRX_WAVE;
-    const int n = a.n, tau = a.tau, KK = a.K * KM, TE = tau * KM;
-    const T *M = static_cast<const T *>(a.inv) + (size_t)w * n * n;
-    T *u = const_cast<T *>(static_cast<const T *>(a.u)) + (size_t)w * KM * n;
-    const T *fa = static_cast<const T *>(a.fa) + (size_t)w * KK * n;
-    const T *fb = static_cast<const T *>(a.fb) + (size_t)w * n * KK;
-    uint8_t *st = a.stash + (size_t)w * a.L.stride;
-    T *C = reinterpret_cast<T *>(st + a.L.c);
-    T *G = reinterpret_cast<T *>(st + a.L.g);
-    T *Rinv = reinterpret_cast<T *>(st + a.L.rinv);
-    Wd *ratio_st = reinterpret_cast<Wd *>(st + a.L.ratio);
-    const int *kslot = reinterpret_cast<const int *>(st + a.L.kslot);
-
-    T *s_fbI = reinterpret_cast<T *>(smem);                 // [KM][TE]
-    T *s_red = s_fbI + (size_t)KM * TE;                     // [NW][64]
-    int *s_live = reinterpret_cast<int *>(s_red + NW * 64);   // [TE]
-    int *s_ks = s_live + TE;                                   // [tau]
-    __shared__ int s_rows[KM], s_src[KM], s_dst[KM];
-    __shared__ int s_k, s_bad, s_nl;
-
-    const bool fused = a.hop_table != nullptr;
-    for (int t = tid; t < tau; t += NT) s_ks[t] = min(max(kslot[t], 0), KM);
-    if (tid < KM) {
-        int kw = a.k[w];
-        const int bad = (kw < 1 || kw > KM);
-        kw = bad ? 1 : kw;
-        int r = a.rows[w * KM + tid];
-        int src = 0, dst = 0, b = bad;
-        if (tid < kw) {
-            if (r < 0 || r >= n) { b = 1; r = 0; }
-            if (fused) {
-                const int sl = a.slot[w * KM + tid];
-                if (sl < 0 || sl >= a.n_empty) {
-                    b = 1;
-                } else {
-                    src = a.occ[(size_t)w * n + r];
-                    dst = a.empty[(size_t)w * a.n_empty + sl];
-                    if (src < 0 || src >= a.sites || dst < 0 || dst >= a.sites) { b = 1; src = dst = 0; }
-                }
-            }
-        }
-        s_rows[tid] = (tid < kw) ? r : 0;
-        s_src[tid] = src;
-        s_dst[tid] = dst;
-        if (tid == 0) { s_k = kw; s_bad = 0; }
-        __builtin_amdgcn_wave_barrier();
-        if (b) atomicOr(&s_bad, 1);
-    }
-    for (int idx = tid; idx < TE * KM; idx += NT) G[idx] = zero<T>();
-    __syncthreads();
-    if (tid == 0) {
-        int nl = 0;
-        for (int t = 0; t < tau; ++t)
-            for (int e = 0; e < s_ks[t]; ++e) s_live[nl++] = t * KM + e;
-        s_nl = nl;
-    }
-    const int k = s_k;
-    const bool bad = s_bad != 0;
-    for (int idx = tid; idx < KM * TE; idx += NT) {
-        int c = idx / TE, te = idx - c * TE;
-        s_fbI[idx] = (c < k) ? fb[(size_t)s_rows[c] * KK + te] : zero<T>();
-    }
-
-    T uv[NI][KM], cv[NI][KM];
-    const Wd *tab = static_cast<const Wd *>(a.hop_table);
-#pragma unroll
-    for (int ii = 0; ii < NI; ++ii) {
-        const int i = tid + ii * NT;
-        const bool valid = i < n;
-#pragma unroll
-        for (int c = 0; c < KM; ++c) {
-            T uu = zero<T>(), cc = zero<T>();
-            if (valid && c < k) {
-                if (fused) uu = bad ? zero<T>() : conv<T>(tab[(size_t)s_dst[c] * n + i] - tab[(size_t)s_src[c] * n + i]);
-                else uu = u[(size_t)c * n + i];
-                cc = M[(size_t)s_rows[c] * n + i];
-            }
-            if (fused && valid) u[(size_t)c * n + i] = uu;
-            uv[ii][c] = uu;
-            cv[ii][c] = cc;
-        }
-    }
-    __syncthreads();
-    const int nl = s_nl;
-    for (int g0 = 0; g0 < nl; g0 += GS) {
-        T gp[GS * KM];
-#pragma unroll
-        for (int q = 0; q < GS * KM; ++q) gp[q] = zero<T>();
-        T av[GS][NI];
-#pragma unroll
-        for (int gi = 0; gi < GS; ++gi) {
-            const int te = (g0 + gi < nl) ? s_live[g0 + gi] : -1;
-#pragma unroll
-            for (int ii = 0; ii < NI; ++ii) {
-                const int i = tid + ii * NT;
-                av[gi][ii] = (te >= 0 && i < n) ? fa[(size_t)te * n + i] : zero<T>();
-            }
-        }
-#pragma unroll
-        for (int gi = 0; gi < GS; ++gi) {
-            const int te = (g0 + gi < nl) ? s_live[g0 + gi] : 0;
-#pragma unroll
-            for (int ii = 0; ii < NI; ++ii)
-#pragma unroll
-                for (int c = 0; c < KM; ++c) {
-                    cv[ii][c] = fmsc(av[gi][ii], s_fbI[c * TE + te], cv[ii][c]);
-                    gp[gi * KM + c] = fmac(av[gi][ii], uv[ii][c], gp[gi * KM + c]);
-                }
-        }
-        const T tot = wave_sum_multi<T, GS * KM>(gp);      // lane l: value l (gi = l / KM, c = l % KM)
-        if constexpr (NW == 1) {
-            if (lane < GS * KM && g0 + lane / KM < nl) {
-                const int c = lane % KM;
-                G[(size_t)s_live[g0 + lane / KM] * KM + c] = (c < k) ? tot : zero<T>();
-            }
-        } else {
-            if (lane < GS * KM) s_red[wv * 64 + lane] = tot;
-            __syncthreads();
-            if (tid < GS * KM && g0 + tid / KM < nl) {
-                T sum = zero<T>();
-#pragma unroll
-                for (int q = 0; q < NW; ++q) sum = sum + s_red[q * 64 + tid];
-                const int c = tid % KM;
-                G[(size_t)s_live[g0 + tid / KM] * KM + c] = (c < k) ? sum : zero<T>();
-            }
-            __syncthreads();
-        }
-    }
-    // C, and R[c][d] = delta_cd + sum_i u[c][i] C[d][i]
-    T rp[KM * KM];
-#pragma unroll
-    for (int q = 0; q < KM * KM; ++q) rp[q] = zero<T>();
-#pragma unroll
-    for (int ii = 0; ii < NI; ++ii) {
-        const int i = tid + ii * NT;
-        if (i < n) {
-#pragma unroll
-            for (int c = 0; c < KM; ++c) C[(size_t)c * n + i] = cv[ii][c];
-        }
-#pragma unroll
-        for (int c = 0; c < KM; ++c)
-#pragma unroll
-            for (int d = 0; d < KM; ++d) rp[c * KM + d] = fmac(uv[ii][c], cv[ii][d], rp[c * KM + d]);
-    }
-    const T rt = wave_sum_multi<T, KM * KM>(rp);
-    if (lane < KM * KM) s_red[wv * 64 + lane] = rt;
-    __syncthreads();
-
-    if (tid == 0) {
-        T r[KM * KM], ri[KM * KM];
-        for (int c = 0; c < KM; ++c)
-            for (int d = 0; d < KM; ++d) {
-                T sacc = (c == d) ? one<T>() : zero<T>();
-                if (c < k && d < k)
-                    for (int q = 0; q < NW; ++q) sacc = sacc + s_red[q * 64 + c * KM + d];
-                r[c * KM + d] = sacc;
-                ri[c * KM + d] = zero<T>();
-            }
-        Wd det;
-        bool sing;
-        small_lu_det_inv<T, KM>(r, k, ri, det, sing);
-        for (int c = 0; c < KM * KM; ++c) Rinv[c] = ri[c];
-        if (bad) det = zero<Wd>();
-        *ratio_st = det;
-        static_cast<Wd *>(a.ratio)[w] = det;
-        // A zero or non-finite ratio makes the update impossible (Sec. II.A): the
-        // stash copy is zeroed so accept skips the walker.  Bad indices are sticky.
-        if (bad) atomicOr(a.flags + w, LRX_FLAG_BADINDEX);
-        if (sing || is_zero(det) || !finite_v(det)) *ratio_st = zero<Wd>();
-    }
-}
-
-// ------------------------------------------------------------------ accept
-// Row-streaming pass.  A work-group handles `rows_per_block` rows of one
-// walker; each wave takes RB rows at a time, each lane holding NEL elements of
-// every row (16-byte vectors, coalesced).  u and C live in LDS, shared by all
-// rows of the block.  The row loop is specialised on KC, the walker's rank
-// rounded up to a power of two: the padded columns of u and C are zero and the
-// padded rows/columns of R^-1 are zero, so padding is exact.
-//
-// Per row batch: dots p[r][c] = M[q_r,:] . u_c (minus the slot correction),
-// one multi-value butterfly reduction (lane l then holds w[r][c] with
-// l = r*KC + c), z[r][c] = sum_d R^-1[c][d] w[r][d] on that lane, then
-//   DELAYED = false: M[q_r,:] -= sum_c z[r][c] C[:, c]^T  (Eq. det_inv)
-//   DELAYED = true : b_tau[q_r][c] = z[r][c]               (Eq. det_b)
-template <class T>
-__device__ __forceinline__ T lane_bcast(T v, int src) {     // src: wave-uniform
-    static_assert(sizeof(T) % 4 == 0, "");
-    constexpr int NW = sizeof(T) / 4;
-    int w[NW];
-    __builtin_memcpy(w, &v, sizeof(T));
-#pragma unroll
-    for (int i = 0; i < NW; ++i) w[i] = __builtin_amdgcn_readlane(w[i], src);
-    T o;
-    __builtin_memcpy(&o, w, sizeof(T));
-    return o;
-}
-__device__ __forceinline__ float shfl_any(float v, int src) { return __shfl(v, src, LRX_WAVE); }
-__device__ __forceinline__ double shfl_any(double v, int src) { return __shfl(v, src, LRX_WAVE); }
-__device__ __forceinline__ cf32 shfl_any(cf32 v, int src) { return {__shfl(v.x, src, LRX_WAVE), __shfl(v.y, src, LRX_WAVE)}; }
-__device__ __forceinline__ cf64 shfl_any(cf64 v, int src) { return {__shfl(v.x, src, LRX_WAVE), __shfl(v.y, src, LRX_WAVE)}; }
-
-template <class T>
-struct AcceptCtx {
-    T *M, *fa, *fb;
-    const T *G;
-    const T *s_u, *s_c, *s_ri;
-    int n, KK, tau, TE, q0, q1, npad, wv, lane;
-    bool vec_ok;
-};
-
-template <class T, int KC, int KM, int NEL, int RB, int MG, bool DELAYED>
-__device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
-    constexpr int V = vec16<T>();
-    constexpr int NCH = NEL / V;
-    constexpr int NV = RB * KC;
-    const int lane = c.lane;
-    const int my_r = (lane % NV) / KC, my_c = lane % KC;
-    T rrow[KC];
-#pragma unroll
-    for (int d = 0; d < KC; ++d) rrow[d] = c.s_ri[my_c * KM + d];
-    // Slot products G[te][c] (= a_te . u_c) for the slot columns this lane owns, te = lane + 64 m.
-    T g[MG][KC];
-#pragma unroll
-    for (int m = 0; m < MG; ++m)
-#pragma unroll
-        for (int cc = 0; cc < KC; ++cc) {
-            const int te = lane + m * LRX_WAVE;
-            g[m][cc] = (DELAYED && te < c.TE) ? c.G[(size_t)te * KM + cc] : zero<T>();
-        }
-    const int n = c.n;
-    // Software pipeline: the rows of the next batch are requested before the
-    // current batch is reduced, so two batches of loads are in flight per wave.
-    auto load_rows = [&](int qb, T (&x)[RB][NEL]) {
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int q = qb + r;
-            const T *row = c.M + (size_t)q * n;
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                const int j0 = ch * V * LRX_WAVE + lane * V;
-                T tmp[V];
-                if (q < c.q1 && c.vec_ok && j0 + V <= n) {
-                    ld16<T>(row + j0, tmp);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) tmp[v] = (q < c.q1 && j0 + v < n) ? row[j0 + v] : zero<T>();
-                }
-#pragma unroll
-                for (int v = 0; v < V; ++v) x[r][ch * V + v] = tmp[v];
-            }
-        }
-    };
-    const int qstep = kWaves * RB;
-    T xn[RB][NEL];
-    load_rows(c.q0 + c.wv * RB, xn);
-    for (int qb = c.q0 + c.wv * RB; qb < c.q1; qb += qstep) {
-        T x[RB][NEL];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int e = 0; e < NEL; ++e) x[r][e] = xn[r][e];
-        if (qb + qstep < c.q1) load_rows(qb + qstep, xn);
-        T p[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) p[i] = zero<T>();
-#pragma unroll
-        for (int cc = 0; cc < KC; ++cc) {
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                T uv[V];
-                ld16<T>(c.s_u + (size_t)cc * c.npad + ch * V * LRX_WAVE + lane * V, uv);
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-#pragma unroll
-                    for (int v = 0; v < V; ++v) p[r * KC + cc] = fmac(x[r][ch * V + v], uv[v], p[r * KC + cc]);
-            }
-        }
-        if (DELAYED) {
-            // - sum_t b_t[q][:] (a_t^T u): this lane owns slot columns te = lane + 64 m
-#pragma unroll
-            for (int m = 0; m < MG; ++m) {
-                if (m * LRX_WAVE < c.TE) {
-                    const int te = lane + m * LRX_WAVE;
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) {
-                        const int q = qb + r;
-                        const T bv = (te < c.TE && q < c.q1) ? c.fb[(size_t)q * c.KK + te] : zero<T>();
-#pragma unroll
-                        for (int cc = 0; cc < KC; ++cc) p[r * KC + cc] = fmsc(bv, g[m][cc], p[r * KC + cc]);
-                    }
-                }
-            }
-        }
-        const T w = wave_sum_multi<T, NV>(p);     // lane l: w[r][c], l mod NV = r*KC + c
-        T z = zero<T>();
-#pragma unroll
-        for (int d = 0; d < KC; ++d) z = fmac(rrow[d], shfl_any(w, my_r * KC + d), z);
-        if (DELAYED) {
-            const int q = qb + my_r;
-            if (lane < NV && q < c.q1) c.fb[(size_t)q * c.KK + c.tau * KM + my_c] = z;
-        } else {
-#pragma unroll
-            for (int cc = 0; cc < KC; ++cc) {
-                T zr[RB];
-#pragma unroll
-                for (int r = 0; r < RB; ++r) zr[r] = lane_bcast(z, r * KC + cc);
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    T cv[V];
-                    ld16<T>(c.s_c + (size_t)cc * c.npad + ch * V * LRX_WAVE + lane * V, cv);
-#pragma unroll
-                    for (int r = 0; r < RB; ++r)
-#pragma unroll
-                        for (int v = 0; v < V; ++v) x[r][ch * V + v] = fmsc(zr[r], cv[v], x[r][ch * V + v]);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const int q = qb + r;
-                if (q >= c.q1) continue;
-                T *row = c.M + (size_t)q * n;
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    const int j0 = ch * V * LRX_WAVE + lane * V;
-                    T tmp[V];
-#pragma unroll
-                    for (int v = 0; v < V; ++v) tmp[v] = x[r][ch * V + v];
-                    if (c.vec_ok && j0 + V <= n) {
-                        st16<T>(row + j0, tmp);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < V; ++v) if (j0 + v < n) row[j0 + v] = tmp[v];
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <class T, int KM, int NEL, int RB, int MG, bool DELAYED>
-__global__ __launch_bounds__(kThreads) void det_accept_kernel(StepArgs a, int rows_per_block, int blocks_per_walker) {
-    using Wd = typename Wide<T>::type;
-    constexpr int V = vec16<T>();
-    constexpr int NCH = NEL / V;
-    extern __shared__ __align__(16) unsigned char smem[];
-
-    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int w = lb / blocks_per_walker;
-    const int rb = lb - w * blocks_per_walker;
-    if (w >= a.W) return;
-    const int tid = threadIdx.x, lane = tid & (LRX_WAVE - 1), wv = tid / LRX_WAVE;
-    const int n = a.n, KK = a.K * KM, tau = a.tau, TE = tau * KM;
-    const int q0 = rb * rows_per_block;
-    const int q1 = min(n, q0 + rows_per_block);
-
-    T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
-    const T *u = static_cast<const T *>(a.u) + (size_t)w * KM * n;
-    uint8_t *st = a.stash + (size_t)w * a.L.stride;
-    const T *C = reinterpret_cast<const T *>(st + a.L.c);
-    const T *G = reinterpret_cast<const T *>(st + a.L.g);
-    const T *Rinv = reinterpret_cast<const T *>(st + a.L.rinv);
-    const Wd ratio = *reinterpret_cast<const Wd *>(st + a.L.ratio);
-    int *kslot = reinterpret_cast<int *>(st + a.L.kslot);
-    T *fa = DELAYED ? static_cast<T *>(a.fa) + (size_t)w * KK * n : nullptr;
-    T *fb = DELAYED ? static_cast<T *>(a.fb) + (size_t)w * n * KK : nullptr;
-
-    int k = a.k[w];
-    k = (k < 1 || k > KM) ? 1 : k;
-    const uint32_t fl = a.flags[w];
-    uint8_t acc;
-    if (a.mh_mode >= 0) {   // fused Metropolis decision (identical in every block of the walker)
-        acc = mh_decide<Wd>(ratio, fl, a.mh_mode, a.mh_mode == LRX_MH_UNIFORMS ? a.u01[w] : 0.0, a.seed,
-                            a.counter, (uint32_t)w);
-    } else {
-        acc = a.accept[w];
-    }
-    const bool take = acc != 0 && fl == 0 && !is_zero(ratio);
-    const int kc = k == 1 ? 1 : (k <= 2 ? 2 : (k <= 4 ? 4 : 8));
-    if (rb == 0 && tid == 0) {
-        if (a.mh_mode >= 0 || (!take && acc)) a.accept[w] = take ? 1 : 0;   // skipped: no occupancy commit
-        if (take && a.occ) {   // fused occupancy commit
-            for (int c = 0; c < k; ++c) {
-                const int e = a.rows[w * KM + c], sl = a.slot[w * KM + c];
-                if (e < 0 || e >= n || sl < 0 || sl >= a.n_empty) continue;
-                int32_t *po = a.occ + (size_t)w * n + e;
-                int32_t *pe = a.empty + (size_t)w * a.n_empty + sl;
-                const int32_t t = *po;
-                *po = *pe;
-                *pe = t;
-            }
-        }
-    }
-
-    if (!take) {
-        if (DELAYED) {   // a rejected walker's slot contributes nothing
-            for (int idx = tid; idx < KM * (q1 - q0); idx += kThreads) {
-                int c = idx / (q1 - q0), q = q0 + idx - c * (q1 - q0);
-                fa[(size_t)(tau * KM + c) * n + q] = zero<T>();
-                fb[(size_t)q * KK + tau * KM + c] = zero<T>();
-            }
-            if (rb == 0 && tid == 0) kslot[tau] = 0;
-        }
-        return;
-    }
-    if (rb == 0 && tid == 0) {
-        accum_logphase(ratio, a.logabs + w, static_cast<Wd *>(a.phase) + w);
-        if (DELAYED) kslot[tau] = k;
-    }
-
-    const int npad = NCH * V * LRX_WAVE;        // padded row length held in LDS
-    T *s_u = reinterpret_cast<T *>(smem);       // [KM][npad]
-    T *s_c = s_u + (size_t)KM * npad;           // [KM][npad]
-    T *s_ri = s_c + (size_t)KM * npad;          // [KM*KM]
-    for (int idx = tid; idx < kc * npad; idx += kThreads) {
-        int c = idx / npad, j = idx - c * npad;
-        bool ok = c < k && j < n;
-        s_u[idx] = ok ? u[(size_t)c * n + j] : zero<T>();
-        if (!DELAYED) s_c[idx] = ok ? C[(size_t)c * n + j] : zero<T>();
-    }
-    if (tid < KM * KM) {
-        const int c = tid / KM, d = tid - c * KM;
-        s_ri[tid] = (c < k && d < k) ? Rinv[tid] : zero<T>();
-    }
-    if (DELAYED) {   // a_tau = C for this block's rows; b_tau columns beyond kc are zero
-        for (int idx = tid; idx < KM * (q1 - q0); idx += kThreads) {
-            int c = idx / (q1 - q0), q = q0 + idx - c * (q1 - q0);
-            fa[(size_t)(tau * KM + c) * n + q] = (c < k) ? C[(size_t)c * n + q] : zero<T>();
-            if (c >= kc) fb[(size_t)q * KK + tau * KM + c] = zero<T>();
-        }
-    }
-    __syncthreads();
-
-    AcceptCtx<T> ctx{M, fa, fb, G, s_u, s_c, s_ri, n, KK, tau, TE, q0, q1, npad, wv, lane, a.aligned != 0};
-    if (kc == 1) {
-        accept_rows<T, 1, KM, NEL, RB, MG, DELAYED>(ctx);
-    } else if (kc == 2) {
-        if constexpr (KM >= 2) accept_rows<T, 2, KM, NEL, RB, MG, DELAYED>(ctx);
-    } else if (kc == 4) {
-        if constexpr (KM >= 4) accept_rows<T, 4, KM, NEL, RB, MG, DELAYED>(ctx);
-    } else {
-        if constexpr (KM >= 8) accept_rows<T, 8, KM, NEL, RB, MG, DELAYED>(ctx);
-    }
-}
-
-// ------------------------------------------------------------------ Metropolis
-template <class Wd>
-__global__ void metropolis_kernel(int W, const Wd *ratio, const double *u01, uint64_t seed,
-                                  uint64_t counter, int mode, const uint32_t *flags, uint8_t *accept) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= W) return;
-    accept[w] = mh_decide<Wd>(ratio[w], flags[w], mode, mode == LRX_MH_UNIFORMS ? u01[w] : 0.0, seed, counter,
-                              (uint32_t)w);
-}
-
-__global__ void hop_commit_kernel(int W, int n, int n_empty, int KM, const int32_t *k, const int32_t *elec,
-                                  const int32_t *slot, const uint8_t *accept, int32_t *occ, int32_t *empty) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= W || !accept[w]) return;
-    int kw = k[w];
-    if (kw < 1 || kw > KM) return;
-    for (int c = 0; c < kw; ++c) {
-        int e = elec[w * KM + c], s = slot[w * KM + c];
-        if (e < 0 || e >= n || s < 0 || s >= n_empty) continue;
-        int32_t *po = occ + (size_t)w * n + e;
-        int32_t *pe = empty + (size_t)w * n_empty + s;
-        int32_t t = *po;
-        *po = *pe;
-        *pe = t;
-    }
-}
 
 // ------------------------------------------------------------------ launchers
 template <class T> hipError_t build_hop_t(const HopArgs &a, hipStream_t s) {
@@ -601,13 +59,6 @@ template <class T> hipError_t propose_k(const StepArgs &a, hipStream_t s) {
         case 8: return propose_n<T, 8>(a, s);
     }
     return hipErrorInvalidValue;
-}
-
-// Rows held per wave batch: the RB x NEL row values plus the RB x KM partial
-// dot products stay within ~96 VGPRs.
-template <class T, int NEL, int KM> constexpr int rows_per_batch() {
-    constexpr int per_row = (NEL + KM) * (int)sizeof(T);
-    return 8 * per_row <= 384 ? 8 : (4 * per_row <= 384 ? 4 : (2 * per_row <= 384 ? 2 : 1));
 }
 
 template <class T, int KM, int NEL, bool D> hipError_t accept_t(const StepArgs &a, hipStream_t s) {

@@ -122,4 +122,25 @@ struct FactorArgs {
 size_t factor_work_bytes(int kind, int dtype, int W, int n);
 hipError_t factor(const FactorArgs &a, hipStream_t s);
 
+// Low-rank log-determinant and adjoint (lrx_adjoint.hip).
+struct LowRankArgs {
+    int dtype, W, n, r, sites;
+    const void *inv;                 // A^-T (bulk [W][n][n])
+    const void *B, *C;               // bulk [W][n][r]
+    void *P, *Q, *Rinv;              // bulk [W][n][r], [W][n][r], [W][r][r]
+    double *logabs;                  // out: log|det M|
+    void *phase;                     // out: wide
+    const double *state_logabs;      // log|det A|
+    const void *state_phase;         // wide
+    const void *g;                   // wide [W] cotangent
+    const int32_t *occ;              // [W][n]
+    void *dphi, *dB, *dC;            // bulk outputs
+    void *E, *F;                     // workspace
+    int *csr_start, *csr_cursor, *csr_list;
+};
+size_t lowrank_work_bytes(int dtype, int W, int n, int r, int sites);
+void lowrank_bind_work(LowRankArgs &a, void *work);
+hipError_t lowrank_fwd(const LowRankArgs &a, hipStream_t s);
+hipError_t lowrank_bwd(const LowRankArgs &a, hipStream_t s);
+
 }  // namespace lrx

@@ -71,6 +71,11 @@ _SIGS = {
     "lrx_det_propose_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "lrx_det_accept_hop": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _I, _P, ctypes.c_uint64, ctypes.c_uint64,
                             _P, _P, _P, _I, _P], ctypes.c_int),
+    "lrx_det_lowrank_fwd": ([ctypes.POINTER(lrx_state), _I, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_det_lowrank_work_bytes": ([ctypes.POINTER(lrx_shape), _I, _I, ctypes.POINTER(ctypes.c_size_t)],
+                                   ctypes.c_int),
+    "lrx_det_lowrank_bwd": ([ctypes.POINTER(lrx_state), _I, _P, _I, _P, _P, _P, _P, _P, _P, _P, _P,
+                             ctypes.c_size_t, _P], ctypes.c_int),
     "lrx_pf_init_inverse": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P], ctypes.c_int),
     "lrx_pf_refresh": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _P], ctypes.c_int),
     "lrx_pf_build_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -263,6 +268,41 @@ def lrx_det_accept_hop(st: State, k, elec, slot, u, mode, u01, seed, counter, ac
 
 def lrx_det_flush_delayed(st: State, stream=None):
     _check(_lib.lrx_det_flush_delayed(st.ptr(), _stream(stream)), "lrx_det_flush_delayed")
+
+
+# ------------------------------------------------------------------ low-rank log det
+def lrx_det_lowrank_fwd(st: State, r, B, C, P, Q, Rinv, logabs, phase, stream=None):
+    shp = (st.walkers, st.n, r)
+    for t, nm in ((B, "B"), (C, "C"), (P, "P"), (Q, "Q")):
+        _dev(t, nm, st.dtype, shp)
+    _dev(Rinv, "Rinv", st.dtype, (st.walkers, r, r))
+    _dev(logabs, "logabs", torch.float64, (st.walkers,))
+    _dev(phase, "phase", st.wide, (st.walkers,))
+    _check(_lib.lrx_det_lowrank_fwd(st.ptr(), int(r), _dev(B, "B"), _dev(C, "C"), _dev(P, "P"), _dev(Q, "Q"),
+                                    _dev(Rinv, "Rinv"), _dev(logabs, "logabs"), _dev(phase, "phase"),
+                                    _stream(stream)), "lrx_det_lowrank_fwd")
+
+
+def lrx_det_lowrank_work_bytes(st: State, r, sites) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.lrx_det_lowrank_work_bytes(ctypes.byref(st.c.shape), int(r), int(sites), ctypes.byref(out)),
+           "lrx_det_lowrank_work_bytes")
+    return int(out.value)
+
+
+def lrx_det_lowrank_bwd(st: State, r, occ, sites, P, Q, Rinv, g, dphi, dB, dC, work, stream=None):
+    shp = (st.walkers, st.n, r)
+    _dev(occ, "occ", torch.int32, (st.walkers, st.n))
+    for t, nm in ((P, "P"), (Q, "Q"), (dB, "dB"), (dC, "dC")):
+        _dev(t, nm, st.dtype, shp)
+    _dev(Rinv, "Rinv", st.dtype, (st.walkers, r, r))
+    _dev(g, "g", st.wide, (st.walkers,))
+    _dev(dphi, "dphi", st.dtype, (sites, st.n))
+    _dev(work, "work", torch.uint8)
+    _check(_lib.lrx_det_lowrank_bwd(st.ptr(), int(r), _dev(occ, "occ"), int(sites), _dev(P, "P"), _dev(Q, "Q"),
+                                    _dev(Rinv, "Rinv"), _dev(g, "g"), _dev(dphi, "dphi"), _dev(dB, "dB"),
+                                    _dev(dC, "dC"), _dev(work, "work"), ctypes.c_size_t(work.numel()),
+                                    _stream(stream)), "lrx_det_lowrank_bwd")
 
 
 # ------------------------------------------------------------------ PF
