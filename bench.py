@@ -219,8 +219,9 @@ def measure(wl, dtype, walkers, args, torch, label):
             fbytes = walkers * elem * (1.5 * n * n + 2 * n * K)
             elem_peak = FP32_PEAK_TFS if elem <= 8 else FP64_PEAK_TFS
         else:
-            fflops = walkers * 2.0 * n * n * K * km * (4 if elem == 16 else 1)
-            fbytes = walkers * elem * (2 * n * n + 2 * n * K * km)
+            kbar = float(np.mean(wl.ranks))    # live slot columns per step (padding is skipped)
+            fflops = walkers * 2.0 * n * n * K * kbar * (4 if elem == 16 else 1)
+            fbytes = walkers * elem * (2 * n * n + 2 * n * K * kbar)
             elem_peak = FP64_PEAK_TFS if elem == 8 else FP32_PEAK_TFS
         flush = {"avg_us": flush_t * 1e6, "tflops": fflops / flush_t / 1e12,
                  "gbs": fbytes / flush_t / 1e9,
@@ -355,6 +356,101 @@ def bench_adjoint(wl, args, torch):
             "note": "includes the complex128 factorisation of every A_s = Phi[occ_s] (init) in each step"}
 
 
+def bench_uneven(wl, args, torch):
+    """Uneven batch: every size class advanced by one persistent launch per window
+    of K steps; one benchmark step is one refresh period (P / K windows, then the
+    FP64 refresh of every class)."""
+    from paper_2602_05255_amd import inputs as gen
+    from paper_2602_05255_amd import lrx
+    from paper_2602_05255_amd.uneven import UnevenWalkers
+    classes, g = gen.uneven_inputs(wl, walkers=args.walkers or None)
+    K, P = wl.delay, wl.refresh
+    nwin = P // K
+    t0 = time.time()
+    uw = UnevenWalkers(torch.float32, classes, wl.k_max, K, K)
+    big = []
+    for c, p in zip(classes, uw.parts):
+        k, e, s = gen.hop_draws_batch(g, P, len(c["walkers"]), c["n"], c["n"], wl.ranks, wl.k_max)
+        big.append(tuple(torch.as_tensor(x).cuda() for x in (k, e, s)))
+    log(f"  setup {time.time() - t0:.1f}s; classes " +
+        ", ".join(f"n={p.st.n}:W={p.st.walkers}" for p in uw.parts) + f"; grid {uw.grid}")
+
+    def window(i):
+        for p, (k, e, s) in zip(uw.parts, big):
+            p.k, p.elec, p.slot = k[i * K:(i + 1) * K], e[i * K:(i + 1) * K], s[i * K:(i + 1) * K]
+        lrx.lrx_det_window(uw.parts, K, lrx.LRX_MH_FORCE, 0, i * K, uw.order, uw.queue, uw.grid)
+
+    def period():
+        for i in range(nwin):
+            window(i)
+        uw.refresh(report=False)
+
+    # eager pass with events around every window launch and the refresh
+    period()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nwin + 2)]
+    ev[0].record()
+    for i in range(nwin):
+        window(i)
+        ev[i + 1].record()
+    uw.refresh(report=False)
+    ev[-1].record()
+    torch.cuda.synchronize()
+    win_s = [ev[i].elapsed_time(ev[i + 1]) * 1e-3 for i in range(nwin)]
+    refresh_s = ev[nwin].elapsed_time(ev[-1]) * 1e-3
+    graph = None
+    if not args.no_graph:
+        s_ = torch.cuda.Stream()
+        s_.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_):
+            period()
+        torch.cuda.current_stream().wait_stream(s_)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            period()
+        torch.cuda.synchronize()
+    step = graph.replay if graph is not None else period
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    T = max(time.perf_counter() - t0, e0.elapsed_time(e1) * 1e-3)
+    W = uw.walkers
+    value = W * P * args.steps / T
+    # algorithmic bytes of one window (all proposals applied): per walker and step
+    # read A_0^-1 (n^2) and the live b-slot rows (n kbar tau), u and C (2 n kbar),
+    # write the new slot (2 n kbar); per walker and window the flush reads and
+    # writes A_0^-1 and reads the K kbar live slot columns of a and b.
+    kbar = float(np.mean(wl.ranks))
+    es = 4
+    wbytes = 0.0
+    for p in uw.parts:
+        n = p.st.n
+        per_step = n * n + n * kbar * (K - 1) / 2.0 + 4 * n * kbar
+        wbytes += p.st.walkers * es * (K * per_step + 2 * n * n + 2 * n * K * kbar)
+    win = float(np.mean(win_s))
+    log(f"  [uneven f32] {value:.4g} walker-steps/s, {T / args.steps * 1e3:.2f} ms per period; window "
+        f"{win * 1e3:.3f} ms ({wbytes / win / 1e9:.0f} GB/s algorithmic); refresh {refresh_s * 1e3:.1f} ms")
+    return {"metric": METRIC, "value": value, "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": wl.name, "walkers": W, "sizes": list(wl.extra["sizes"]),
+                       "class_walkers": {int(p.st.n): int(p.st.walkers) for p in uw.parts},
+                       "ranks": list(wl.ranks), "delay": K, "refresh_every": P, "mode": "forced-accept",
+                       "graph": graph is not None, "grid": uw.grid},
+            "roofline": {"bound": "hbm", "kernel": "det_window_kernel", "achieved": wbytes / win / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": wbytes / win / 1e9 / HBM_PEAK_GBS,
+                         "traffic": None, "avg_us": win * 1e6, "bytes_per_launch": wbytes},
+            "refresh_ms": refresh_s * 1e3}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -373,6 +469,9 @@ def main():
         return
     if wl.kind == "pf":
         print(json.dumps(bench_secondary(wl, args, torch, torch.complex64)), flush=True)
+        return
+    if wl.name == "uneven_n64_1024_fp32":
+        print(json.dumps(bench_uneven(wl, args, torch)), flush=True)
         return
     assert wl.kind == "det" and wl.n > 0, "the default benchmark drives a uniform-n determinant workload"
     W = args.walkers or wl.walkers

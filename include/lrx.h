@@ -92,8 +92,12 @@ enum {
 enum {
     LRX_MH_UNIFORMS = 0,  /* accept iff u01[w] < min(1, |r|^2)                      */
     LRX_MH_DEVICE_RNG = 1,/* same rule, u from a counter-based generator (seed, ctr) */
-    LRX_MH_FORCE = 2      /* accept every unflagged walker with a finite nonzero r    */
+    LRX_MH_FORCE = 2,     /* accept every unflagged walker with a finite nonzero r    */
+    LRX_MH_MASK = 3       /* lrx_det_window only: accept[] holds the caller's decision */
 };
+
+/* Largest number of size classes in one lrx_det_window call. */
+#define LRX_MAX_CLASSES 8
 
 typedef struct lrx_shape {
     int32_t kind;     /* LRX_DET or LRX_PF                                    */
@@ -250,6 +254,61 @@ int lrx_det_accept_hop(lrx_state *st, const int32_t *k, const int32_t *elec,
  * set st->slot = 0.  A no-op when st->slot == 0 or K == 0.
  */
 int lrx_det_flush_delayed(lrx_state *st, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Uneven batches: one launch for a window of delayed steps                  */
+/* ------------------------------------------------------------------------ */
+
+/* One size class of an uneven batch (all walkers of a class share n). */
+typedef struct lrx_window_class {
+    lrx_state *state;       /* DET state of the class: real bulk dtype, delay K >= 1;
+                               st->slot is advanced by the call                     */
+    const void *table;      /* device phi [sites][n], FP64                           */
+    int32_t sites;
+    int32_t n_empty;
+    int32_t *occ, *empty;   /* device int32 [W][n], [W][n_empty]; updated on accept  */
+    const int32_t *k;       /* device int32 [steps][W]: rank of each proposal        */
+    const int32_t *elec;    /* device int32 [steps][W][k_max]: electrons moved       */
+    const int32_t *slot;    /* device int32 [steps][W][k_max]: indices into empty    */
+    const double *u01;      /* device [steps][W] uniforms (LRX_MH_UNIFORMS) or NULL  */
+    void *u;                /* device bulk [W][k_max][n]: update vectors (scratch)   */
+    void *ratio;            /* device double [steps][W]: ratio of every proposal     */
+    uint8_t *accept;        /* device uint8 [steps][W]: decision applied (in and out
+                               for LRX_MH_MASK, out otherwise)                       */
+} lrx_window_class;
+
+/*
+ * Work order of a window (host only): the (class, walker) pairs of all classes,
+ * heaviest first (n^2 descending, then class, then walker), written to
+ * order[2*i], order[2*i+1].  Returns the number of pairs in *count.
+ *   capacity: pairs that fit in order (LRX_EINVAL if fewer than the walkers).
+ */
+int lrx_window_plan(const lrx_window_class *classes, int32_t n_classes,
+                    int32_t *order, int32_t capacity, int32_t *count);
+
+/*
+ * Advance every walker of every class by `steps` Markov-chain steps in one
+ * persistent launch: per walker and step, the hop vectors u = phi[s'] - phi[s]
+ * (Sec. II.B), the ratio r = det(I + u^T C) of the delayed form (Eqs. det_R,
+ * det_ratio and the C recurrence of Sec. II.C), the decision (`mode`, as for
+ * lrx_metropolis, or LRX_MH_MASK), the slot write a_tau = C,
+ * b_tau = (M_{tau-1} u) R^-T (Eqs. det_a, det_b), the occupancy commit, and
+ * whenever a class's slot reaches K the flush M0 -= sum_t b_t a_t^T
+ * (Eq. delayed_Ainv) of that walker.  Results equal the sequence of per-step
+ * calls (propose_hop, accept_hop, flush_delayed) up to rounding.
+ *   order: device int32 [n_items][2] from lrx_window_plan (copied to the device);
+ *   queue: device uint32 [1] work counter (reset by the call);
+ *   grid: work-groups of the persistent launch (a few per compute unit);
+ *   seed, counter: generator key and step-0 counter (LRX_MH_DEVICE_RNG); the
+ *   key's walker index is the walker's position in the class list (class 0
+ *   first), and step t uses counter + t.
+ * All classes must share the bulk dtype (FP32 or FP64) and k_max.  The refresh
+ * of each class stays a separate lrx_det_refresh call.
+ */
+int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps,
+                   int32_t mode, uint64_t seed, uint64_t counter,
+                   const int32_t *order, int32_t n_items, uint32_t *queue,
+                   int32_t grid, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Low-rank log-determinant and its adjoint                                  */

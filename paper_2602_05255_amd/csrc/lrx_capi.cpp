@@ -50,6 +50,10 @@ static int check_shape(const lrx_shape *s) {
         if (s->k_max > s->n) return LRX_ESHAPE;
         // accept kernel keeps u and C panels in LDS
         if (2 * (size_t)s->k_max * padded_n(s->n, es) * es > 65536) return LRX_EUNSUPPORTED;
+        // delayed accept: u panel, R^-1 and the slot products G in LDS
+        if (s->delay > 0 &&
+            (size_t)s->k_max * padded_n(s->n, es) * es + (size_t)(s->delay + 1) * s->k_max * s->k_max * es > 65536)
+            return LRX_EUNSUPPORTED;
         // delayed accept: a lane owns at most 4 slot columns
         if ((size_t)s->delay * s->k_max > 256) return LRX_ESHAPE;
         // propose keeps b-slot rows I in LDS
@@ -446,6 +450,116 @@ int lrx_metropolis(const lrx_state *st, const void *ratio, const double *u01, ui
     if (mode == LRX_MH_UNIFORMS && !u01) return LRX_EINVAL;
     return hip_rc(metropolis(st->shape.dtype, st->shape.walkers, ratio, u01, seed, counter, mode, st->flags,
                              accept, as_stream(stream)));
+}
+
+// ------------------------------------------------------------------ uneven window
+static int window_check(const lrx_window_class *classes, int32_t n_classes, int64_t *walkers_total) {
+    if (!classes || n_classes < 1 || n_classes > LRX_MAX_CLASSES) return LRX_EINVAL;
+    int64_t total = 0;
+    for (int c = 0; c < n_classes; ++c) {
+        const lrx_window_class &wc = classes[c];
+        if (!wc.state) return LRX_EINVAL;
+        int rc = lrx_validate(wc.state);
+        if (rc) return rc;
+        const lrx_shape &sh = wc.state->shape;
+        if (sh.kind != LRX_DET) return LRX_EKIND;
+        if (sh.dtype != LRX_F32 && sh.dtype != LRX_F64) return LRX_EUNSUPPORTED;
+        if (sh.delay < 1) return LRX_EUNSUPPORTED;
+        if (sh.dtype != classes[0].state->shape.dtype || sh.k_max != classes[0].state->shape.k_max)
+            return LRX_EUNSUPPORTED;
+        if (wc.state->slot >= sh.delay) return LRX_ENEEDFLUSH;
+        if (!wc.table || !wc.occ || !wc.empty || !wc.k || !wc.elec || !wc.slot || !wc.u || !wc.ratio || !wc.accept)
+            return LRX_EINVAL;
+        if (wc.sites < 1 || wc.n_empty < 1) return LRX_ESHAPE;
+        total += sh.walkers;
+    }
+    if (walkers_total) *walkers_total = total;
+    return LRX_OK;
+}
+
+int lrx_window_plan(const lrx_window_class *classes, int32_t n_classes, int32_t *order, int32_t capacity,
+                    int32_t *count) {
+    int64_t total = 0;
+    int rc = window_check(classes, n_classes, &total);
+    if (rc) return rc;
+    if (!order || !count || capacity < total) return LRX_EINVAL;
+    // classes by n descending (stable in the class index), walkers in order within a class
+    int idx[LRX_MAX_CLASSES];
+    for (int c = 0; c < n_classes; ++c) idx[c] = c;
+    for (int i = 1; i < n_classes; ++i)
+        for (int j = i; j > 0 && classes[idx[j]].state->shape.n > classes[idx[j - 1]].state->shape.n; --j) {
+            int t = idx[j];
+            idx[j] = idx[j - 1];
+            idx[j - 1] = t;
+        }
+    int64_t p = 0;
+    for (int ci = 0; ci < n_classes; ++ci) {
+        const int c = idx[ci];
+        for (int w = 0; w < classes[c].state->shape.walkers; ++w) {
+            order[2 * p] = c;
+            order[2 * p + 1] = w;
+            ++p;
+        }
+    }
+    *count = (int32_t)p;
+    return LRX_OK;
+}
+
+int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps, int32_t mode, uint64_t seed,
+                   uint64_t counter, const int32_t *order, int32_t n_items, uint32_t *queue, int32_t grid,
+                   void *stream) {
+    int64_t total = 0;
+    int rc = window_check(classes, n_classes, &total);
+    if (rc) return rc;
+    if (steps < 1 || grid < 1 || !order || !queue || n_items != total) return LRX_EINVAL;
+    if (mode != LRX_MH_UNIFORMS && mode != LRX_MH_DEVICE_RNG && mode != LRX_MH_FORCE && mode != LRX_MH_MASK)
+        return LRX_EINVAL;
+    WindowArgs wa;
+    memset(&wa, 0, sizeof(wa));
+    const int dtype = classes[0].state->shape.dtype;
+    const size_t es = bulk_bytes(dtype);
+    const int per = (int)(16 / es) * 64;     // elements of one 16-byte chunk per lane across a wave
+    size_t lds = 0;
+    uint32_t rng_base = 0;
+    for (int c = 0; c < n_classes; ++c) {
+        const lrx_window_class &wc = classes[c];
+        if (mode == LRX_MH_UNIFORMS && !wc.u01) return LRX_EINVAL;
+        WindowClass &d = wa.cls[c];
+        d.a = step_args(wc.state);
+        d.a.u = wc.u;
+        d.a.hop_table = wc.table;
+        d.a.sites = wc.sites;
+        d.a.n_empty = wc.n_empty;
+        d.a.occ = wc.occ;
+        d.a.empty = wc.empty;
+        d.a.mh_mode = mode == LRX_MH_MASK ? -1 : mode;
+        d.a.seed = seed;
+        d.a.counter = counter;
+        d.a.rng_base = rng_base;
+        int nch = 1;
+        while (nch * per < wc.state->shape.n) nch <<= 1;
+        d.nch = nch;
+        d.k = wc.k;
+        d.elec = wc.elec;
+        d.slot = wc.slot;
+        d.u01 = wc.u01;
+        d.ratio = wc.ratio;
+        d.accept = wc.accept;
+        rng_base += (uint32_t)wc.state->shape.walkers;
+        const size_t l = window_lds_bytes(dtype, wc.state->shape.k_max, wc.state->shape.delay, nch);
+        lds = l > lds ? l : lds;
+    }
+    if (lds == 0 || lds > 160 * 1024) return LRX_EUNSUPPORTED;
+    wa.n_classes = n_classes;
+    wa.steps = steps;
+    wa.n_items = n_items;
+    wa.order = order;
+    wa.queue = queue;
+    rc = hip_rc(det_window(dtype, wa, grid, as_stream(stream)));
+    if (rc == LRX_OK)
+        for (int c = 0; c < n_classes; ++c)
+            classes[c].state->slot = (classes[c].state->slot + steps) % classes[c].state->shape.delay;
+    return rc;
 }
 
 int lrx_hop_commit(int32_t walkers, int32_t n, int32_t n_empty, int32_t k_max, const int32_t *k,

@@ -147,6 +147,65 @@ template <class T, int NV> __device__ __forceinline__ T wave_sum_multi(T (&v)[NV
     return r;
 }
 
+// Shuffle from an arbitrary lane (src taken modulo the wave size).
+__device__ __forceinline__ float shfl_any(float v, int src) { return __shfl(v, src, LRX_WAVE); }
+__device__ __forceinline__ double shfl_any(double v, int src) { return __shfl(v, src, LRX_WAVE); }
+__device__ __forceinline__ cf32 shfl_any(cf32 v, int src) { return {__shfl(v.x, src, LRX_WAVE), __shfl(v.y, src, LRX_WAVE)}; }
+__device__ __forceinline__ cf64 shfl_any(cf64 v, int src) { return {__shfl(v.x, src, LRX_WAVE), __shfl(v.y, src, LRX_WAVE)}; }
+
+// ---------------------------------------------------------------- wave LU
+// LU with partial pivoting (largest modulus, lowest row on ties) of a KM x KM
+// matrix spread over the first KM*KM lanes of a wave: lane l holds entry
+// (l / KM, l % KM).  Every lane of the wave calls it.  The row operations are
+// applied to the identity alongside (b = L^-1 P), then U X = b is solved by
+// back substitution, so on return lane l holds entry (l / KM, l % KM) of the
+// inverse.  det (wide type) and singular (a zero pivot; the inverse is then
+// undefined) are the same on every lane.  All indices are compile-time or
+// wave-uniform, so nothing goes to scratch memory.
+template <class T, int KM>
+__device__ __forceinline__ void wave_lu_det_inv(T a, T &inv, typename Wide<T>::type &det, bool &singular) {
+    using W = typename Wide<T>::type;
+    const int lane = threadIdx.x & (LRX_WAVE - 1);
+    const int i = lane / KM, c = lane % KM;
+    T b = (i == c) ? one<T>() : zero<T>();
+    W d = one<W>();
+    bool sing = false;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        int p = j;
+        double best = absv(shfl_any(a, j * KM + j));
+#pragma unroll
+        for (int ii = j + 1; ii < KM; ++ii) {
+            const double v = absv(shfl_any(a, ii * KM + j));
+            if (v > best) { best = v; p = ii; }
+        }
+        if (p != j) {
+            const T aj = shfl_any(a, j * KM + c), ap = shfl_any(a, p * KM + c);
+            const T bj = shfl_any(b, j * KM + c), bp = shfl_any(b, p * KM + c);
+            if (i == j) { a = ap; b = bp; } else if (i == p) { a = aj; b = bj; }
+            d = -d;
+        }
+        const T piv = shfl_any(a, j * KM + j);
+        d = d * conv<W>(piv);
+        if (is_zero(piv)) { sing = true; continue; }
+        const T l = divv(shfl_any(a, i * KM + j), piv);
+        const T ajc = shfl_any(a, j * KM + c), bjc = shfl_any(b, j * KM + c);
+        if (i > j) { a = fmsc(l, ajc, a); b = fmsc(l, bjc, b); }
+    }
+    T x = b;
+#pragma unroll
+    for (int ii = KM - 1; ii >= 0; --ii) {
+        const T uii = shfl_any(a, ii * KM + ii);
+        if (i == ii) x = divv(x, uii);
+        const T xr = shfl_any(x, ii * KM + c);
+        const T uc = shfl_any(a, i * KM + ii);
+        if (i < ii) x = fmsc(uc, xr, x);
+    }
+    inv = x;
+    det = d;
+    singular = sing;
+}
+
 // ---------------------------------------------------------------- small LU
 // In-place LU with partial pivoting of a k x k matrix held by one thread
 // (row-major, stride KM).  Returns det(R) in the wide type, writes R^-1 into

@@ -25,8 +25,7 @@ template <class T> hipError_t build_hop_t(const HopArgs &a, hipStream_t s) {
 }
 
 template <class T, int KM, int NW, int NI> hipError_t propose_t(const StepArgs &a, hipStream_t s) {
-    const int TE = a.tau * KM;
-    size_t lds = sizeof(T) * ((size_t)KM * TE + (size_t)NW * 64) + sizeof(int) * ((size_t)TE + a.tau);
+    const size_t lds = propose_lds_bytes<T, KM, NW>(a.tau);
     hipLaunchKernelGGL((det_propose_kernel<T, KM, NW, NI>), dim3(a.W), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
 }
@@ -76,8 +75,7 @@ template <class T, int KM, int NEL, bool D> hipError_t accept_t(const StepArgs &
         blocks = (long long)a.W * ((n + rpb - 1) / rpb);
     }
     const int bpw = (n + rpb - 1) / rpb;
-    const int npad = (NEL / vec16<T>()) * vec16<T>() * LRX_WAVE;
-    size_t lds = sizeof(T) * ((size_t)2 * KM * npad + KM * KM);
+    const size_t lds = accept_lds_bytes<T, KM, NEL, D>(a.K);
     const dim3 grid((unsigned)(a.W * bpw)), block(kThreads);
     if (!D || a.K * KM <= LRX_WAVE)   // one slot column per lane
         hipLaunchKernelGGL((det_accept_kernel<T, KM, NEL, RB, 1, D>), grid, block, lds, s, a, rpb, bpw);

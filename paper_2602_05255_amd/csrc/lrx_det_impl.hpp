@@ -72,16 +72,18 @@ __global__ __launch_bounds__(kThreads) void det_build_hop_kernel(HopArgs a) {
 template <class T> constexpr int prop_nv() { return sizeof(T) <= 4 ? 32 : (sizeof(T) == 8 ? 16 : 8); }
 
 // NW waves per walker (one work-group); each thread owns NI entries i = t + 64 NW ii.
+// tid is the thread's index in the work-group (passed in so that a caller
+// looping over steps can keep the derived addresses from living across steps).
 // With NW = 1 every reduction stays inside the wave and no block barrier sits on
 // the critical path.
 template <class T, int KM, int NW, int NI>
-__device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, unsigned char *smem) {
+__device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, unsigned char *smem, int tid) {
     using Wd = typename Wide<T>::type;
     constexpr int NT = 64 * NW;
     constexpr int NVG = prop_nv<T>() >= KM ? prop_nv<T>() : KM;   // values per group reduction
     constexpr int GS0 = NVG / KM;
     constexpr int GS = (GS0 * NI <= 32) ? GS0 : (32 / NI > 0 ? 32 / NI : 1);   // slot columns per group
-    const int tid = threadIdx.x, lane = tid & (LRX_WAVE - 1), wv = tid / LRX_WAVE;
+    const int lane = tid & (LRX_WAVE - 1), wv = tid / LRX_WAVE;
     const int n = a.n, tau = a.tau, KK = a.K * KM, TE = tau * KM;
     const T *M = static_cast<const T *>(a.inv) + (size_t)w * n * n;
     T *u = const_cast<T *>(static_cast<const T *>(a.u)) + (size_t)w * KM * n;
@@ -209,10 +211,7 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
             __syncthreads();
         }
     }
-    // C, and R[c][d] = delta_cd + sum_i u[c][i] C[d][i]
-    T rp[KM * KM];
-#pragma unroll
-    for (int q = 0; q < KM * KM; ++q) rp[q] = zero<T>();
+    // C, and R[c][d] = delta_cd + sum_i u[c][i] C[d][i] (one KM-value reduction per row c of R)
 #pragma unroll
     for (int ii = 0; ii < NI; ++ii) {
         const int i = tid + ii * NT;
@@ -220,43 +219,55 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
 #pragma unroll
             for (int c = 0; c < KM; ++c) C[(size_t)c * n + i] = cv[ii][c];
         }
-#pragma unroll
-        for (int c = 0; c < KM; ++c)
-#pragma unroll
-            for (int d = 0; d < KM; ++d) rp[c * KM + d] = fmac(uv[ii][c], cv[ii][d], rp[c * KM + d]);
     }
-    const T rt = wave_sum_multi<T, KM * KM>(rp);
-    if (lane < KM * KM) s_red[wv * 64 + lane] = rt;
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+        T rp[KM];
+#pragma unroll
+        for (int d = 0; d < KM; ++d) {
+            rp[d] = zero<T>();
+#pragma unroll
+            for (int ii = 0; ii < NI; ++ii) rp[d] = fmac(uv[ii][c], cv[ii][d], rp[d]);
+        }
+        const T rt = wave_sum_multi<T, KM>(rp);
+        if (lane < KM) s_red[wv * 64 + c * KM + lane] = rt;
+    }
     __syncthreads();
 
-    if (tid == 0) {
-        T r[KM * KM], ri[KM * KM];
-        for (int c = 0; c < KM; ++c)
-            for (int d = 0; d < KM; ++d) {
-                T sacc = (c == d) ? one<T>() : zero<T>();
-                if (c < k && d < k)
-                    for (int q = 0; q < NW; ++q) sacc = sacc + s_red[q * 64 + c * KM + d];
-                r[c * KM + d] = sacc;
-                ri[c * KM + d] = zero<T>();
-            }
+    if (wv == 0) {   // R on the first KM*KM lanes of wave 0 (identity beyond the rank), LU across the wave
+        const int c = lane / KM, d = lane % KM;
+        T rv = zero<T>();
+        if (lane < KM * KM) {
+            rv = (c == d) ? one<T>() : zero<T>();
+            if (c < k && d < k)
+                for (int q = 0; q < NW; ++q) rv = rv + s_red[q * 64 + lane];
+        }
+        T iv;
         Wd det;
         bool sing;
-        small_lu_det_inv<T, KM>(r, k, ri, det, sing);
-        for (int c = 0; c < KM * KM; ++c) Rinv[c] = ri[c];
-        if (bad) det = zero<Wd>();
-        *ratio_st = det;
-        static_cast<Wd *>(a.ratio)[w] = det;
-        // A zero or non-finite ratio makes the update impossible (Sec. II.A): the
-        // stash copy is zeroed so accept skips the walker.  Bad indices are sticky.
-        if (bad) atomicOr(a.flags + w, LRX_FLAG_BADINDEX);
-        if (sing || is_zero(det) || !finite_v(det)) *ratio_st = zero<Wd>();
+        wave_lu_det_inv<T, KM>(rv, iv, det, sing);
+        if (lane < KM * KM) Rinv[lane] = (c < k && d < k) ? iv : zero<T>();
+        if (lane == 0) {
+            if (bad) det = zero<Wd>();
+            *ratio_st = det;
+            static_cast<Wd *>(a.ratio)[w] = det;
+            // A zero or non-finite ratio makes the update impossible (Sec. II.A): the
+            // stash copy is zeroed so accept skips the walker.  Bad indices are sticky.
+            if (bad) atomicOr(a.flags + w, LRX_FLAG_BADINDEX);
+            if (sing || is_zero(det) || !finite_v(det)) *ratio_st = zero<Wd>();
+        }
     }
+}
+
+template <class T, int KM, int NW> size_t propose_lds_bytes(int tau) {
+    const size_t TE = (size_t)tau * KM;
+    return sizeof(T) * (KM * TE + (size_t)NW * 64) + sizeof(int) * (TE + (size_t)tau);
 }
 
 template <class T, int KM, int NW, int NI>
 __global__ __launch_bounds__(64 * NW) void det_propose_kernel(StepArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    det_propose_walker<T, KM, NW, NI>(a, blockIdx.x, smem);
+    det_propose_walker<T, KM, NW, NI>(a, blockIdx.x, smem, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ accept
@@ -284,15 +295,11 @@ __device__ __forceinline__ T lane_bcast(T v, int src) {     // src: wave-uniform
     __builtin_memcpy(&o, w, sizeof(T));
     return o;
 }
-__device__ __forceinline__ float shfl_any(float v, int src) { return __shfl(v, src, LRX_WAVE); }
-__device__ __forceinline__ double shfl_any(double v, int src) { return __shfl(v, src, LRX_WAVE); }
-__device__ __forceinline__ cf32 shfl_any(cf32 v, int src) { return {__shfl(v.x, src, LRX_WAVE), __shfl(v.y, src, LRX_WAVE)}; }
-__device__ __forceinline__ cf64 shfl_any(cf64 v, int src) { return {__shfl(v.x, src, LRX_WAVE), __shfl(v.y, src, LRX_WAVE)}; }
 
 template <class T>
 struct AcceptCtx {
     T *M, *fa, *fb;
-    const T *G;
+    const T *s_g;           // slot products G[te][c] staged in LDS (delayed update)
     const T *s_u, *s_c, *s_ri;
     int n, KK, tau, TE, q0, q1, npad, wv, lane;
     bool vec_ok;
@@ -308,15 +315,6 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
     T rrow[KC];
 #pragma unroll
     for (int d = 0; d < KC; ++d) rrow[d] = c.s_ri[my_c * KM + d];
-    // Slot products G[te][c] (= a_te . u_c) for the slot columns this lane owns, te = lane + 64 m.
-    T g[MG][KC];
-#pragma unroll
-    for (int m = 0; m < MG; ++m)
-#pragma unroll
-        for (int cc = 0; cc < KC; ++cc) {
-            const int te = lane + m * LRX_WAVE;
-            g[m][cc] = (DELAYED && te < c.TE) ? c.G[(size_t)te * KM + cc] : zero<T>();
-        }
     const int n = c.n;
     // Software pipeline: the rows of the next batch are requested before the
     // current batch is reduced, so two batches of loads are in flight per wave.
@@ -370,13 +368,17 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
 #pragma unroll
             for (int m = 0; m < MG; ++m) {
                 if (m * LRX_WAVE < c.TE) {
+                    // slot products G[te][c] (= a_te . u_c) of the column this lane owns, te = lane + 64 m
                     const int te = lane + m * LRX_WAVE;
+                    T g[KC];
+#pragma unroll
+                    for (int cc = 0; cc < KC; ++cc) g[cc] = te < c.TE ? c.s_g[te * KM + cc] : zero<T>();
 #pragma unroll
                     for (int r = 0; r < RB; ++r) {
                         const int q = qb + r;
                         const T bv = (te < c.TE && q < c.q1) ? c.fb[(size_t)q * c.KK + te] : zero<T>();
 #pragma unroll
-                        for (int cc = 0; cc < KC; ++cc) p[r * KC + cc] = fmsc(bv, g[m][cc], p[r * KC + cc]);
+                        for (int cc = 0; cc < KC; ++cc) p[r * KC + cc] = fmsc(bv, g[cc], p[r * KC + cc]);
                     }
                 }
             }
@@ -431,11 +433,11 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
 // per-walker bookkeeping (log|det|, phase, slot rank, decision, commit).
 template <class T, int KM, int NEL, int RB, int MG, bool DELAYED>
 __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, int rb, int q0, int q1,
-                                                      unsigned char *smem) {
+                                                      unsigned char *smem, int tid) {
     using Wd = typename Wide<T>::type;
     constexpr int V = vec16<T>();
     constexpr int NCH = NEL / V;
-    const int tid = threadIdx.x, lane = tid & (LRX_WAVE - 1), wv = tid / LRX_WAVE;
+    const int lane = tid & (LRX_WAVE - 1), wv = tid / LRX_WAVE;
     const int n = a.n, KK = a.K * KM, tau = a.tau, TE = tau * KM;
 
     T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
@@ -455,7 +457,7 @@ __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, 
     uint8_t acc;
     if (a.mh_mode >= 0) {   // fused Metropolis decision (identical in every block of the walker)
         acc = mh_decide<Wd>(ratio, fl, a.mh_mode, a.mh_mode == LRX_MH_UNIFORMS ? a.u01[w] : 0.0, a.seed,
-                            a.counter, (uint32_t)w);
+                            a.counter, (uint32_t)w + a.rng_base);
     } else {
         acc = a.accept[w];
     }
@@ -493,9 +495,10 @@ __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, 
     }
 
     const int npad = NCH * V * LRX_WAVE;        // padded row length held in LDS
-    T *s_u = reinterpret_cast<T *>(smem);       // [KM][npad]
-    T *s_c = s_u + (size_t)KM * npad;           // [KM][npad]
-    T *s_ri = s_c + (size_t)KM * npad;          // [KM*KM]
+    T *s_u = reinterpret_cast<T *>(smem);                   // [KM][npad]
+    T *s_c = DELAYED ? s_u : s_u + (size_t)KM * npad;       // [KM][npad], plain update only
+    T *s_ri = s_c + (size_t)KM * npad;                      // [KM*KM]
+    T *s_g = s_ri + KM * KM;                                // [TE][KM], delayed update only
     for (int idx = tid; idx < kc * npad; idx += kThreads) {
         int c = idx / npad, j = idx - c * npad;
         bool ok = c < k && j < n;
@@ -506,6 +509,8 @@ __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, 
         const int c = tid / KM, d = tid - c * KM;
         s_ri[tid] = (c < k && d < k) ? Rinv[tid] : zero<T>();
     }
+    if (DELAYED)
+        for (int idx = tid; idx < TE * KM; idx += kThreads) s_g[idx] = G[idx];
     if (DELAYED) {   // a_tau = C for this block's rows; b_tau columns beyond kc are zero
         for (int idx = tid; idx < KM * (q1 - q0); idx += kThreads) {
             int c = idx / (q1 - q0), q = q0 + idx - c * (q1 - q0);
@@ -515,7 +520,7 @@ __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, 
     }
     __syncthreads();
 
-    AcceptCtx<T> ctx{M, fa, fb, G, s_u, s_c, s_ri, n, KK, tau, TE, q0, q1, npad, wv, lane, a.aligned != 0};
+    AcceptCtx<T> ctx{M, fa, fb, s_g, s_u, s_c, s_ri, n, KK, tau, TE, q0, q1, npad, wv, lane, a.aligned != 0};
     if (kc == 1) {
         accept_rows<T, 1, KM, NEL, RB, MG, DELAYED>(ctx);
     } else if (kc == 2) {
@@ -535,7 +540,7 @@ __global__ __launch_bounds__(kThreads) void det_accept_kernel(StepArgs a, int ro
     const int rb = lb - w * blocks_per_walker;
     if (w >= a.W) return;
     const int q0 = rb * rows_per_block;
-    det_accept_rows_block<T, KM, NEL, RB, MG, DELAYED>(a, w, rb, q0, min(a.n, q0 + rows_per_block), smem);
+    det_accept_rows_block<T, KM, NEL, RB, MG, DELAYED>(a, w, rb, q0, min(a.n, q0 + rows_per_block), smem, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ Metropolis
@@ -563,6 +568,13 @@ __global__ void hop_commit_kernel(int W, int n, int n_empty, int KM, const int32
         *po = *pe;
         *pe = t;
     }
+}
+
+// Dynamic LDS of det_accept_rows_block: u (and C for the plain update) panels
+// padded to whole 16-byte chunks per lane, R^-1, and the slot products G.
+template <class T, int KM, int NEL, bool DELAYED> size_t accept_lds_bytes(int K) {
+    constexpr size_t npad = (size_t)(NEL / vec16<T>()) * vec16<T>() * LRX_WAVE;
+    return sizeof(T) * ((DELAYED ? 1 : 2) * KM * npad + KM * KM + (DELAYED ? (size_t)K * KM * KM : 0));
 }
 
 // Rows held per wave batch: the RB x NEL row values plus the RB x KM partial

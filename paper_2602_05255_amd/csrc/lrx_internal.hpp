@@ -54,6 +54,7 @@ struct StepArgs {
     int mh_mode;
     const double *u01;
     uint64_t seed, counter;
+    uint32_t rng_base;      // added to the walker index in the device generator's key
 };
 
 struct HopArgs {
@@ -105,6 +106,25 @@ hipError_t hop_commit(int W, int n, int n_empty, int KM, const int32_t *k,
                       const int32_t *elec, const int32_t *slot,
                       const uint8_t *accept, int32_t *occ, int32_t *empty,
                       hipStream_t s);
+
+// Persistent window over an uneven batch (lrx_window.hip).
+constexpr int kMaxClasses = 8;
+struct WindowClass {
+    StepArgs a;              // step-0 arguments; a.tau = slot at the window start
+    int nch;                 // 16-byte row chunks per lane, rounded to a power of two
+    const int32_t *k, *elec, *slot;   // draws [steps][W], [steps][W][KM]
+    const double *u01;       // [steps][W] (uniforms mode) or NULL
+    void *ratio;             // wide [steps][W]
+    uint8_t *accept;         // [steps][W]
+};
+struct WindowArgs {
+    WindowClass cls[kMaxClasses];
+    int n_classes, steps, n_items;
+    const int32_t *order;    // [n_items][2] = (class, walker), heaviest first
+    uint32_t *queue;         // work counter, reset by the launch
+};
+size_t window_lds_bytes(int dtype, int KM, int K, int nch_max);
+hipError_t det_window(int dtype, const WindowArgs &a, int grid, hipStream_t s);
 
 // Init / refresh (lrx_factor.hip).
 struct FactorArgs {

@@ -1,0 +1,184 @@
+// Persistent window kernel: one launch advances every walker of an uneven
+// batch (several size classes n, one state per class) by `steps` delayed
+// steps (Sec. II.C), flushing each walker's slots into M0 whenever its window
+// fills (Eq. delayed_Ainv).
+//
+// Work items are whole walkers, handed out heaviest first (n^2 descending, a
+// longest-processing-time order) from a device counter, so the large classes
+// start early and the small ones fill the tail.  A work-group of four waves
+// keeps one walker for the whole window: propose -> decision -> delayed
+// accept -> commit, step after step, with only work-group barriers between
+// the phases (the slot data written by one step is read by the next inside
+// the same work-group).  The size class picks the row-chunk specialisation of
+// the step functions shared with the per-step kernels.
+#include "lrx_det_impl.hpp"
+#include "lrx_flush_impl.hpp"
+
+namespace {
+
+using namespace lrxdet;
+using namespace lrxfl;
+using lrx::StepArgs;
+using lrx::WindowArgs;
+using lrx::WindowClass;
+
+constexpr int kWindowThreads = 256;   // det_propose_walker with NW = 4 and the accept rows share it
+
+template <class T>
+__device__ __forceinline__ void window_flush(const StepArgs &a, int w, int tau, unsigned char *smem) {
+    const int n = a.n, KK = a.K * a.KM;
+    int *s_live = reinterpret_cast<int *>(smem + FlushLds<T>::bytes);
+    int *s_nl = s_live + KK;
+    const int *kslot = reinterpret_cast<const int *>(a.stash + (size_t)w * a.L.stride + a.L.kslot);
+    const int nl = det_live_columns(kslot, tau, a.KM, s_live, s_nl);
+    T *s_b = reinterpret_cast<T *>(smem);
+    T *s_a = s_b + 64 * FlushLds<T>::SB;
+    T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
+    const T *fa = static_cast<const T *>(a.fa) + (size_t)w * KK * n;
+    const T *fb = static_cast<const T *>(a.fb) + (size_t)w * n * KK;
+    const int tpd = (n + 63) / 64;
+    for (int tile = 0; tile < tpd * tpd; ++tile) {
+        const int ti = tile / tpd, tj = tile - ti * tpd;
+        det_flush_tile<T>(M, fa, fb, n, KK, s_live, nl, ti * 64, tj * 64, s_b, s_a);
+    }
+    __syncthreads();
+}
+
+template <class T, int KM, int NCH>
+__device__ __forceinline__ void window_walker(const WindowClass &wc, int steps, int w, unsigned char *smem) {
+    using Wd = typename Wide<T>::type;
+    constexpr int V = vec16<T>();
+    constexpr int NEL = NCH * V;
+    constexpr int NI = (NCH * V / 4) > 1 ? NCH * V / 4 : 1;   // entries per thread of a 256-wide column
+    // Half the per-step kernel's row batch: two work-groups share a CU here, so
+    // one can propose while the other streams rows.
+    constexpr int RB0 = rows_per_batch<T, NEL, KM>();
+    constexpr int RB = RB0 > 1 ? RB0 / 2 : 1;
+    StepArgs a = wc.a;
+    const int W = a.W, K = a.K;
+    int tau = a.tau;
+    for (int t = 0; t < steps; ++t) {
+        a.tau = tau;
+        a.k = wc.k + (size_t)t * W;
+        a.rows = wc.elec + (size_t)t * W * KM;
+        a.slot = wc.slot + (size_t)t * W * KM;
+        a.u01 = wc.u01 ? wc.u01 + (size_t)t * W : nullptr;
+        a.ratio = static_cast<Wd *>(wc.ratio) + (size_t)t * W;
+        a.accept = wc.accept + (size_t)t * W;
+        a.counter = wc.a.counter + (uint64_t)t;
+        // The thread index is made opaque once per step so that the compiler
+        // recomputes the per-thread addresses of each phase instead of keeping
+        // them all live across the whole window.
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        det_propose_walker<T, KM, 4, NI>(a, w, smem, tid);
+        __syncthreads();
+        tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        det_accept_rows_block<T, KM, NEL, RB, 4, true>(a, w, 0, 0, a.n, smem, tid);
+        __syncthreads();
+        if (++tau == K) {
+            window_flush<T>(a, w, K, smem);
+            tau = 0;
+        }
+    }
+}
+
+template <class T, int KM>
+__global__ __launch_bounds__(kWindowThreads, 2) void det_window_kernel(WindowArgs wa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
+    constexpr int V = vec16<T>();
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(wa.queue, 1u);
+        __syncthreads();
+        // The item is block-uniform: keep it (and everything addressed through it) in scalar registers.
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= wa.n_items) break;     // every work-group leaves once the list is drained
+        const int c = __builtin_amdgcn_readfirstlane(wa.order[2 * item]);
+        const int w = __builtin_amdgcn_readfirstlane(wa.order[2 * item + 1]);
+        const WindowClass &wc = wa.cls[c];
+        switch (wc.nch) {
+            case 1: window_walker<T, KM, 1>(wc, wa.steps, w, smem); break;
+            case 2: window_walker<T, KM, 2>(wc, wa.steps, w, smem); break;
+            case 4: window_walker<T, KM, 4>(wc, wa.steps, w, smem); break;
+            case 8: if constexpr (V <= 2) window_walker<T, KM, 8>(wc, wa.steps, w, smem); break;
+            default: break;
+        }
+    }
+}
+
+__global__ void window_reset_kernel(uint32_t *queue) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0u;
+}
+
+template <class T, int KM> size_t window_lds_t(int K, int nch_max) {
+    constexpr int V = vec16<T>();
+    const size_t npad = (size_t)nch_max * V * LRX_WAVE;
+    const size_t acc = sizeof(T) * (KM * npad + KM * KM + (size_t)K * KM * KM);
+    const size_t prop = propose_lds_bytes<T, KM, 4>(K);
+    const size_t fl = FlushLds<T>::bytes + sizeof(int) * ((size_t)K * KM + 1);
+    return acc > prop ? (acc > fl ? acc : fl) : (prop > fl ? prop : fl);
+}
+
+template <class T, int KM> hipError_t window_t(const WindowArgs &a, int grid, hipStream_t s) {
+    int nch_max = 1;
+    for (int c = 0; c < a.n_classes; ++c) nch_max = a.cls[c].nch > nch_max ? a.cls[c].nch : nch_max;
+    const size_t lds = window_lds_t<T, KM>(a.cls[0].a.K > 0 ? a.cls[0].a.K : 1, nch_max);
+    size_t need = lds;
+    for (int c = 1; c < a.n_classes; ++c) {
+        const size_t l = window_lds_t<T, KM>(a.cls[c].a.K, nch_max);
+        need = l > need ? l : need;
+    }
+    if (need > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&det_window_kernel<T, KM>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(window_reset_kernel, dim3(1), dim3(64), 0, s, a.queue);
+    hipLaunchKernelGGL((det_window_kernel<T, KM>), dim3((unsigned)grid), dim3(kWindowThreads), need, s, a);
+    return hipGetLastError();
+}
+
+template <class T> hipError_t window_k(const WindowArgs &a, int grid, hipStream_t s) {
+    switch (a.cls[0].a.KM) {
+        case 1: return window_t<T, 1>(a, grid, s);
+        case 2: return window_t<T, 2>(a, grid, s);
+        case 4: return window_t<T, 4>(a, grid, s);
+        case 8: return window_t<T, 8>(a, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class T> size_t window_lds_k(int KM, int K, int nch_max) {
+    switch (KM) {
+        case 1: return window_lds_t<T, 1>(K, nch_max);
+        case 2: return window_lds_t<T, 2>(K, nch_max);
+        case 4: return window_lds_t<T, 4>(K, nch_max);
+        case 8: return window_lds_t<T, 8>(K, nch_max);
+    }
+    return 0;
+}
+
+}  // namespace
+
+namespace lrx {
+
+size_t window_lds_bytes(int dtype, int KM, int K, int nch_max) {
+    switch (dtype) {
+        case LRX_F32: return window_lds_k<float>(KM, K, nch_max);
+        case LRX_F64: return window_lds_k<double>(KM, K, nch_max);
+    }
+    return 0;
+}
+
+hipError_t det_window(int dtype, const WindowArgs &a, int grid, hipStream_t s) {
+    switch (dtype) {
+        case LRX_F32: return window_k<float>(a, grid, s);
+        case LRX_F64: return window_k<double>(a, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lrx

@@ -162,6 +162,22 @@ def uneven_sizes(rng: np.random.Generator, walkers: int, sizes):
     return sizes[rng.integers(0, len(sizes), size=walkers)]
 
 
+def uneven_inputs(wl: Workload, walkers: int | None = None, seed_offset: int = 0):
+    """Size classes of the uneven workload: per-walker n drawn from the size list,
+    one Phi (2n x n, N(0,1)) per size, random occupancies.  Returns (classes, rng)
+    with classes a list of dicts {n, phi, occ, empty, walkers} in size order."""
+    rng = generator(wl.seed + seed_offset)
+    w = wl.walkers if walkers is None else walkers
+    sizes = uneven_sizes(rng, w, wl.extra["sizes"])
+    classes = []
+    for n in sorted(set(int(x) for x in sizes)):
+        ids = np.nonzero(sizes == n)[0]
+        phi = normal(rng, (2 * n, n))
+        occ, emp = occupancy(rng, len(ids), 2 * n, n)
+        classes.append({"n": n, "phi": phi, "occ": occ, "empty": emp, "walkers": ids})
+    return classes, rng
+
+
 def lowrank_inputs(wl: Workload, samples: int | None = None, sites: int | None = None,
                    n: int | None = None, seed_offset: int = 0):
     """Phi [L][n], occ [S][n], B, C [S][n][r] (CN(0, 0.1)), loss weights w [S] (CN(0, 1))."""

@@ -28,8 +28,9 @@ LRX_OK, LRX_EINVAL, LRX_EUNSUPPORTED, LRX_ESHAPE, LRX_ENEEDFLUSH, LRX_EODD, LRX_
 LRX_DET, LRX_PF = 0, 1
 LRX_F32, LRX_F64, LRX_C64, LRX_C128 = 0, 1, 2, 3
 LRX_FLAG_SINGULAR_R, LRX_FLAG_NONFINITE, LRX_FLAG_SINGULAR_A, LRX_FLAG_BADINDEX = 1, 2, 4, 8
-LRX_MH_UNIFORMS, LRX_MH_DEVICE_RNG, LRX_MH_FORCE = 0, 1, 2
+LRX_MH_UNIFORMS, LRX_MH_DEVICE_RNG, LRX_MH_FORCE, LRX_MH_MASK = 0, 1, 2, 3
 LRX_MAX_N, LRX_MAX_KMAX_DET, LRX_MAX_KMAX_PF, LRX_MAX_DELAY = 1024, 8, 1, 64
+LRX_MAX_CLASSES = 8
 
 DTYPE_CODE = {torch.float32: LRX_F32, torch.float64: LRX_F64,
               torch.complex64: LRX_C64, torch.complex128: LRX_C128}
@@ -53,6 +54,14 @@ class lrx_state(ctypes.Structure):
                 ("inv", ctypes.c_void_p), ("fa", ctypes.c_void_p), ("fb", ctypes.c_void_p),
                 ("stash", ctypes.c_void_p), ("logabs", ctypes.c_void_p), ("phase", ctypes.c_void_p),
                 ("flags", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+class lrx_window_class(ctypes.Structure):
+    _fields_ = [("state", ctypes.POINTER(lrx_state)), ("table", ctypes.c_void_p), ("sites", ctypes.c_int32),
+                ("n_empty", ctypes.c_int32), ("occ", ctypes.c_void_p), ("empty", ctypes.c_void_p),
+                ("k", ctypes.c_void_p), ("elec", ctypes.c_void_p), ("slot", ctypes.c_void_p),
+                ("u01", ctypes.c_void_p), ("u", ctypes.c_void_p), ("ratio", ctypes.c_void_p),
+                ("accept", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -85,6 +94,10 @@ _SIGS = {
     "lrx_metropolis": ([ctypes.POINTER(lrx_state), _P, _P, ctypes.c_uint64, ctypes.c_uint64, _I, _P, _P],
                        ctypes.c_int),
     "lrx_hop_commit": ([_I, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_window_plan": ([ctypes.POINTER(lrx_window_class), _I, _P, _I, ctypes.POINTER(ctypes.c_int32)],
+                        ctypes.c_int),
+    "lrx_det_window": ([ctypes.POINTER(lrx_window_class), _I, _I, _I, ctypes.c_uint64, ctypes.c_uint64, _P, _I,
+                        _P, _I, _P], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -370,3 +383,64 @@ def lrx_hop_commit(walkers, n, n_empty, k_max, k, elec, slot, accept, occ, empty
     _check(_lib.lrx_hop_commit(int(walkers), int(n), int(n_empty), int(k_max), _dev(k, "k"), _dev(elec, "elec"),
                                _dev(slot, "slot"), _dev(accept, "accept"), _dev(occ, "occ"),
                                _dev(empty, "empty"), _stream(stream)), "lrx_hop_commit")
+
+
+# ------------------------------------------------------------------ uneven window
+class WindowClass:
+    """Device buffers of one size class for lrx_det_window.
+
+    st: State (DET, FP32/FP64, delay >= 1); table: phi [sites][n] FP64; occ/empty:
+    int32 [W][n] / [W][n_empty]; k: int32 [steps][W]; elec/slot: int32
+    [steps][W][k_max]; u: bulk [W][k_max][n]; ratio: float64 [steps][W]; accept:
+    uint8 [steps][W]; u01: float64 [steps][W] or None.
+    """
+
+    def __init__(self, st, table, occ, empty, k, elec, slot, u, ratio, accept, u01=None):
+        self.st, self.table, self.occ, self.empty = st, table, occ, empty
+        self.k, self.elec, self.slot, self.u, self.ratio, self.accept, self.u01 = k, elec, slot, u, ratio, accept, u01
+
+    def c_struct(self, steps):
+        st = self.st
+        W, KM, n = st.walkers, st.k_max, st.n
+        n_empty = int(self.empty.shape[1])
+        _dev(self.table, "table", torch.float64)
+        _dev(self.occ, "occ", torch.int32, (W, n))
+        _dev(self.empty, "empty", torch.int32, (W, n_empty))
+        _dev(self.k, "k", torch.int32, (steps, W))
+        _dev(self.elec, "elec", torch.int32, (steps, W, KM))
+        _dev(self.slot, "slot", torch.int32, (steps, W, KM))
+        _dev(self.u, "u", st.dtype, (W, KM, n))
+        _dev(self.ratio, "ratio", torch.float64, (steps, W))
+        _dev(self.accept, "accept", torch.uint8, (steps, W))
+        pu = _dev(self.u01, "u01", torch.float64, (steps, W), allow_none=True)
+        return lrx_window_class(ctypes.pointer(st.c), self.table.data_ptr(), int(self.table.shape[0]), n_empty,
+                                self.occ.data_ptr(), self.empty.data_ptr(), self.k.data_ptr(),
+                                self.elec.data_ptr(), self.slot.data_ptr(), pu, self.u.data_ptr(),
+                                self.ratio.data_ptr(), self.accept.data_ptr())
+
+
+def _class_array(classes, steps):
+    arr = (lrx_window_class * len(classes))()
+    for i, c in enumerate(classes):
+        arr[i] = c.c_struct(steps) if isinstance(c, WindowClass) else c
+    return arr
+
+
+def lrx_window_plan(classes, steps=1):
+    """Host int32 [n_items][2] work order (class, walker), heaviest first."""
+    arr = _class_array(classes, steps)
+    total = sum(int(arr[i].state.contents.shape.walkers) for i in range(len(classes)))
+    order = torch.empty(max(total, 1), 2, dtype=torch.int32)
+    count = ctypes.c_int32()
+    _check(_lib.lrx_window_plan(arr, len(classes), ctypes.c_void_p(order.data_ptr()), int(total),
+                                ctypes.byref(count)), "lrx_window_plan")
+    return order[: count.value]
+
+
+def lrx_det_window(classes, steps, mode, seed, counter, order, queue, grid, stream=None):
+    arr = _class_array(classes, steps)
+    _dev(order, "order", torch.int32)
+    _dev(queue, "queue", torch.int32)
+    _check(_lib.lrx_det_window(arr, len(classes), int(steps), int(mode), ctypes.c_uint64(seed),
+                               ctypes.c_uint64(counter), _dev(order, "order"), int(order.shape[0]),
+                               _dev(queue, "queue"), int(grid), _stream(stream)), "lrx_det_window")

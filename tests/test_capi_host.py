@@ -164,3 +164,69 @@ def test_pf_refresh_sites_check():
     lib = lrx._lib
     st = fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64, n=8)
     assert lib.lrx_pf_refresh(ctypes.byref(st), P, 4, P, None, None) == lrx.LRX_ESHAPE
+
+
+def fake_class(st, null=()):
+    p = {f: 0x30000 + 0x100 * i for i, f in
+         enumerate(("table", "occ", "empty", "k", "elec", "slot", "u01", "u", "ratio", "accept"))}
+    for f in null:
+        p[f] = 0
+    return lrx.lrx_window_class(ctypes.pointer(st), p["table"], 2 * st.shape.n, st.shape.n, p["occ"], p["empty"],
+                                p["k"], p["elec"], p["slot"], p["u01"], p["u"], p["ratio"], p["accept"])
+
+
+def classes_of(*cls):
+    arr = (lrx.lrx_window_class * len(cls))()
+    for i, c in enumerate(cls):
+        arr[i] = c
+    return arr
+
+
+def test_window_plan_is_heaviest_first():
+    lib = lrx._lib
+    sts = [fake_state(W=3, n=64, k_max=4, delay=4, dtype=lrx.LRX_F32),
+           fake_state(W=2, n=256, k_max=4, delay=8, dtype=lrx.LRX_F32),
+           fake_state(W=4, n=128, k_max=4, delay=4, dtype=lrx.LRX_F32),
+           fake_state(W=1, n=256, k_max=4, delay=2, dtype=lrx.LRX_F32)]
+    arr = classes_of(*[fake_class(s) for s in sts])
+    order = (ctypes.c_int32 * 20)()
+    count = ctypes.c_int32()
+    assert lib.lrx_window_plan(arr, 4, order, 20, ctypes.byref(count)) == lrx.LRX_OK
+    pairs = [(order[2 * i], order[2 * i + 1]) for i in range(count.value)]
+    assert pairs == [(1, 0), (1, 1), (3, 0), (2, 0), (2, 1), (2, 2), (2, 3), (0, 0), (0, 1), (0, 2)]
+    assert lib.lrx_window_plan(arr, 4, order, 9, ctypes.byref(count)) == lrx.LRX_EINVAL
+
+
+def test_window_validation():
+    lib = lrx._lib
+    P2 = ctypes.c_void_p(0x40000)
+
+    def call(arr, n_cls, steps=4, mode=lrx.LRX_MH_FORCE, n_items=None, grid=8):
+        if n_items is None:
+            n_items = sum(arr[i].state.contents.shape.walkers for i in range(n_cls))
+        return lib.lrx_det_window(arr, n_cls, steps, mode, 1, 0, P2, n_items, P2, grid, None)
+
+    ok = fake_state(W=4, n=64, k_max=4, delay=4, dtype=lrx.LRX_F32)
+    base = fake_class(ok)
+    assert lib.lrx_det_window(None, 1, 4, lrx.LRX_MH_FORCE, 1, 0, P2, 4, P2, 8, None) == lrx.LRX_EINVAL
+    assert call(classes_of(base), 0) == lrx.LRX_EINVAL
+    assert call(classes_of(*[base] * 9), 9) == lrx.LRX_EINVAL
+    assert call(classes_of(base), 1, steps=0) == lrx.LRX_EINVAL
+    assert call(classes_of(base), 1, grid=0) == lrx.LRX_EINVAL
+    assert call(classes_of(base), 1, n_items=3) == lrx.LRX_EINVAL
+    assert call(classes_of(base), 1, mode=7) == lrx.LRX_EINVAL
+    assert call(classes_of(fake_class(ok, null=("u01",))), 1, mode=lrx.LRX_MH_UNIFORMS) == lrx.LRX_EINVAL
+    for f in ("table", "occ", "empty", "k", "elec", "slot", "u", "ratio", "accept"):
+        assert call(classes_of(fake_class(ok, null=(f,))), 1) == lrx.LRX_EINVAL, f
+    cplx = fake_state(W=4, n=64, k_max=4, delay=4, dtype=lrx.LRX_C64)
+    assert call(classes_of(fake_class(cplx)), 1) == lrx.LRX_EUNSUPPORTED
+    plain = fake_state(W=4, n=64, k_max=4, delay=0, dtype=lrx.LRX_F32)
+    assert call(classes_of(fake_class(plain)), 1) == lrx.LRX_EUNSUPPORTED
+    other_dtype = fake_state(W=4, n=64, k_max=4, delay=4, dtype=lrx.LRX_F64)
+    assert call(classes_of(base, fake_class(other_dtype)), 2) == lrx.LRX_EUNSUPPORTED
+    other_k = fake_state(W=4, n=64, k_max=2, delay=4, dtype=lrx.LRX_F32)
+    assert call(classes_of(base, fake_class(other_k)), 2) == lrx.LRX_EUNSUPPORTED
+    pf = fake_state(kind=lrx.LRX_PF, W=4, n=64, k_max=1, delay=4, dtype=lrx.LRX_F32)
+    assert call(classes_of(fake_class(pf)), 1) == lrx.LRX_EKIND
+    full = fake_state(W=4, n=64, k_max=4, delay=4, slot=4, dtype=lrx.LRX_F32)
+    assert call(classes_of(fake_class(full)), 1) == lrx.LRX_ENEEDFLUSH

@@ -1,0 +1,177 @@
+"""Persistent window over uneven batches vs the full-recompute oracle (Sec. II.C)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from gpu_util import EPS64, det_ratio_bound, ratio_err, rel_err, say
+from test_rng_host import philox4x32_10
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as orc  # noqa: E402
+from paper_2602_05255_amd import inputs as gen  # noqa: E402
+from paper_2602_05255_amd import lrx  # noqa: E402
+from paper_2602_05255_amd.uneven import UnevenWalkers  # noqa: E402
+
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+def small_classes(g, sizes, walkers):
+    out = []
+    for n, W in zip(sizes, walkers):
+        phi = gen.normal(g, (2 * n, n))
+        occ, emp = gen.occupancy(g, W, 2 * n, n)
+        out.append({"n": n, "phi": phi, "occ": occ, "empty": emp})
+    return out
+
+
+def oracle_window(classes, draws, u01s, mode):
+    """Run the oracle chains through the window; returns per class the ratios,
+    the decisions, the ratio error bounds and the chain."""
+    res = []
+    for cls, (k, e, s), u in zip(classes, draws, u01s):
+        chain = orc.DetChain(cls["phi"], cls["occ"], cls["empty"])
+        rs, masks, bounds = [], [], []
+        for t in range(k.shape[0]):
+            inv0, occ0 = chain.inv.copy(), chain.book.occ.copy()
+            r = chain.propose(k[t], e[t], s[t])
+            after = chain.book.proposed(k[t], e[t], s[t])
+            bounds.append(det_ratio_bound(cls["phi"], occ0, after, inv0, k[t], e[t]))
+            m = orc.metropolis(r, u[t]) if mode == "mh" else np.isfinite(r) & (r != 0)
+            chain.accept(k[t], e[t], s[t], m)
+            rs.append(r)
+            masks.append(m)
+        res.append((np.array(rs), np.array(masks), np.array(bounds), chain))
+    return res
+
+
+@pytest.mark.parametrize("dt,delays,steps", [
+    ("f64", (4, 5, 3, 7), 11),     # several flushes inside one launch, ragged n
+    ("f64", (16, 16, 16, 16), 16),  # one flush at the end of the window
+])
+def test_window_matches_oracle(dt, delays, steps):
+    say(f"window {dt} delays={delays} steps={steps}")
+    g = gen.generator(900 + steps)
+    sizes, walkers = (24, 64, 100, 130), (5, 4, 3, 2)
+    classes = small_classes(g, sizes, walkers)
+    k_max, ranks = 4, (1, 2, 3, 4)
+    draws = [gen.hop_draws_batch(g, steps, W, n, n, ranks, k_max) for n, W in zip(sizes, walkers)]
+    u01 = [g.random((steps, W)) for W in walkers]
+    ref = oracle_window(classes, draws, u01, "mh")
+    uw = UnevenWalkers(torch.float64 if dt == "f64" else torch.float32, classes, k_max, list(delays), steps,
+                       grid=7)
+    uw.set_draws(draws)
+    uw.window(mode=lrx.LRX_MH_MASK, mask=[m for _, m, _, _ in ref])
+    torch.cuda.synchronize()
+    for p, (r_o, m_o, bnd, chain), K in zip(uw.parts, ref, delays):
+        r = p.ratio.cpu().numpy()
+        tol = np.maximum(1e-10, 8 * EPS64 * np.sqrt(1.0 + np.arange(steps))[:, None] * bnd)
+        err = ratio_err(r, r_o)
+        assert np.all(err <= tol), (p.st.n, err.max())
+        np.testing.assert_array_equal(p.accept.cpu().numpy().astype(bool), m_o)
+        np.testing.assert_array_equal(p.occ.cpu().numpy(), chain.book.occ)
+        np.testing.assert_array_equal(p.empty.cpu().numpy(), chain.book.empty)
+        assert p.st.slot == steps % K
+        np.testing.assert_allclose(p.st.logabs.cpu().numpy(), chain.logabs, atol=1e-9)
+    for inv, (_, _, _, chain) in zip(uw.inverses(), ref):
+        assert rel_err(inv.cpu().numpy(), chain.inv, axis=(1, 2)).max() <= 1e-10
+
+
+def test_window_fp32_forced_and_second_window():
+    """FP32 bulk, every proposal applied, two windows back to back (the second
+    starts from a partly filled delay window)."""
+    say("window f32")
+    g = gen.generator(950)
+    sizes, walkers = (64, 128, 256), (6, 4, 3)
+    classes = small_classes(g, sizes, walkers)
+    steps, k_max = 6, 8
+    uw = UnevenWalkers(torch.float32, classes, k_max, [4, 8, 5], steps, grid=5)
+    chains = [orc.DetChain(c["phi"], c["occ"], c["empty"]) for c in classes]
+    worst = 0.0
+    for win in range(2):
+        draws = [gen.hop_draws_batch(g, steps, W, n, n, (1, 2, 4, 8), k_max) for n, W in zip(sizes, walkers)]
+        uw.set_draws(draws)
+        uw.window(mode=lrx.LRX_MH_FORCE)
+        torch.cuda.synchronize()
+        for p, chain, (k, e, s) in zip(uw.parts, chains, draws):
+            r = p.ratio.cpu().numpy()
+            for t in range(steps):
+                inv0, occ0 = chain.inv.copy(), chain.book.occ.copy()
+                r_o = chain.propose(k[t], e[t], s[t])
+                bnd = det_ratio_bound(p.table.cpu().numpy(), occ0, chain.book.proposed(k[t], e[t], s[t]), inv0,
+                                      k[t], e[t])
+                err = ratio_err(r[t], r_o)
+                worst = max(worst, float(err.max()))
+                tol = np.maximum(1e-4, 16 * EPS32 * np.sqrt(1.0 + win * steps + t) * bnd)
+                assert np.all(err <= tol), (win, t, p.st.n, err.max())
+                chain.accept(k[t], e[t], s[t], np.isfinite(r_o) & (r_o != 0))
+            np.testing.assert_array_equal(p.occ.cpu().numpy(), chain.book.occ)
+    say(f"  f32 window ratio error max {worst:.2e}")
+
+
+def test_window_device_rng_decisions():
+    """LRX_MH_DEVICE_RNG: each decision is u < min(1, |r|^2) with u from
+    Philox-4x32-10 keyed by the walker's position in the class list."""
+    say("window device rng")
+    g = gen.generator(960)
+    sizes, walkers = (32, 48), (7, 5)
+    classes = small_classes(g, sizes, walkers)
+    steps, seed, ctr = 5, 0x0BAD_5EED_1234_5678, 1000
+    uw = UnevenWalkers(torch.float64, classes, 2, [3, 4], steps, grid=3)
+    uw.set_draws([gen.hop_draws_batch(g, steps, W, n, n, (1, 2), 2) for n, W in zip(sizes, walkers)])
+    uw.window(mode=lrx.LRX_MH_DEVICE_RNG, seed=seed, counter=ctr)
+    base = 0
+    for p in uw.parts:
+        r = p.ratio.cpu().numpy()
+        acc = p.accept.cpu().numpy().astype(bool)
+        for t in range(steps):
+            uu = np.empty(p.st.walkers)
+            c_t = ctr + t
+            for w in range(p.st.walkers):
+                c = philox4x32_10([base + w, c_t & 0xFFFFFFFF, c_t >> 32, 0], (seed & 0xFFFFFFFF, seed >> 32))
+                uu[w] = (((c[0] >> 5) << 26) | (c[1] >> 6)) * 2.0 ** -53
+            np.testing.assert_array_equal(acc[t], orc.metropolis(r[t], uu))
+        base += p.st.walkers
+
+
+def test_uneven_workload_full_size_sampled():
+    """4096 walkers, n in {64, 128, 256, 512, 1024}, k in {1, 2, 4, 8}, FP32 bulk,
+    one window of K = 16 steps in the launch shape the benchmark times;
+    two walkers per class recomputed by the oracle at every step."""
+    wl = gen.WORKLOADS["uneven_n64_1024_fp32"]
+    say(f"full-size {wl.name}")
+    classes, g = gen.uneven_inputs(wl)
+    steps = wl.delay
+    uw = UnevenWalkers(torch.float32, classes, wl.k_max, wl.delay, steps)
+    draws = [gen.hop_draws_batch(g, steps, len(c["walkers"]), c["n"], c["n"], wl.ranks, wl.k_max)
+             for c in classes]
+    uw.set_draws(draws)
+    uw.window(mode=lrx.LRX_MH_FORCE)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for p, cls, (k, e, s) in zip(uw.parts, classes, draws):
+        sample = np.array([0, p.st.walkers - 1])
+        book = orc.Occupancy(cls["occ"][sample], cls["empty"][sample])
+        r = p.ratio.cpu().numpy()[:, sample]
+        check = range(steps) if cls["n"] <= 256 else (0, 1, steps // 2, steps - 1)
+        for t in range(steps):
+            if t not in check:
+                book.commit(k[t][sample], e[t][sample], s[t][sample], np.ones(len(sample), bool))
+                continue
+            la0, ph0, inv0 = orc.slogdet(orc.slater_matrices(cls["phi"], book.occ))
+            prop = book.proposed(k[t][sample], e[t][sample], s[t][sample])
+            la1, ph1, _ = orc.slogdet(orc.slater_matrices(cls["phi"], prop), want_inv=False)
+            r_o = orc.ratio(la1, ph1, la0, ph0)
+            bnd = det_ratio_bound(cls["phi"], book.occ, prop, inv0, k[t][sample], e[t][sample])
+            err = ratio_err(r[t], r_o)
+            worst = max(worst, float(err.max()))
+            assert np.all(err <= np.maximum(1e-3, 16 * EPS32 * np.sqrt(1.0 + t) * bnd)), (cls["n"], t, err)
+            book.commit(k[t][sample], e[t][sample], s[t][sample], np.ones(len(sample), bool))
+        np.testing.assert_array_equal(p.occ.cpu().numpy()[sample], book.occ)
+        assert p.st.slot == 0
+    say(f"  uneven f32 sampled ratio error max {worst:.2e}")
