@@ -106,14 +106,29 @@ template <> __device__ __forceinline__ cf64 conv<cf64, cf32>(cf32 s) { return {(
 template <> __device__ __forceinline__ cf32 conv<cf32, cf32>(cf32 s) { return s; }
 
 // ---------------------------------------------------------------- reductions
-__device__ __forceinline__ float shfl_xor_v(float v, int m) { return __shfl_xor(v, m, LRX_WAVE); }
-__device__ __forceinline__ double shfl_xor_v(double v, int m) { return __shfl_xor(v, m, LRX_WAVE); }
-__device__ __forceinline__ cf32 shfl_xor_v(cf32 v, int m) {
-    return {__shfl_xor(v.x, m, LRX_WAVE), __shfl_xor(v.y, m, LRX_WAVE)};
+// Exchange with lane ^ m, m a power of two that is a compile-time constant once
+// the caller's loops are unrolled: DPP quad permutes for 1 and 2 and the row
+// rotate by 8 for 8 (a rotation by half of a 16-lane row is the xor), the
+// ds_swizzle bit mode (and 0x1f, xor m) for 4 and 16, and ds_bpermute across
+// the two 32-lane halves for 32.
+__device__ __forceinline__ int xshfl_i32(int v, int m) {
+    switch (m) {
+        case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        case 4: return __builtin_amdgcn_ds_swizzle(v, 0x101F);
+        case 8: return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+        case 16: return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+        default: return __builtin_amdgcn_ds_bpermute((((int)threadIdx.x & (LRX_WAVE - 1)) ^ m) << 2, v);
+    }
 }
-__device__ __forceinline__ cf64 shfl_xor_v(cf64 v, int m) {
-    return {__shfl_xor(v.x, m, LRX_WAVE), __shfl_xor(v.y, m, LRX_WAVE)};
+__device__ __forceinline__ float shfl_xor_v(float v, int m) { return __int_as_float(xshfl_i32(__float_as_int(v), m)); }
+__device__ __forceinline__ double shfl_xor_v(double v, int m) {
+    const long long b = __double_as_longlong(v);
+    const int lo = xshfl_i32((int)(b & 0xffffffffll), m), hi = xshfl_i32((int)(b >> 32), m);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
+__device__ __forceinline__ cf32 shfl_xor_v(cf32 v, int m) { return {shfl_xor_v(v.x, m), shfl_xor_v(v.y, m)}; }
+__device__ __forceinline__ cf64 shfl_xor_v(cf64 v, int m) { return {shfl_xor_v(v.x, m), shfl_xor_v(v.y, m)}; }
 
 // Sum over the 64 lanes of a wave; every lane receives the total.
 template <class T> __device__ __forceinline__ T wave_sum(T v) {

@@ -146,23 +146,30 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
         s_fbI[idx] = (c < k) ? fb[(size_t)s_rows[c] * KK + te] : zero<T>();
     }
 
+    // Loads from clamped, always valid addresses, then select: loads under
+    // divergent branches would be serialised by the compiler's waits.
     T uv[NI][KM], cv[NI][KM];
     const Wd *tab = static_cast<const Wd *>(a.hop_table);
 #pragma unroll
     for (int ii = 0; ii < NI; ++ii) {
         const int i = tid + ii * NT;
         const bool valid = i < n;
+        const int ic = valid ? i : n - 1;
 #pragma unroll
         for (int c = 0; c < KM; ++c) {
-            T uu = zero<T>(), cc = zero<T>();
-            if (valid && c < k) {
-                if (fused) uu = bad ? zero<T>() : conv<T>(tab[(size_t)s_dst[c] * n + i] - tab[(size_t)s_src[c] * n + i]);
-                else uu = u[(size_t)c * n + i];
-                cc = M[(size_t)s_rows[c] * n + i];
+            const bool live = valid && c < k;
+            T uu;
+            if (fused) {
+                const Wd d = tab[(size_t)s_dst[c] * n + ic], sv = tab[(size_t)s_src[c] * n + ic];
+                uu = (live && !bad) ? conv<T>(d - sv) : zero<T>();
+            } else {
+                const T uraw = u[(size_t)c * n + ic];
+                uu = live ? uraw : zero<T>();
             }
+            const T craw = M[(size_t)s_rows[c] * n + ic];
             if (fused && valid) u[(size_t)c * n + i] = uu;
             uv[ii][c] = uu;
-            cv[ii][c] = cc;
+            cv[ii][c] = live ? craw : zero<T>();
         }
     }
     __syncthreads();
@@ -174,11 +181,13 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
         T av[GS][NI];
 #pragma unroll
         for (int gi = 0; gi < GS; ++gi) {
-            const int te = (g0 + gi < nl) ? s_live[g0 + gi] : -1;
+            const bool tok = g0 + gi < nl;
+            const int te = tok ? s_live[g0 + gi] : 0;
 #pragma unroll
             for (int ii = 0; ii < NI; ++ii) {
                 const int i = tid + ii * NT;
-                av[gi][ii] = (te >= 0 && i < n) ? fa[(size_t)te * n + i] : zero<T>();
+                const T val = fa[(size_t)te * n + (i < n ? i : n - 1)];
+                av[gi][ii] = (tok && i < n) ? val : zero<T>();
             }
         }
 #pragma unroll
@@ -211,13 +220,19 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
             __syncthreads();
         }
     }
-    // C, and R[c][d] = delta_cd + sum_i u[c][i] C[d][i] (one KM-value reduction per row c of R)
+    // C (stash, and slot a_tau = C of the delayed form, Eq. det_a; a rejected
+    // step leaves it dead), and R[c][d] = delta_cd + sum_i u[c][i] C[d][i]
+    // (one KM-value reduction per row c of R)
+    T *fa_tau = (a.K > 0) ? static_cast<T *>(a.fa) + ((size_t)w * KK + (size_t)tau * KM) * n : nullptr;
 #pragma unroll
     for (int ii = 0; ii < NI; ++ii) {
         const int i = tid + ii * NT;
         if (i < n) {
 #pragma unroll
-            for (int c = 0; c < KM; ++c) C[(size_t)c * n + i] = cv[ii][c];
+            for (int c = 0; c < KM; ++c) {
+                C[(size_t)c * n + i] = cv[ii][c];
+                if (fa_tau) fa_tau[(size_t)c * n + i] = cv[ii][c];
+            }
         }
     }
 #pragma unroll
@@ -305,49 +320,72 @@ struct AcceptCtx {
     bool vec_ok;
 };
 
-template <class T, int KC, int KM, int NEL, int RB, int MG, bool DELAYED>
+template <class T, int KC, int KM, int NEL, int RB, int MG, bool DELAYED, int PD, bool VEC>
 __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
     constexpr int V = vec16<T>();
     constexpr int NCH = NEL / V;
     constexpr int NV = RB * KC;
+    // u is held in registers when its KC x NEL slice is small; else read from LDS per row.
+    constexpr bool UREG = KC * NEL * sizeof(T) <= 128;
     const int lane = c.lane;
     const int my_r = (lane % NV) / KC, my_c = lane % KC;
     T rrow[KC];
 #pragma unroll
     for (int d = 0; d < KC; ++d) rrow[d] = c.s_ri[my_c * KM + d];
+    T ureg[UREG ? KC : 1][UREG ? NEL : 1];
+    if constexpr (UREG) {
+#pragma unroll
+        for (int cc = 0; cc < KC; ++cc)
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                T uv[V];
+                ld16<T>(c.s_u + (size_t)cc * c.npad + ch * V * LRX_WAVE + lane * V, uv);
+#pragma unroll
+                for (int v = 0; v < V; ++v) ureg[cc][ch * V + v] = uv[v];
+            }
+    }
     const int n = c.n;
-    // Software pipeline: the rows of the next batch are requested before the
-    // current batch is reduced, so two batches of loads are in flight per wave.
-    auto load_rows = [&](int qb, T (&x)[RB][NEL]) {
+    // Software pipeline: the rows of the next PD (1..3) batches, with the
+    // slot-row values b_t[q][te] they need, are in flight while the current
+    // batch is reduced.
+    // Loads are unconditional, from clamped (always valid) addresses, and
+    // nothing is selected right after them: a load under a divergent branch,
+    // or a select on its result, makes the compiler wait for it on the spot,
+    // which would serialise the pipeline.  Out-of-range values are harmless:
+    // u is zero beyond n (LDS panel padding) and G is zero beyond the live
+    // slot columns, so they add nothing; rows past q1 are computed on a copy
+    // of row q1-1 and never stored.  VEC: rows are 16-byte aligned and n is a
+    // multiple of the vector width.
+    auto load_rows = [&](int qb, T (&x)[RB][NEL], T (&bq)[RB][MG]) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const int q = qb + r;
+            const int q = min(qb + r, c.q1 - 1);
             const T *row = c.M + (size_t)q * n;
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int j0 = ch * V * LRX_WAVE + lane * V;
-                T tmp[V];
-                if (q < c.q1 && c.vec_ok && j0 + V <= n) {
-                    ld16<T>(row + j0, tmp);
+                if constexpr (VEC) {
+                    T tmp[V];
+                    ld16<T>(row + (j0 < n ? j0 : 0), tmp);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) x[r][ch * V + v] = tmp[v];
                 } else {
 #pragma unroll
-                    for (int v = 0; v < V; ++v) tmp[v] = (q < c.q1 && j0 + v < n) ? row[j0 + v] : zero<T>();
+                    for (int v = 0; v < V; ++v) x[r][ch * V + v] = row[min(j0 + v, n - 1)];
                 }
+            }
 #pragma unroll
-                for (int v = 0; v < V; ++v) x[r][ch * V + v] = tmp[v];
+            for (int m = 0; m < MG; ++m) {
+                const int te = lane + m * LRX_WAVE;
+                bq[r][m] = (DELAYED && c.TE > m * LRX_WAVE) ? c.fb[(size_t)q * c.KK + min(te, c.TE - 1)] : zero<T>();
             }
         }
     };
     const int qstep = kWaves * RB;
-    T xn[RB][NEL];
-    load_rows(c.q0 + c.wv * RB, xn);
-    for (int qb = c.q0 + c.wv * RB; qb < c.q1; qb += qstep) {
-        T x[RB][NEL];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int e = 0; e < NEL; ++e) x[r][e] = xn[r][e];
-        if (qb + qstep < c.q1) load_rows(qb + qstep, xn);
+    // One batch: dots with u, slot correction, reduction, z, then the store.
+    // The batch registers are used in place (no copies between ring buffers:
+    // moving a register with a load still in flight would wait for it).
+    auto process = [&](int qb, T (&x)[RB][NEL], T (&bv)[RB][MG]) {
         T p[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) p[i] = zero<T>();
@@ -356,7 +394,12 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 T uv[V];
-                ld16<T>(c.s_u + (size_t)cc * c.npad + ch * V * LRX_WAVE + lane * V, uv);
+                if constexpr (UREG) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) uv[v] = ureg[cc][ch * V + v];
+                } else {
+                    ld16<T>(c.s_u + (size_t)cc * c.npad + ch * V * LRX_WAVE + lane * V, uv);
+                }
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -368,25 +411,28 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
 #pragma unroll
             for (int m = 0; m < MG; ++m) {
                 if (m * LRX_WAVE < c.TE) {
-                    // slot products G[te][c] (= a_te . u_c) of the column this lane owns, te = lane + 64 m
+                    // slot products G[te][c] (= a_te . u_c) of the column this lane owns
                     const int te = lane + m * LRX_WAVE;
                     T g[KC];
 #pragma unroll
                     for (int cc = 0; cc < KC; ++cc) g[cc] = te < c.TE ? c.s_g[te * KM + cc] : zero<T>();
 #pragma unroll
-                    for (int r = 0; r < RB; ++r) {
-                        const int q = qb + r;
-                        const T bv = (te < c.TE && q < c.q1) ? c.fb[(size_t)q * c.KK + te] : zero<T>();
+                    for (int r = 0; r < RB; ++r)
 #pragma unroll
-                        for (int cc = 0; cc < KC; ++cc) p[r * KC + cc] = fmsc(bv, g[cc], p[r * KC + cc]);
-                    }
+                        for (int cc = 0; cc < KC; ++cc) p[r * KC + cc] = fmsc(bv[r][m], g[cc], p[r * KC + cc]);
                 }
             }
         }
         const T w = wave_sum_multi<T, NV>(p);     // lane l: w[r][c], l mod NV = r*KC + c
+        // w[r][d] sits in lane r*KC + d: read it as a wave-uniform value.
         T z = zero<T>();
 #pragma unroll
-        for (int d = 0; d < KC; ++d) z = fmac(rrow[d], shfl_any(w, my_r * KC + d), z);
+        for (int r = 0; r < RB; ++r) {
+            T zr = zero<T>();
+#pragma unroll
+            for (int d = 0; d < KC; ++d) zr = fmac(rrow[d], lane_bcast(w, r * KC + d), zr);
+            z = (my_r == r) ? zr : z;
+        }
         if (DELAYED) {
             const int q = qb + my_r;
             if (lane < NV && q < c.q1) c.fb[(size_t)q * c.KK + c.tau * KM + my_c] = z;
@@ -426,12 +472,35 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
                 }
             }
         }
+    };
+    // Ring of PD + 1 batches, unrolled so that each buffer keeps its name:
+    // consume buffer j, then refill it with the batch PD + 1 steps ahead.
+    constexpr int S = PD + 1;
+    T x0[RB][NEL], x1[RB][NEL], x2[RB][NEL], x3[RB][NEL];
+    T b0[RB][MG], b1[RB][MG], b2[RB][MG], b3[RB][MG];
+    int qb = c.q0 + c.wv * RB;
+    load_rows(qb, x0, b0);
+    if constexpr (S > 1) load_rows(qb + qstep, x1, b1);
+    if constexpr (S > 2) load_rows(qb + 2 * qstep, x2, b2);
+    if constexpr (S > 3) load_rows(qb + 3 * qstep, x3, b3);
+    auto stage = [&](T (&x)[RB][NEL], T (&bq)[RB][MG]) -> bool {
+        if (qb >= c.q1) return false;
+        process(qb, x, bq);
+        load_rows(qb + S * qstep, x, bq);   // clamped past the end
+        qb += qstep;
+        return true;
+    };
+    for (;;) {
+        if (!stage(x0, b0)) break;
+        if constexpr (S > 1) { if (!stage(x1, b1)) break; }
+        if constexpr (S > 2) { if (!stage(x2, b2)) break; }
+        if constexpr (S > 3) { if (!stage(x3, b3)) break; }
     }
 }
 
 // Rows [q0, q1) of walker w; rb == 0 marks the block that also does the
 // per-walker bookkeeping (log|det|, phase, slot rank, decision, commit).
-template <class T, int KM, int NEL, int RB, int MG, bool DELAYED>
+template <class T, int KM, int NEL, int RB, int MG, bool DELAYED, int PD = 1>
 __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, int rb, int q0, int q1,
                                                       unsigned char *smem, int tid) {
     using Wd = typename Wide<T>::type;
@@ -479,10 +548,12 @@ __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, 
     }
 
     if (!take) {
-        if (DELAYED) {   // a rejected walker's slot contributes nothing
+        // A rejected walker's slot contributes nothing: its rank is 0, so the
+        // propose and the flush skip its a-columns, and its b-columns are zero
+        // for the slot correction of the following accepts.
+        if (DELAYED) {
             for (int idx = tid; idx < KM * (q1 - q0); idx += kThreads) {
                 int c = idx / (q1 - q0), q = q0 + idx - c * (q1 - q0);
-                fa[(size_t)(tau * KM + c) * n + q] = zero<T>();
                 fb[(size_t)q * KK + tau * KM + c] = zero<T>();
             }
             if (rb == 0 && tid == 0) kslot[tau] = 0;
@@ -494,41 +565,80 @@ __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, 
         if (DELAYED) kslot[tau] = k;
     }
 
-    const int npad = NCH * V * LRX_WAVE;        // padded row length held in LDS
+    // Staging: every load is issued (unrolled, from clamped addresses) before
+    // the first one is consumed, so the set-up costs one memory latency.
+    constexpr int NPAD = NCH * V * LRX_WAVE;    // padded row length held in LDS
+    const int npad = NPAD;
     T *s_u = reinterpret_cast<T *>(smem);                   // [KM][npad]
     T *s_c = DELAYED ? s_u : s_u + (size_t)KM * npad;       // [KM][npad], plain update only
     T *s_ri = s_c + (size_t)KM * npad;                      // [KM*KM]
     T *s_g = s_ri + KM * KM;                                // [TE][KM], delayed update only
-    for (int idx = tid; idx < kc * npad; idx += kThreads) {
-        int c = idx / npad, j = idx - c * npad;
-        bool ok = c < k && j < n;
-        s_u[idx] = ok ? u[(size_t)c * n + j] : zero<T>();
-        if (!DELAYED) s_c[idx] = ok ? C[(size_t)c * n + j] : zero<T>();
+    constexpr int UIT = (KM * NPAD + kThreads - 1) / kThreads;
+    constexpr int GIT = DELAYED ? KM : 1;     // TE * KM <= 256 KM (the C ABI keeps K * KM <= 256)
+    T ub[UIT], cb[DELAYED ? 1 : UIT];
+#pragma unroll
+    for (int it = 0; it < UIT; ++it) {
+        const int idx = tid + it * kThreads;
+        const int c = min(idx / NPAD, KM - 1), j = min(idx % NPAD, n - 1);
+        ub[it] = u[(size_t)c * n + j];
+        if constexpr (!DELAYED) cb[it] = C[(size_t)c * n + j];
+    }
+    const T rv = Rinv[tid < KM * KM ? tid : 0];
+    T gb[GIT];
+    const int TEK = TE * KM;
+#pragma unroll
+    for (int it = 0; it < GIT; ++it) {
+        const int idx = tid + it * kThreads;
+        gb[it] = (DELAYED && it * kThreads < TEK) ? G[min(idx, TEK - 1)] : zero<T>();
+    }
+#pragma unroll
+    for (int it = 0; it < UIT; ++it) {
+        const int idx = tid + it * kThreads;
+        if (idx < kc * NPAD) {
+            const int c = idx / NPAD, j = idx % NPAD;
+            const bool ok = c < k && j < n;
+            s_u[idx] = ok ? ub[it] : zero<T>();
+            if constexpr (!DELAYED) s_c[idx] = ok ? cb[it] : zero<T>();
+        }
     }
     if (tid < KM * KM) {
         const int c = tid / KM, d = tid - c * KM;
-        s_ri[tid] = (c < k && d < k) ? Rinv[tid] : zero<T>();
+        s_ri[tid] = (c < k && d < k) ? rv : zero<T>();
     }
-    if (DELAYED)
-        for (int idx = tid; idx < TE * KM; idx += kThreads) s_g[idx] = G[idx];
-    if (DELAYED) {   // a_tau = C for this block's rows; b_tau columns beyond kc are zero
-        for (int idx = tid; idx < KM * (q1 - q0); idx += kThreads) {
-            int c = idx / (q1 - q0), q = q0 + idx - c * (q1 - q0);
-            fa[(size_t)(tau * KM + c) * n + q] = (c < k) ? C[(size_t)c * n + q] : zero<T>();
-            if (c >= kc) fb[(size_t)q * KK + tau * KM + c] = zero<T>();
+#pragma unroll
+    for (int it = 0; it < GIT; ++it) {
+        const int idx = tid + it * kThreads;
+        if (DELAYED && idx < TEK) s_g[idx] = gb[it];
+    }
+    if (DELAYED && kc < KM) {   // b_tau columns beyond kc are zero (a_tau is written by the propose)
+        for (int idx = tid; idx < (KM - kc) * (q1 - q0); idx += kThreads) {
+            const int c = kc + idx / (q1 - q0), q = q0 + idx % (q1 - q0);
+            fb[(size_t)q * KK + tau * KM + c] = zero<T>();
         }
     }
     __syncthreads();
 
     AcceptCtx<T> ctx{M, fa, fb, s_g, s_u, s_c, s_ri, n, KK, tau, TE, q0, q1, npad, wv, lane, a.aligned != 0};
-    if (kc == 1) {
-        accept_rows<T, 1, KM, NEL, RB, MG, DELAYED>(ctx);
-    } else if (kc == 2) {
-        if constexpr (KM >= 2) accept_rows<T, 2, KM, NEL, RB, MG, DELAYED>(ctx);
-    } else if (kc == 4) {
-        if constexpr (KM >= 4) accept_rows<T, 4, KM, NEL, RB, MG, DELAYED>(ctx);
+    if (ctx.vec_ok) {
+        if (kc == 1) {
+            accept_rows<T, 1, KM, NEL, RB, MG, DELAYED, PD, true>(ctx);
+        } else if (kc == 2) {
+            if constexpr (KM >= 2) accept_rows<T, 2, KM, NEL, RB, MG, DELAYED, PD, true>(ctx);
+        } else if (kc == 4) {
+            if constexpr (KM >= 4) accept_rows<T, 4, KM, NEL, RB, MG, DELAYED, PD, true>(ctx);
+        } else {
+            if constexpr (KM >= 8) accept_rows<T, 8, KM, NEL, RB, MG, DELAYED, PD, true>(ctx);
+        }
     } else {
-        if constexpr (KM >= 8) accept_rows<T, 8, KM, NEL, RB, MG, DELAYED>(ctx);
+        if (kc == 1) {
+            accept_rows<T, 1, KM, NEL, RB, MG, DELAYED, PD, false>(ctx);
+        } else if (kc == 2) {
+            if constexpr (KM >= 2) accept_rows<T, 2, KM, NEL, RB, MG, DELAYED, PD, false>(ctx);
+        } else if (kc == 4) {
+            if constexpr (KM >= 4) accept_rows<T, 4, KM, NEL, RB, MG, DELAYED, PD, false>(ctx);
+        } else {
+            if constexpr (KM >= 8) accept_rows<T, 8, KM, NEL, RB, MG, DELAYED, PD, false>(ctx);
+        }
     }
 }
 
@@ -577,11 +687,13 @@ template <class T, int KM, int NEL, bool DELAYED> size_t accept_lds_bytes(int K)
     return sizeof(T) * ((DELAYED ? 1 : 2) * KM * npad + KM * KM + (DELAYED ? (size_t)K * KM * KM : 0));
 }
 
-// Rows held per wave batch: the RB x NEL row values plus the RB x KM partial
-// dot products stay within ~96 VGPRs.
-template <class T, int NEL, int KM> constexpr int rows_per_batch() {
-    constexpr int per_row = (NEL + KM) * (int)sizeof(T);
-    return 8 * per_row <= 384 ? 8 : (4 * per_row <= 384 ? 4 : (2 * per_row <= 384 ? 2 : 1));
+// Rows per wave batch: the RB x NEL row values of PD + 1 batches plus the
+// RB x KM partial dot products stay within a small register budget (batches
+// of one or two rows measured fastest: occupancy matters more than batch size).
+template <class T, int NEL, int KM, int PD = 1> constexpr int rows_per_batch() {
+    constexpr int per_row = ((PD + 1) * NEL + KM) * (int)sizeof(T);
+    constexpr int budget = 192 + (PD - 1) * 128;
+    return 8 * per_row <= budget ? 8 : (4 * per_row <= budget ? 4 : (2 * per_row <= budget ? 2 : 1));
 }
 
 }  // namespace lrxdet

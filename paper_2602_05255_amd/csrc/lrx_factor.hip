@@ -11,21 +11,31 @@
 //        Eq. pf_block, which splits off a 2x2 block whose Pfaffian is its (0,1)
 //        entry); A^-1 by the same Gauss-Jordan kernels, then M = (X - X^T)/2.
 //
-// Blocked Gauss-Jordan, one panel of nb columns at a time (all in the
-// workspace X, row-major):
+// Two-level blocked Gauss-Jordan (all in the workspace X, row-major).  The
+// columns are taken in outer panels of up to 64; inside an outer panel,
+// sub-panels of nb columns (nb limited by LDS) are eliminated one at a time
+// and their transform is applied to the other columns of the outer panel
+// only.  The outer panel's columns then hold Zt + E_P, with I + Zt E_P^T the
+// composite transform of the whole outer panel, and every remaining column
+// gets it in one MFMA GEMM of inner dimension 64 (gj_outer_kernel).  Per
+// sub-panel:
 //   panel kernel : LU with partial pivoting of the panel rows j0..n-1 in LDS;
 //                  with Y_P the pivoted nb x nb diagonal block, the transform
 //                  that turns the panel into identity columns is I + Z E_P^T
 //                  with Z[P] = Y_P^-1 - I, Z[below] = -L21 L11^-1,
 //                  Z[above] = -Y_above Y_P^-1.  The panel columns become the
 //                  matching inverse columns, Z + E_P.
-//   update kernel: every other column: swap rows, then X += Z X[P rows].
+//   update kernel: the other columns of the outer panel: swap rows, then
+//                  X += Z X[P rows].
 //   final kernel : undo the row pivoting as a column permutation, cast to the
 //                  bulk dtype, and (refresh) measure the drift of the old state.
 #include "lrx_common.hpp"
+#include "lrx_flush_impl.hpp"
 #include "lrx_internal.hpp"
 
 namespace {
+
+using namespace lrxfl;
 
 using lrx::FactorArgs;
 
@@ -375,18 +385,18 @@ __global__ __launch_bounds__(kT) void gj_panel_kernel(FA a, int j0, int nb) {
 }
 
 // ------------------------------------------------------------------ GJ update
-// Every column outside the panel: X_new[i] = X_old[pi(i)] + Z[i] . X_old[pi(P)].
+// Columns [c_lo, c_hi) outside the panel: X_new[i] = X_old[pi(i)] + Z[i] . X_old[pi(P)].
 // A work-group owns 64 of those columns (one per lane) for all rows.  Rows
 // moved by the panel's pivoting (at most 2 nb) and the pivot rows are staged
 // in LDS first, so every other row is read and written in place by one lane.
 // Z[i][:] is wave-uniform and is read through the scalar cache.
 template <class Wd, int NB>
-__global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int ncb) {
+__global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int ncb, int c_lo, int c_hi) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int w = lb / ncb, cb = lb - w * ncb;
     if (w >= a.W) return;
-    const int n = a.n, others = n - nb;
+    const int n = a.n, others = (c_hi - c_lo) - nb;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Wd *X = wX<Wd>(a, w);
@@ -412,7 +422,7 @@ __global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int
     __syncthreads();
     const int ci = cb * 64 + lane;
     const bool live = ci < others;
-    const int col = ci < j0 ? ci : ci + nb;
+    const int col = c_lo + ci < j0 ? c_lo + ci : c_lo + ci + nb;   // columns [c_lo, c_hi) minus the panel
     // pivot rows and moved rows, from the pre-update matrix
     for (int c = wv; c < nb; c += kT / 64)
         sXP[c * 64 + lane] = live ? X[(size_t)perm[j0 + c] * n + col] : zero<Wd>();
@@ -453,6 +463,110 @@ __global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int
         for (int r = 0; r < 16; ++r) {
             const int i = i0 + wv * 16 + r;
             if (live && i < n) X[(size_t)i * n + col] = v[r];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ GJ outer update
+// After the last sub-panel of the outer panel [j0, j0 + nbo), its columns hold
+// Zt + E_P; with pi the row swaps piv[j0 .. j0+nbo) in order, every column
+// outside the outer panel becomes
+//   X_new[i] = X_old[pi(i)] + Zt[i] . X_old[pi(P)],   P = rows j0 .. j0+nbo-1,
+// an MFMA GEMM (v_mfma_f64_16x16x4f64; four real products per complex one)
+// with inner dimension nbo.  A work-group (4 waves) owns CB columns of one
+// walker and walks the rows in chunks of 64, 16 per wave.  Rows moved by pi
+// only ever come from the positions j0 .. j0+nbo-1, so the pre-update pivot
+// rows X_old[pi(P)] and the pre-update rows at those positions are all that
+// is staged in LDS; every other row is read and written in place by one lane.
+template <class Wd> constexpr int outer_cb() { return sizeof(Wd) == 8 ? 64 : 32; }
+template <class Wd> size_t outer_lds(int n) {
+    return (((size_t)n * 4 + 15) / 16) * 16 + 2 * (size_t)64 * (outer_cb<Wd>() + 1) * sizeof(Wd);
+}
+
+template <class Wd, int CB>
+__global__ __launch_bounds__(kT) void gj_outer_kernel(FA a, int j0, int nbo, int ncb) {
+    using R = typename Real<Wd>::type;
+    using A4 = typename Acc<R>::type;
+    constexpr int NTL = CB / 16;          // 16-column MFMA tiles per wave
+    constexpr int SP = CB + 1;            // padded LDS row stride
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int w = lb / ncb, cb = lb - w * ncb;
+    if (w >= a.W) return;
+    const int n = a.n, others = n - nbo;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    Wd *X = wX<Wd>(a, w);
+    const int *piv = wPiv(a, w);
+    int *perm = reinterpret_cast<int *>(smem);                                   // [n]
+    Wd *sXP = reinterpret_cast<Wd *>(smem + (((size_t)n * 4 + 15) / 16) * 16);    // [64][SP]: X_old[pi(j0+c)]
+    Wd *sOP = sXP + (size_t)64 * SP;                                              // [64][SP]: X_old[j0+c]
+    for (int i = tid; i < n; i += kT) perm[i] = i;
+    __syncthreads();
+    if (tid == 0) {
+        for (int c = 0; c < nbo; ++c) {
+            const int r = j0 + c, p = piv[r];
+            const int t = perm[r]; perm[r] = perm[p]; perm[p] = t;
+        }
+    }
+    __syncthreads();
+    const int ci0 = cb * CB;
+    for (int idx = tid; idx < nbo * CB; idx += kT) {
+        const int c = idx / CB, jj = idx - c * CB;
+        const int ci = ci0 + jj;
+        const int col = ci < j0 ? ci : ci + nbo;
+        const bool live = ci < others;
+        sXP[c * SP + jj] = live ? X[(size_t)perm[j0 + c] * n + col] : zero<Wd>();
+        sOP[c * SP + jj] = live ? X[(size_t)(j0 + c) * n + col] : zero<Wd>();
+    }
+    __syncthreads();
+    const int kq = lane >> 4, lc = lane & 15;
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int rbase = i0 + wv * 16;
+        A4 re[NTL], im[NTL];
+#pragma unroll
+        for (int jt = 0; jt < NTL; ++jt) {
+            const int jj = jt * 16 + lc;
+            const int ci = ci0 + jj;
+            const int col = ci < j0 ? ci : ci + nbo;
+            const bool live = ci < others;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = rbase + acc_row<R>(lane, r);
+                Wd v = zero<Wd>();
+                if (live && i < n) {
+                    const int src = perm[i];
+                    if (i >= j0 && i < j0 + nbo) v = sXP[(i - j0) * SP + jj];
+                    else if (src != i) v = sOP[(src - j0) * SP + jj];
+                    else v = X[(size_t)i * n + col];
+                }
+                re[jt][r] = re_(v);
+                im[jt][r] = im_(v);
+            }
+        }
+        const int zrow = rbase + lc;
+        for (int k0 = 0; k0 < nbo; k0 += 4) {
+            const int k = k0 + kq;
+            Wd z = zero<Wd>();
+            if (zrow < n && k < nbo) {
+                z = X[(size_t)zrow * n + j0 + k];
+                if (zrow == j0 + k) z = z - one<Wd>();
+            }
+#pragma unroll
+            for (int jt = 0; jt < NTL; ++jt) {
+                const Wd b = k < nbo ? sXP[k * SP + jt * 16 + lc] : zero<Wd>();
+                mac<Wd>(z, b, re[jt], im[jt]);
+            }
+        }
+#pragma unroll
+        for (int jt = 0; jt < NTL; ++jt) {
+            const int ci = ci0 + jt * 16 + lc;
+            const int col = ci < j0 ? ci : ci + nbo;
+            if (ci >= others) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = rbase + acc_row<R>(lane, r);
+                if (i < n) X[(size_t)i * n + col] = make_<Wd>(re[jt][r], im[jt][r]);
+            }
         }
     }
 }
@@ -610,19 +724,30 @@ __global__ void finish_kernel(FA a) {
 }
 
 template <class Wd>
-hipError_t launch_update(const FA &fa, int j0, int nb, hipStream_t s) {
-    const int others = fa.n - nb;
+hipError_t launch_outer(const FA &fa, int j0, int nbo, hipStream_t s) {
+    const int others = fa.n - nbo;
+    if (others <= 0) return hipSuccess;
+    constexpr int CB = outer_cb<Wd>();
+    const int ncb = (others + CB - 1) / CB;
+    hipLaunchKernelGGL((gj_outer_kernel<Wd, CB>), dim3((unsigned)(fa.W * ncb)), dim3(kT), outer_lds<Wd>(fa.n), s,
+                       fa, j0, nbo, ncb);
+    return hipGetLastError();
+}
+
+template <class Wd>
+hipError_t launch_update(const FA &fa, int j0, int nb, int c_lo, int c_hi, hipStream_t s) {
+    const int others = (c_hi - c_lo) - nb;
     if (others <= 0) return hipSuccess;
     const int ncb = (others + 63) / 64;
     const size_t lds = (((2 * fa.n + 1) * 4 + 15) / 16) * 16 + sizeof(Wd) * (size_t)4 * nb * 64;
     const dim3 grid((unsigned)(fa.W * ncb)), block(kT);
     switch (fa.nb) {
-        case 32: hipLaunchKernelGGL((gj_update_kernel<Wd, 32>), grid, block, lds, s, fa, j0, nb, ncb); break;
-        case 16: hipLaunchKernelGGL((gj_update_kernel<Wd, 16>), grid, block, lds, s, fa, j0, nb, ncb); break;
-        case 8: hipLaunchKernelGGL((gj_update_kernel<Wd, 8>), grid, block, lds, s, fa, j0, nb, ncb); break;
-        case 4: hipLaunchKernelGGL((gj_update_kernel<Wd, 4>), grid, block, lds, s, fa, j0, nb, ncb); break;
-        case 2: hipLaunchKernelGGL((gj_update_kernel<Wd, 2>), grid, block, lds, s, fa, j0, nb, ncb); break;
-        default: hipLaunchKernelGGL((gj_update_kernel<Wd, 1>), grid, block, lds, s, fa, j0, nb, ncb); break;
+        case 32: hipLaunchKernelGGL((gj_update_kernel<Wd, 32>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        case 16: hipLaunchKernelGGL((gj_update_kernel<Wd, 16>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        case 8: hipLaunchKernelGGL((gj_update_kernel<Wd, 8>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        case 4: hipLaunchKernelGGL((gj_update_kernel<Wd, 4>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        case 2: hipLaunchKernelGGL((gj_update_kernel<Wd, 2>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        default: hipLaunchKernelGGL((gj_update_kernel<Wd, 1>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
     }
     return hipGetLastError();
 }
@@ -648,8 +773,11 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     }
     hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    for (int j0 = 0; j0 < n; j0 += a.nb) {
-        const int nb = min(a.nb, n - j0);
+    constexpr int kOuter = 64;
+    for (int o0 = 0; o0 < n; o0 += kOuter) {
+      const int nbo = min(kOuter, n - o0);
+      for (int j0 = o0; j0 < o0 + nbo; j0 += a.nb) {
+        const int nb = min(a.nb, o0 + nbo - j0);
         const size_t lds = sizeof(Wd) * ((size_t)(n - j0) * (nb + 1) + 2 * (size_t)nb * nb);
         switch (a.nb) {
             case 32: hipLaunchKernelGGL((gj_panel_kernel<Wd, 32>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
@@ -659,8 +787,11 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
             case 2: hipLaunchKernelGGL((gj_panel_kernel<Wd, 2>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
             default: hipLaunchKernelGGL((gj_panel_kernel<Wd, 1>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
         }
-        e = launch_update<Wd>(a, j0, nb, s);
+        e = launch_update<Wd>(a, j0, nb, o0, o0 + nbo, s);
         if (e != hipSuccess) return e;
+      }
+      e = launch_outer<Wd>(a, o0, nbo, s);
+      if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(src_perm_kernel, dim3(W), dim3(kT), sizeof(int) * 2 * (size_t)n, s, a);
     if (a.kind == LRX_DET) {

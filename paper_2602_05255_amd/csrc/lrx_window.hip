@@ -50,10 +50,7 @@ __device__ __forceinline__ void window_walker(const WindowClass &wc, int steps, 
     constexpr int V = vec16<T>();
     constexpr int NEL = NCH * V;
     constexpr int NI = (NCH * V / 4) > 1 ? NCH * V / 4 : 1;   // entries per thread of a 256-wide column
-    // Half the per-step kernel's row batch: two work-groups share a CU here, so
-    // one can propose while the other streams rows.
-    constexpr int RB0 = rows_per_batch<T, NEL, KM>();
-    constexpr int RB = RB0 > 1 ? RB0 / 2 : 1;
+    constexpr int RB = rows_per_batch<T, NEL, KM>();
     StepArgs a = wc.a;
     const int W = a.W, K = a.K;
     int tau = a.tau;
