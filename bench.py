@@ -34,6 +34,32 @@ FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
 
+def counter_traffic(profile, sources):
+    """HBM bytes per launch measured by the FETCH_SIZE / WRITE_SIZE counter passes
+    recorded in profiles/<profile>, or None when the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    keys = {}
+    for line in open(path):
+        part = line.strip().split(":", 1)
+        if len(part) == 2:
+            keys[part[0].strip()] = part[1].strip()
+    if keys.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in keys:
+        return None
+    return float(keys["traffic_bytes_per_launch"])
+
+
+DET_SOURCES = ["paper_2602_05255_amd/csrc/lrx_common.hpp", "paper_2602_05255_amd/csrc/lrx_internal.hpp",
+               "paper_2602_05255_amd/csrc/lrx_det_impl.hpp", "paper_2602_05255_amd/csrc/lrx_det.hip",
+               "include/lrx.h"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -50,6 +76,8 @@ def parse():
     ap.add_argument("--no-recompute", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -451,6 +479,23 @@ def bench_uneven(wl, args, torch):
             "refresh_ms": refresh_s * 1e3}
 
 
+def copy_calibration(torch, nbytes=1 << 30, reps=5):
+    """A plain device copy of nbytes (read nbytes, write nbytes): the reference
+    that scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    return {"copy_bytes": nbytes, "reps": reps + 1, "us": dt * 1e6, "gbs_read_plus_write": 2 * nbytes / dt / 1e9}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -463,6 +508,9 @@ def main():
     from paper_2602_05255_amd import lrx  # noqa: F401  (fails loudly without liblrx.so)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration(torch)), flush=True)
+        return
     wl = gen.WORKLOADS[args.workload]
     if wl.name == "logpsi_grad_n512_c64":
         print(json.dumps(bench_adjoint(wl, args, torch)), flush=True)
@@ -504,7 +552,9 @@ def main():
                    "delay": wl.delay, "refresh_every": wl.refresh, "mc_steps_per_bench_step": wl.refresh,
                    "mode": "forced-accept", "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "kernel": "det_accept_kernel (delayed)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic("det_accept_kernel_slater_n256_k124_counters.md", DET_SOURCES),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "avg_us": r64["accept_avg_us"], "bytes_per_launch": r64["accept_bytes_per_launch"]},
         "cpu_baseline": cpu,
         "rel_error": err64,
