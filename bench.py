@@ -395,13 +395,19 @@ def bench_uneven(wl, args, torch):
     K, P = wl.delay, wl.refresh
     nwin = P // K
     t0 = time.time()
-    uw = UnevenWalkers(torch.float32, classes, wl.k_max, K, K)
+    from paper_2602_05255_amd import autotune
+    log(f"  autotune cache {autotune.cache_path()}")
+    uw = UnevenWalkers(torch.float32, classes, wl.k_max, "auto", K, ranks=wl.ranks)
+    gt = gen.generator(gen.SEED_BASE + 11)    # draws for the grid search only
+    uw.set_draws([gen.hop_draws_batch(gt, K, p.st.walkers, c["n"], c["n"], wl.ranks, wl.k_max)
+                  for c, p in zip(classes, uw.parts)])
+    autotune.tune_grid(uw)
     big = []
     for c, p in zip(classes, uw.parts):
         k, e, s = gen.hop_draws_batch(g, P, len(c["walkers"]), c["n"], c["n"], wl.ranks, wl.k_max)
         big.append(tuple(torch.as_tensor(x).cuda() for x in (k, e, s)))
     log(f"  setup {time.time() - t0:.1f}s; classes " +
-        ", ".join(f"n={p.st.n}:W={p.st.walkers}" for p in uw.parts) + f"; grid {uw.grid}")
+        ", ".join(f"n={p.st.n}:W={p.st.walkers}:K={p.st.delay}" for p in uw.parts) + f"; grid {uw.grid}")
 
     def window(i):
         for p, (k, e, s) in zip(uw.parts, big):
@@ -454,15 +460,15 @@ def bench_uneven(wl, args, torch):
     value = W * P * args.steps / T
     # algorithmic bytes of one window (all proposals applied): per walker and step
     # read A_0^-1 (n^2) and the live b-slot rows (n kbar tau), u and C (2 n kbar),
-    # write the new slot (2 n kbar); per walker and window the flush reads and
-    # writes A_0^-1 and reads the K kbar live slot columns of a and b.
+    # write the new slot (2 n kbar); per walker and flush the flush reads and
+    # writes A_0^-1 and reads the Kc kbar live slot columns of a and b.
     kbar = float(np.mean(wl.ranks))
     es = 4
     wbytes = 0.0
-    for p in uw.parts:
-        n = p.st.n
-        per_step = n * n + n * kbar * (K - 1) / 2.0 + 4 * n * kbar
-        wbytes += p.st.walkers * es * (K * per_step + 2 * n * n + 2 * n * K * kbar)
+    for p in uw.parts:      # each class with its own (autotuned) delay Kc, flushed K / Kc times per window
+        n, Kc = p.st.n, p.st.delay
+        per_step = n * n + n * kbar * (Kc - 1) / 2.0 + 4 * n * kbar
+        wbytes += p.st.walkers * es * (K * per_step + (K / Kc) * (2 * n * n + 2 * n * Kc * kbar))
     win = float(np.mean(win_s))
     log(f"  [uneven f32] {value:.4g} walker-steps/s, {T / args.steps * 1e3:.2f} ms per period; window "
         f"{win * 1e3:.3f} ms ({wbytes / win / 1e9:.0f} GB/s algorithmic); refresh {refresh_s * 1e3:.1f} ms")
@@ -471,8 +477,9 @@ def bench_uneven(wl, args, torch):
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": wl.name, "walkers": W, "sizes": list(wl.extra["sizes"]),
                        "class_walkers": {int(p.st.n): int(p.st.walkers) for p in uw.parts},
-                       "ranks": list(wl.ranks), "delay": K, "refresh_every": P, "mode": "forced-accept",
-                       "graph": graph is not None, "grid": uw.grid},
+                       "ranks": list(wl.ranks), "window_steps": K, "refresh_every": P, "mode": "forced-accept",
+                       "delay_per_class": {int(p.st.n): int(p.st.delay) for p in uw.parts},
+                       "delay_and_grid": "autotuned", "graph": graph is not None, "grid": uw.grid},
             "roofline": {"bound": "hbm", "kernel": "det_window_kernel", "achieved": wbytes / win / 1e9,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": wbytes / win / 1e9 / HBM_PEAK_GBS,
                          "traffic": None, "avg_us": win * 1e6, "bytes_per_launch": wbytes},

@@ -18,11 +18,20 @@ _INT = torch.int32
 
 
 class UnevenWalkers:
-    def __init__(self, dtype, classes, k_max, delays, steps, refresh_period=0, grid=None, device="cuda"):
+    def __init__(self, dtype, classes, k_max, delays, steps, refresh_period=0, grid=None, device="cuda",
+                 ranks=None):
         """classes: list of dicts {phi [2n][n] float64, occ [W][n], empty [W][n_empty]};
-        delays: K per class (int or list); steps: steps per window."""
+        delays: K per class (int or list), or "auto" (autotuned per size class for the
+        proposal ranks `ranks`); steps: steps per window; grid: work-groups of the
+        persistent launch, None (two per compute unit) or "auto" (autotuned)."""
+        if delays == "auto":
+            from . import autotune
+            rk = tuple(ranks) if ranks is not None else tuple(2 ** i for i in range(int(np.log2(k_max)) + 1))
+            delays = [autotune.tune_delay(dtype, int(np.asarray(c["occ"]).shape[1]), k_max, rk, device=device)
+                      for c in classes]
         if isinstance(delays, int):
             delays = [delays] * len(classes)
+        self.delays = [int(K) for K in delays]
         self.device = torch.device(device)
         self.steps, self.k_max, self.refresh_period = int(steps), int(k_max), int(refresh_period)
         self.parts, self.tables = [], []
@@ -48,11 +57,12 @@ class UnevenWalkers:
             self.parts.append(part)
         self.order = lrx.lrx_window_plan(self.parts, self.steps).to(self.device)
         self.queue = torch.zeros(1, dtype=_INT, device=self.device)
-        if grid is None:
-            cus = torch.cuda.get_device_properties(self.device).multi_processor_count
-            grid = 2 * cus
-        self.grid = int(grid)
+        cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+        self.grid = 2 * cus if grid in (None, "auto") else int(grid)
         self.windows = 0
+        if grid == "auto":
+            from . import autotune
+            autotune.tune_grid(self)
 
     @property
     def walkers(self):

@@ -175,3 +175,37 @@ def test_uneven_workload_full_size_sampled():
         np.testing.assert_array_equal(p.occ.cpu().numpy()[sample], book.occ)
         assert p.st.slot == 0
     say(f"  uneven f32 sampled ratio error max {worst:.2e}")
+
+
+def test_autotuned_delays_and_grid(tmp_path, monkeypatch):
+    """delays="auto" / grid="auto": the tuned K per class is one of the candidates, the
+    choices are cached, and the grid search leaves the walkers' state untouched."""
+    from paper_2602_05255_amd import autotune
+    monkeypatch.setenv("LRX_TUNE_CACHE", str(tmp_path / "tune.json"))
+    say("autotune")
+    g = gen.generator(970)
+    sizes, walkers, ranks = (64, 200), (40, 24), (1, 2, 4)
+    classes = small_classes(g, sizes, walkers)
+    steps = 8
+    uw = UnevenWalkers(torch.float64, classes, 4, "auto", steps, grid="auto", ranks=ranks)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert uw.grid % cus == 0 and 1 <= uw.grid // cus <= 4
+    for p, n in zip(uw.parts, sizes):
+        assert p.st.delay in autotune.delay_candidates(n, 4, ranks)
+        assert p.st.slot == 0
+    assert (tmp_path / "tune.json").exists()
+    chains = [orc.DetChain(c["phi"], c["occ"], c["empty"]) for c in classes]
+    draws = [gen.hop_draws_batch(g, steps, W, n, n, ranks, 4) for n, W in zip(sizes, walkers)]
+    uw.set_draws(draws)
+    uw.window(mode=lrx.LRX_MH_FORCE)
+    for p, chain, (k, e, s) in zip(uw.parts, chains, draws):
+        r = p.ratio.cpu().numpy()
+        for t in range(steps):
+            inv0, occ0 = chain.inv.copy(), chain.book.occ.copy()
+            r_o = chain.propose(k[t], e[t], s[t])
+            bnd = det_ratio_bound(p.table.cpu().numpy(), occ0, chain.book.proposed(k[t], e[t], s[t]), inv0,
+                                  k[t], e[t])
+            tol = np.maximum(1e-10, 8 * EPS64 * np.sqrt(1.0 + t) * bnd)
+            assert np.all(ratio_err(r[t], r_o) <= tol), (p.st.n, t)
+            chain.accept(k[t], e[t], s[t], np.isfinite(r_o) & (r_o != 0))
+        np.testing.assert_array_equal(p.occ.cpu().numpy(), chain.book.occ)
