@@ -473,14 +473,21 @@ __global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int
 // outside the outer panel becomes
 //   X_new[i] = X_old[pi(i)] + Zt[i] . X_old[pi(P)],   P = rows j0 .. j0+nbo-1,
 // an MFMA GEMM (v_mfma_f64_16x16x4f64; four real products per complex one)
-// with inner dimension nbo.  A work-group (4 waves) owns CB columns of one
-// walker and walks the rows in chunks of 64, 16 per wave.  Rows moved by pi
-// only ever come from the positions j0 .. j0+nbo-1, so the pre-update pivot
-// rows X_old[pi(P)] and the pre-update rows at those positions are all that
-// is staged in LDS; every other row is read and written in place by one lane.
-template <class Wd> constexpr int outer_cb() { return sizeof(Wd) == 8 ? 64 : 32; }
+// with inner dimension nbo.  Two facts keep it a plain streaming GEMM:
+//  * Zt[i] is the panel row X[i][j0..] except on P, where the identity comes
+//    off; there X_old[pi(i)] is the pivot row itself and cancels it, so
+//    X_new[i] = X[i][j0..] . X_old[pi(P)] on P (no initial value) and
+//    X_new[i] = X_old[pi(i)] + X[i][j0..] . X_old[pi(P)] elsewhere;
+//  * rows moved by pi outside P only ever come from positions in P, so all
+//    other row blocks are done first (reading those positions still unchanged)
+//    and the block of P last.  Only the pivot rows X_old[pi(P)] are staged.
+// A work-group (4 waves) owns CB columns of one walker and walks 64-row
+// blocks (16 rows per wave), loading the next block while the current one is
+// on the matrix cores.  Loads are unconditional from clamped addresses
+// (rows past n and columns past the batch are computed and not stored).
+template <class Wd> constexpr int outer_cb() { return sizeof(Wd) == 8 ? 32 : 16; }
 template <class Wd> size_t outer_lds(int n) {
-    return (((size_t)n * 4 + 15) / 16) * 16 + 2 * (size_t)64 * (outer_cb<Wd>() + 1) * sizeof(Wd);
+    return (((size_t)n * 4 + 15) / 16) * 16 + (size_t)64 * (outer_cb<Wd>() + 1) * sizeof(Wd);
 }
 
 template <class Wd, int CB>
@@ -489,6 +496,7 @@ __global__ __launch_bounds__(kT) void gj_outer_kernel(FA a, int j0, int nbo, int
     using A4 = typename Acc<R>::type;
     constexpr int NTL = CB / 16;          // 16-column MFMA tiles per wave
     constexpr int SP = CB + 1;            // padded LDS row stride
+    constexpr int NK = 64 / 4;            // 4-deep MFMA steps over the (zero-padded) outer panel
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int w = lb / ncb, cb = lb - w * ncb;
@@ -499,7 +507,6 @@ __global__ __launch_bounds__(kT) void gj_outer_kernel(FA a, int j0, int nbo, int
     const int *piv = wPiv(a, w);
     int *perm = reinterpret_cast<int *>(smem);                                   // [n]
     Wd *sXP = reinterpret_cast<Wd *>(smem + (((size_t)n * 4 + 15) / 16) * 16);    // [64][SP]: X_old[pi(j0+c)]
-    Wd *sOP = sXP + (size_t)64 * SP;                                              // [64][SP]: X_old[j0+c]
     for (int i = tid; i < n; i += kT) perm[i] = i;
     __syncthreads();
     if (tid == 0) {
@@ -510,65 +517,79 @@ __global__ __launch_bounds__(kT) void gj_outer_kernel(FA a, int j0, int nbo, int
     }
     __syncthreads();
     const int ci0 = cb * CB;
-    for (int idx = tid; idx < nbo * CB; idx += kT) {
+    auto colof = [&](int jj) {
+        const int ci = min(ci0 + jj, others - 1);
+        return ci < j0 ? ci : ci + nbo;
+    };
+    for (int idx = tid; idx < 64 * CB; idx += kT) {
         const int c = idx / CB, jj = idx - c * CB;
-        const int ci = ci0 + jj;
-        const int col = ci < j0 ? ci : ci + nbo;
-        const bool live = ci < others;
-        sXP[c * SP + jj] = live ? X[(size_t)perm[j0 + c] * n + col] : zero<Wd>();
-        sOP[c * SP + jj] = live ? X[(size_t)(j0 + c) * n + col] : zero<Wd>();
+        const Wd v = X[(size_t)perm[j0 + min(c, nbo - 1)] * n + colof(jj)];
+        sXP[c * SP + jj] = (c < nbo && ci0 + jj < others) ? v : zero<Wd>();
     }
     __syncthreads();
     const int kq = lane >> 4, lc = lane & 15;
-    for (int i0 = 0; i0 < n; i0 += 64) {
-        const int rbase = i0 + wv * 16;
+    int col[NTL];
+#pragma unroll
+    for (int jt = 0; jt < NTL; ++jt) col[jt] = colof(jt * 16 + lc);
+    const int nblk = (n + 63) / 64, pblk = j0 / 64;
+
+    struct Buf { Wd x[NTL][4]; Wd z[NK]; };
+    // block index t = 0 .. nblk-1: the other blocks in order, the P block last
+    auto blk_of = [&](int t) { return t < nblk - 1 ? (t < pblk ? t : t + 1) : pblk; };
+    auto issue = [&](int t, Buf &b) {
+        const int blk = blk_of(t);
+        const int rbase = blk * 64 + wv * 16;
+        const bool pb = blk == pblk;
+#pragma unroll
+        for (int jt = 0; jt < NTL; ++jt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = min(rbase + acc_row<R>(lane, r), n - 1);
+                b.x[jt][r] = pb ? zero<Wd>() : X[(size_t)perm[i] * n + col[jt]];
+            }
+        const int zrow = min(rbase + lc, n - 1);
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) b.z[kk] = X[(size_t)zrow * n + min(j0 + kk * 4 + kq, n - 1)];
+    };
+    auto consume = [&](int t, Buf &b) {
+        const int blk = blk_of(t);
+        const int rbase = blk * 64 + wv * 16;
         A4 re[NTL], im[NTL];
 #pragma unroll
-        for (int jt = 0; jt < NTL; ++jt) {
-            const int jj = jt * 16 + lc;
-            const int ci = ci0 + jj;
-            const int col = ci < j0 ? ci : ci + nbo;
-            const bool live = ci < others;
+        for (int jt = 0; jt < NTL; ++jt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = rbase + acc_row<R>(lane, r);
-                Wd v = zero<Wd>();
-                if (live && i < n) {
-                    const int src = perm[i];
-                    if (i >= j0 && i < j0 + nbo) v = sXP[(i - j0) * SP + jj];
-                    else if (src != i) v = sOP[(src - j0) * SP + jj];
-                    else v = X[(size_t)i * n + col];
-                }
-                re[jt][r] = re_(v);
-                im[jt][r] = im_(v);
-            }
-        }
-        const int zrow = rbase + lc;
-        for (int k0 = 0; k0 < nbo; k0 += 4) {
-            const int k = k0 + kq;
-            Wd z = zero<Wd>();
-            if (zrow < n && k < nbo) {
-                z = X[(size_t)zrow * n + j0 + k];
-                if (zrow == j0 + k) z = z - one<Wd>();
-            }
+            for (int r = 0; r < 4; ++r) { re[jt][r] = re_(b.x[jt][r]); im[jt][r] = im_(b.x[jt][r]); }
 #pragma unroll
-            for (int jt = 0; jt < NTL; ++jt) {
-                const Wd b = k < nbo ? sXP[k * SP + jt * 16 + lc] : zero<Wd>();
-                mac<Wd>(z, b, re[jt], im[jt]);
-            }
+        for (int kk = 0; kk < NK; ++kk) {
+            const int k = kk * 4 + kq;
+#pragma unroll
+            for (int jt = 0; jt < NTL; ++jt) mac<Wd>(b.z[kk], sXP[k * SP + jt * 16 + lc], re[jt], im[jt]);
         }
 #pragma unroll
         for (int jt = 0; jt < NTL; ++jt) {
-            const int ci = ci0 + jt * 16 + lc;
-            const int col = ci < j0 ? ci : ci + nbo;
-            if (ci >= others) continue;
+            if (ci0 + jt * 16 + lc >= others) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = rbase + acc_row<R>(lane, r);
-                if (i < n) X[(size_t)i * n + col] = make_<Wd>(re[jt][r], im[jt][r]);
+                if (i < n) X[(size_t)i * n + col[jt]] = make_<Wd>(re[jt][r], im[jt][r]);
             }
         }
+    };
+    // Every block except P first (they read the P positions, still unchanged),
+    // then a barrier, then P.
+    const int nA = nblk - 1;
+    Buf b0, b1;
+    if (nA > 0) issue(0, b0);
+    for (int t = 0; t < nA; t += 2) {
+        if (t + 1 < nA) issue(t + 1, b1);
+        consume(t, b0);
+        if (t + 1 >= nA) break;
+        if (t + 2 < nA) issue(t + 2, b0);
+        consume(t + 1, b1);
     }
+    __syncthreads();
+    issue(nA, b0);
+    consume(nA, b0);
 }
 
 // Column source of the final permutation: X (PB)^-1 -> B^-1 = X P, applied as

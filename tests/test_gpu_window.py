@@ -205,7 +205,10 @@ def test_autotuned_delays_and_grid(tmp_path, monkeypatch):
             r_o = chain.propose(k[t], e[t], s[t])
             bnd = det_ratio_bound(p.table.cpu().numpy(), occ0, chain.book.proposed(k[t], e[t], s[t]), inv0,
                                   k[t], e[t])
-            tol = np.maximum(1e-10, 8 * EPS64 * np.sqrt(1.0 + t) * bnd)
-            assert np.all(ratio_err(r[t], r_o) <= tol), (p.st.n, t)
+            # linear growth over the t updates since the start (no refresh in this test)
+            tol = np.maximum(1e-10, 8 * EPS64 * (1.0 + t) * bnd)
+            err = ratio_err(r[t], r_o)
+            bad = np.nonzero(err > tol)[0]
+            assert bad.size == 0, (p.st.n, p.st.delay, t, bad, err[bad], tol[bad], r[t][bad], r_o[bad])
             chain.accept(k[t], e[t], s[t], np.isfinite(r_o) & (r_o != 0))
         np.testing.assert_array_equal(p.occ.cpu().numpy(), chain.book.occ)
