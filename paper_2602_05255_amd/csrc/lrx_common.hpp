@@ -130,11 +130,33 @@ __device__ __forceinline__ double shfl_xor_v(double v, int m) {
 __device__ __forceinline__ cf32 shfl_xor_v(cf32 v, int m) { return {shfl_xor_v(v.x, m), shfl_xor_v(v.y, m)}; }
 __device__ __forceinline__ cf64 shfl_xor_v(cf64 v, int m) { return {shfl_xor_v(v.x, m), shfl_xor_v(v.y, m)}; }
 
+// The exchange distances below are template parameters (compile-time
+// recursion): a loop whose counter halves or doubles is not unrolled by the
+// compiler, and a rolled loop turns the value arrays into runtime-indexed
+// registers (one select per element per access).
+
+// Butterfly rounds lane ^ M, ..., lane ^ 32 on one value; every lane gets the sum.
+template <int M, class T> __device__ __forceinline__ T wave_fold(T r) {
+    if constexpr (M < LRX_WAVE) return wave_fold<M * 2>(r + shfl_xor_v(r, M));
+    else return r;
+}
+
 // Sum over the 64 lanes of a wave; every lane receives the total.
-template <class T> __device__ __forceinline__ T wave_sum(T v) {
+template <class T> __device__ __forceinline__ T wave_sum(T v) { return wave_fold<1>(v); }
+
+// One halving round of wave_sum_multi: exchange with lane ^ H, keep the upper
+// half of the live values on lanes with bit H set.
+template <int H, class T, int NV> __device__ __forceinline__ void wave_halve(T (&v)[NV], int lane) {
+    if constexpr (H >= 1) {
+        const bool up = (lane & H) != 0;
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = v + shfl_xor_v(v, m);
-    return v;
+        for (int i = 0; i < H; ++i) {
+            T send = up ? v[i] : v[i + H];
+            T keep = up ? v[i + H] : v[i];
+            v[i] = keep + shfl_xor_v(send, H);
+        }
+        wave_halve<H / 2>(v, lane);
+    }
 }
 
 // Reduce NV values per lane across the wave with a butterfly that halves the
@@ -145,21 +167,8 @@ template <class T> __device__ __forceinline__ T wave_sum(T v) {
 // power of two <= 64.  Cost: NV - 1 + 6 - log2(NV) exchanges instead of 6 NV.
 template <class T, int NV> __device__ __forceinline__ T wave_sum_multi(T (&v)[NV]) {
     const int lane = threadIdx.x & (LRX_WAVE - 1);
-#pragma unroll
-    for (int half = NV / 2; half >= 1; half >>= 1) {
-        const int bit = half;
-        const bool up = (lane & bit) != 0;
-#pragma unroll
-        for (int i = 0; i < half; ++i) {
-            T send = up ? v[i] : v[i + half];
-            T keep = up ? v[i + half] : v[i];
-            v[i] = keep + shfl_xor_v(send, bit);
-        }
-    }
-    T r = v[0];
-#pragma unroll
-    for (int m = NV; m < LRX_WAVE; m <<= 1) r = r + shfl_xor_v(r, m);
-    return r;
+    wave_halve<NV / 2>(v, lane);
+    return wave_fold<NV>(v[0]);
 }
 
 // Shuffle from an arbitrary lane (src taken modulo the wave size).

@@ -30,17 +30,10 @@ template <class T, int KM, int NW, int NI> hipError_t propose_t(const StepArgs &
     return hipGetLastError();
 }
 
-// One wave per walker while the per-thread column slices (2 NI KM values) fit
-// in about 64 VGPRs; otherwise four waves.
+// One wave per walker for n <= 64; otherwise four waves, each thread owning
+// NI = ceil(n / 256) entries of the columns.
 template <class T, int KM> hipError_t propose_n(const StepArgs &a, hipStream_t s) {
-    const int ni1 = (a.n + 63) / 64;
-    if ((size_t)ni1 * KM * sizeof(T) <= 128) {
-        if (ni1 <= 1) return propose_t<T, KM, 1, 1>(a, s);
-        if (ni1 <= 2) return propose_t<T, KM, 1, 2>(a, s);
-        if constexpr (KM * sizeof(T) <= 32) { if (ni1 <= 4) return propose_t<T, KM, 1, 4>(a, s); }
-        if constexpr (KM * sizeof(T) <= 16) { if (ni1 <= 8) return propose_t<T, KM, 1, 8>(a, s); }
-        if constexpr (KM * sizeof(T) <= 8) { if (ni1 <= 16) return propose_t<T, KM, 1, 16>(a, s); }
-    }
+    if (a.n <= 64) return propose_t<T, KM, 1, 1>(a, s);
     const int ni4 = (a.n + 255) / 256;
     if (ni4 <= 1) return propose_t<T, KM, 4, 1>(a, s);
     if constexpr (KM * sizeof(T) <= 64) {   // larger panels imply n <= 256 (LDS rule of the C ABI)

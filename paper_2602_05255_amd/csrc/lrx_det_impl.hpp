@@ -96,9 +96,11 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
     Wd *ratio_st = reinterpret_cast<Wd *>(st + a.L.ratio);
     const int *kslot = reinterpret_cast<const int *>(st + a.L.kslot);
 
-    T *s_fbI = reinterpret_cast<T *>(smem);                 // [KM][TE]
-    T *s_red = s_fbI + (size_t)KM * TE;                     // [NW][64]
-    int *s_live = reinterpret_cast<int *>(s_red + NW * 64);   // [TE]
+    const int TP = TE + 1;                                  // b-slot rows I, plus a zero column at TE
+    T *s_fbI = reinterpret_cast<T *>(smem);                 // [KM][TP]
+    T *s_red = s_fbI + (size_t)KM * TP;                     // [NW][64]
+    T *s_gpart = s_red + NW * 64;                           // [NW][TE * KM] per-wave partial G (NW > 1)
+    int *s_live = reinterpret_cast<int *>(s_gpart + (NW > 1 ? (size_t)NW * TE * KM : 0));   // [TE]
     int *s_ks = s_live + TE;                                   // [tau]
     __shared__ int s_rows[KM], s_src[KM], s_dst[KM];
     __shared__ int s_k, s_bad, s_nl;
@@ -131,7 +133,8 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
         __builtin_amdgcn_wave_barrier();
         if (b) atomicOr(&s_bad, 1);
     }
-    for (int idx = tid; idx < TE * KM; idx += NT) G[idx] = zero<T>();
+    if constexpr (NW == 1)
+        for (int idx = tid; idx < TE * KM; idx += NT) G[idx] = zero<T>();
     __syncthreads();
     if (tid == 0) {
         int nl = 0;
@@ -141,9 +144,9 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
     }
     const int k = s_k;
     const bool bad = s_bad != 0;
-    for (int idx = tid; idx < KM * TE; idx += NT) {
-        int c = idx / TE, te = idx - c * TE;
-        s_fbI[idx] = (c < k) ? fb[(size_t)s_rows[c] * KK + te] : zero<T>();
+    for (int idx = tid; idx < KM * TP; idx += NT) {
+        int c = idx / TP, te = idx - c * TP;
+        s_fbI[idx] = (c < k && te < TE) ? fb[(size_t)s_rows[c] * KK + te] : zero<T>();
     }
 
     // Loads from clamped, always valid addresses, then select: loads under
@@ -173,51 +176,66 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
         }
     }
     __syncthreads();
+    // Live slot columns in groups of GS: the loads of the next group are in
+    // flight while the current one is reduced (unconditional loads from clamped
+    // addresses; a padded entry multiplies the zero column TE of s_fbI and its
+    // G partial is dropped).  Each wave reduces G over its own part of i and
+    // keeps the partial in LDS, so the loop has no block barrier.
     const int nl = s_nl;
-    for (int g0 = 0; g0 < nl; g0 += GS) {
-        T gp[GS * KM];
-#pragma unroll
-        for (int q = 0; q < GS * KM; ++q) gp[q] = zero<T>();
-        T av[GS][NI];
-#pragma unroll
-        for (int gi = 0; gi < GS; ++gi) {
-            const bool tok = g0 + gi < nl;
-            const int te = tok ? s_live[g0 + gi] : 0;
-#pragma unroll
-            for (int ii = 0; ii < NI; ++ii) {
-                const int i = tid + ii * NT;
-                const T val = fa[(size_t)te * n + (i < n ? i : n - 1)];
-                av[gi][ii] = (tok && i < n) ? val : zero<T>();
-            }
-        }
+    auto load_grp = [&](int g0, T (&av)[GS][NI]) {
 #pragma unroll
         for (int gi = 0; gi < GS; ++gi) {
             const int te = (g0 + gi < nl) ? s_live[g0 + gi] : 0;
 #pragma unroll
+            for (int ii = 0; ii < NI; ++ii) av[gi][ii] = fa[(size_t)te * n + min(tid + ii * NT, n - 1)];
+        }
+    };
+    auto do_grp = [&](int g0, T (&av)[GS][NI]) {
+        T gp[GS * KM];
+#pragma unroll
+        for (int q = 0; q < GS * KM; ++q) gp[q] = zero<T>();
+#pragma unroll
+        for (int gi = 0; gi < GS; ++gi) {
+            const int te = (g0 + gi < nl) ? s_live[g0 + gi] : TE;
+#pragma unroll
             for (int ii = 0; ii < NI; ++ii)
 #pragma unroll
                 for (int c = 0; c < KM; ++c) {
-                    cv[ii][c] = fmsc(av[gi][ii], s_fbI[c * TE + te], cv[ii][c]);
+                    cv[ii][c] = fmsc(av[gi][ii], s_fbI[c * TP + te], cv[ii][c]);
                     gp[gi * KM + c] = fmac(av[gi][ii], uv[ii][c], gp[gi * KM + c]);
                 }
         }
         const T tot = wave_sum_multi<T, GS * KM>(gp);      // lane l: value l (gi = l / KM, c = l % KM)
-        if constexpr (NW == 1) {
-            if (lane < GS * KM && g0 + lane / KM < nl) {
-                const int c = lane % KM;
-                G[(size_t)s_live[g0 + lane / KM] * KM + c] = (c < k) ? tot : zero<T>();
-            }
-        } else {
-            if (lane < GS * KM) s_red[wv * 64 + lane] = tot;
-            __syncthreads();
-            if (tid < GS * KM && g0 + tid / KM < nl) {
-                T sum = zero<T>();
+        if (lane < GS * KM && g0 + lane / KM < nl) {
+            const int c = lane % KM;
+            const int idx = s_live[g0 + lane / KM] * KM + c;
+            if constexpr (NW == 1) G[idx] = (c < k) ? tot : zero<T>();
+            else s_gpart[(size_t)wv * TE * KM + idx] = tot;
+        }
+    };
+    {
+        T a0[GS][NI], a1[GS][NI];
+        int g0 = 0;
+        if (nl > 0) load_grp(0, a0);
+        while (g0 < nl) {
+            load_grp(g0 + GS, a1);
+            do_grp(g0, a0);
+            g0 += GS;
+            if (g0 >= nl) break;
+            load_grp(g0 + GS, a0);
+            do_grp(g0, a1);
+            g0 += GS;
+        }
+    }
+    if constexpr (NW > 1) {   // G = sum of the wave partials; dead slot columns and ranks >= k are zero
+        __syncthreads();
+        for (int idx = tid; idx < TE * KM; idx += NT) {
+            const int te = idx / KM, c = idx - te * KM;
+            const bool live = (te % KM) < s_ks[te / KM] && c < k;
+            T sum = zero<T>();
 #pragma unroll
-                for (int q = 0; q < NW; ++q) sum = sum + s_red[q * 64 + tid];
-                const int c = tid % KM;
-                G[(size_t)s_live[g0 + tid / KM] * KM + c] = (c < k) ? sum : zero<T>();
-            }
-            __syncthreads();
+            for (int q = 0; q < NW; ++q) sum = sum + s_gpart[(size_t)q * TE * KM + idx];
+            G[idx] = live ? sum : zero<T>();
         }
     }
     // C (stash, and slot a_tau = C of the delayed form, Eq. det_a; a rejected
@@ -276,7 +294,8 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
 
 template <class T, int KM, int NW> size_t propose_lds_bytes(int tau) {
     const size_t TE = (size_t)tau * KM;
-    return sizeof(T) * (KM * TE + (size_t)NW * 64) + sizeof(int) * (TE + (size_t)tau);
+    return sizeof(T) * (KM * (TE + 1) + (size_t)NW * 64 + (NW > 1 ? (size_t)NW * TE * KM : 0)) +
+           sizeof(int) * (TE + (size_t)tau);
 }
 
 template <class T, int KM, int NW, int NI>
