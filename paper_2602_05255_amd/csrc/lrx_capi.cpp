@@ -50,10 +50,15 @@ static int check_shape(const lrx_shape *s) {
         if (s->k_max > s->n) return LRX_ESHAPE;
         // accept kernel keeps u and C panels in LDS
         if (2 * (size_t)s->k_max * padded_n(s->n, es) * es > 65536) return LRX_EUNSUPPORTED;
-        // delayed accept: u panel, R^-1 and the slot products G in LDS
-        if (s->delay > 0 &&
-            (size_t)s->k_max * padded_n(s->n, es) * es + (size_t)(s->delay + 1) * s->k_max * s->k_max * es > 65536)
-            return LRX_EUNSUPPORTED;
+        // delayed accept: u panel, R^-1, the slot products G and the staged b_tau rows in LDS
+        if (s->delay > 0) {
+            const size_t np = padded_n(s->n, es);
+            const size_t per_row = (2 * np / 64 + s->k_max) * es;    // rows per batch as the kernel picks them
+            const size_t rb = 8 * per_row <= 192 ? 8 : (4 * per_row <= 192 ? 4 : (2 * per_row <= 192 ? 2 : 1));
+            if ((size_t)s->k_max * np * es + (size_t)(s->delay + 1) * s->k_max * s->k_max * es +
+                    4 * 16 * rb * s->k_max * es > 65536)
+                return LRX_EUNSUPPORTED;
+        }
         // delayed accept: a lane owns at most 4 slot columns
         if ((size_t)s->delay * s->k_max > 256) return LRX_ESHAPE;
         // propose keeps b-slot rows I in LDS

@@ -59,16 +59,17 @@ template <class T, int KM, int NEL, bool D> hipError_t accept_t(const StepArgs &
         return hipErrorInvalidValue;
     } else {
     constexpr int RB = rows_per_batch<T, NEL, KM>();
-    // Rows per block: enough blocks to fill 256 CUs several times over.
+    // Rows per block: long-lived blocks (set-up amortised over many rows) with
+    // still about eight blocks per compute unit.
     const int n = a.n;
     int rpb = kWaves * RB;
     long long blocks = (long long)a.W * ((n + rpb - 1) / rpb);
-    while (rpb < n && blocks > 8 * 256 * 4) {
+    while (rpb < n && blocks > 8 * 256) {
         rpb *= 2;
         blocks = (long long)a.W * ((n + rpb - 1) / rpb);
     }
     const int bpw = (n + rpb - 1) / rpb;
-    const size_t lds = accept_lds_bytes<T, KM, NEL, D>(a.K);
+    const size_t lds = accept_lds_bytes<T, KM, NEL, D, RB>(a.K);
     const dim3 grid((unsigned)(a.W * bpw)), block(kThreads);
     if (!D || a.K * KM <= LRX_WAVE)   // one slot column per lane
         hipLaunchKernelGGL((det_accept_kernel<T, KM, NEL, RB, 1, D>), grid, block, lds, s, a, rpb, bpw);

@@ -335,9 +335,15 @@ struct AcceptCtx {
     T *M, *fa, *fb;
     const T *s_g;           // slot products G[te][c] staged in LDS (delayed update)
     const T *s_u, *s_c, *s_ri;
+    T *s_z;                 // per-wave staging of b_tau values (delayed update), kZB batches
     int n, KK, tau, TE, q0, q1, npad, wv, lane;
     bool vec_ok;
 };
+
+// Batches of b_tau values a wave stages in LDS before writing them out: on
+// this hardware stores share the in-order counter with loads, so a store in
+// every batch would make the next batch's prefetched loads wait for it.
+constexpr int kZB = 16;
 
 template <class T, int KC, int KM, int NEL, int RB, int MG, bool DELAYED, int PD, bool VEC>
 __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
@@ -401,6 +407,7 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
         }
     };
     const int qstep = kWaves * RB;
+    int nzb = 0;                                 // staged batches of b_tau values
     // One batch: dots with u, slot correction, reduction, z, then the store.
     // The batch registers are used in place (no copies between ring buffers:
     // moving a register with a load still in flight would wait for it).
@@ -453,8 +460,7 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
             z = (my_r == r) ? zr : z;
         }
         if (DELAYED) {
-            const int q = qb + my_r;
-            if (lane < NV && q < c.q1) c.fb[(size_t)q * c.KK + c.tau * KM + my_c] = z;
+            if (lane < NV) c.s_z[(size_t)c.wv * kZB * NV + nzb * NV + lane] = z;
         } else {
 #pragma unroll
             for (int cc = 0; cc < KC; ++cc) {
@@ -502,11 +508,25 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
     if constexpr (S > 1) load_rows(qb + qstep, x1, b1);
     if constexpr (S > 2) load_rows(qb + 2 * qstep, x2, b2);
     if constexpr (S > 3) load_rows(qb + 3 * qstep, x3, b3);
+    // b_tau rows of the staged batches go out together (the wave's own LDS
+    // region: no block barrier; LDS operations of one wave stay in order).
+    auto flush_z = [&]() {
+        if constexpr (DELAYED) {
+            const int q00 = qb - nzb * qstep;     // first row of the staged batches
+            for (int idx = lane; idx < nzb * NV; idx += LRX_WAVE) {
+                const int j = idx / NV, v = idx - j * NV;
+                const int q = q00 + j * qstep + v / KC;
+                if (q < c.q1) c.fb[(size_t)q * c.KK + c.tau * KM + v % KC] = c.s_z[(size_t)c.wv * kZB * NV + idx];
+            }
+        }
+        nzb = 0;
+    };
     auto stage = [&](T (&x)[RB][NEL], T (&bq)[RB][MG]) -> bool {
         if (qb >= c.q1) return false;
         process(qb, x, bq);
         load_rows(qb + S * qstep, x, bq);   // clamped past the end
         qb += qstep;
+        if (DELAYED && ++nzb == kZB) flush_z();
         return true;
     };
     for (;;) {
@@ -515,6 +535,7 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
         if constexpr (S > 2) { if (!stage(x2, b2)) break; }
         if constexpr (S > 3) { if (!stage(x3, b3)) break; }
     }
+    if (DELAYED && nzb > 0) flush_z();
 }
 
 // Rows [q0, q1) of walker w; rb == 0 marks the block that also does the
@@ -592,6 +613,7 @@ __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, 
     T *s_c = DELAYED ? s_u : s_u + (size_t)KM * npad;       // [KM][npad], plain update only
     T *s_ri = s_c + (size_t)KM * npad;                      // [KM*KM]
     T *s_g = s_ri + KM * KM;                                // [TE][KM], delayed update only
+    T *s_z = s_g + (DELAYED ? (size_t)TE * KM : 0);         // [kWaves][kZB * RB * KM], delayed update only
     constexpr int UIT = (KM * NPAD + kThreads - 1) / kThreads;
     constexpr int GIT = DELAYED ? KM : 1;     // TE * KM <= 256 KM (the C ABI keeps K * KM <= 256)
     T ub[UIT], cb[DELAYED ? 1 : UIT];
@@ -637,7 +659,7 @@ __device__ __forceinline__ void det_accept_rows_block(const StepArgs &a, int w, 
     }
     __syncthreads();
 
-    AcceptCtx<T> ctx{M, fa, fb, s_g, s_u, s_c, s_ri, n, KK, tau, TE, q0, q1, npad, wv, lane, a.aligned != 0};
+    AcceptCtx<T> ctx{M, fa, fb, s_g, s_u, s_c, s_ri, s_z, n, KK, tau, TE, q0, q1, npad, wv, lane, a.aligned != 0};
     if (ctx.vec_ok) {
         if (kc == 1) {
             accept_rows<T, 1, KM, NEL, RB, MG, DELAYED, PD, true>(ctx);
@@ -701,9 +723,10 @@ __global__ void hop_commit_kernel(int W, int n, int n_empty, int KM, const int32
 
 // Dynamic LDS of det_accept_rows_block: u (and C for the plain update) panels
 // padded to whole 16-byte chunks per lane, R^-1, and the slot products G.
-template <class T, int KM, int NEL, bool DELAYED> size_t accept_lds_bytes(int K) {
+template <class T, int KM, int NEL, bool DELAYED, int RB = 8> size_t accept_lds_bytes(int K) {
     constexpr size_t npad = (size_t)(NEL / vec16<T>()) * vec16<T>() * LRX_WAVE;
-    return sizeof(T) * ((DELAYED ? 1 : 2) * KM * npad + KM * KM + (DELAYED ? (size_t)K * KM * KM : 0));
+    return sizeof(T) * ((DELAYED ? 1 : 2) * KM * npad + KM * KM +
+                        (DELAYED ? (size_t)K * KM * KM + (size_t)kWaves * kZB * RB * KM : 0));
 }
 
 // Rows per wave batch: the RB x NEL row values of PD + 1 batches plus the

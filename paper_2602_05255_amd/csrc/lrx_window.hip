@@ -113,7 +113,7 @@ __global__ void window_reset_kernel(uint32_t *queue) {
 template <class T, int KM> size_t window_lds_t(int K, int nch_max) {
     constexpr int V = vec16<T>();
     const size_t npad = (size_t)nch_max * V * LRX_WAVE;
-    const size_t acc = sizeof(T) * (KM * npad + KM * KM + (size_t)K * KM * KM);
+    const size_t acc = sizeof(T) * (KM * npad + KM * KM + (size_t)K * KM * KM + (size_t)kWaves * kZB * 8 * KM);
     const size_t prop = propose_lds_bytes<T, KM, 4>(K);
     const size_t fl = FlushLds<T>::bytes + sizeof(int) * ((size_t)K * KM + 1);
     return acc > prop ? (acc > fl ? acc : fl) : (prop > fl ? prop : fl);
