@@ -12,19 +12,18 @@
 //        entry); A^-1 by the same Gauss-Jordan kernels, then M = (X - X^T)/2.
 //
 // Two-level blocked Gauss-Jordan (all in the workspace X, row-major).  The
-// columns are taken in outer panels of up to 64; inside an outer panel,
-// sub-panels of nb columns (nb limited by LDS) are eliminated one at a time
-// and their transform is applied to the other columns of the outer panel
-// only.  The outer panel's columns then hold Zt + E_P, with I + Zt E_P^T the
-// composite transform of the whole outer panel, and every remaining column
-// gets it in one MFMA GEMM of inner dimension 64 (gj_outer_kernel).  Per
-// sub-panel:
-//   panel kernel : LU with partial pivoting of the panel rows j0..n-1 in LDS;
-//                  with Y_P the pivoted nb x nb diagonal block, the transform
-//                  that turns the panel into identity columns is I + Z E_P^T
-//                  with Z[P] = Y_P^-1 - I, Z[below] = -L21 L11^-1,
-//                  Z[above] = -Y_above Y_P^-1.  The panel columns become the
-//                  matching inverse columns, Z + E_P.
+// columns are taken in outer panels of up to 64; inside an outer panel, blocks
+// of 4 CPT columns (the whole outer panel for real data up to n = 512) are
+// eliminated one at a time and their transform is applied to the other
+// columns of the outer panel only.  The outer panel's columns then hold
+// Zt + E_P, with I + Zt E_P^T the composite transform of the whole outer
+// panel, and every remaining column gets it in one MFMA GEMM of inner
+// dimension 64 (gj_outer_kernel).  Per block:
+//   block kernel : in-place Gauss-Jordan of the n x nb block in registers
+//                  with partial pivoting; the block columns become Z + E_P,
+//                  I + Z E_P^T the transform that turns the block into
+//                  identity columns (Z also stored when other columns of the
+//                  outer panel remain).
 //   update kernel: the other columns of the outer panel: swap rows, then
 //                  X += Z X[P rows].
 //   final kernel : undo the row pivoting as a column permutation, cast to the
@@ -59,12 +58,12 @@ struct WorkLayout {
     size_t x, z, piv, src, acc, stride;
 };
 
-inline int panel_nb(int n, size_t ws) {
-    // Largest power of two <= 32 whose padded panel (n x (nb+1)) plus the two
-    // nb x nb triangular inverses fit in 96 KiB of LDS.
-    int nb = 32;
-    while (nb > 1 && ((size_t)n * (nb + 1) + 2 * (size_t)nb * nb) * ws > 98304) nb >>= 1;
-    return nb;
+// Columns per lane of the register-resident block kernel: the block is 4 CPT
+// wide (64 real / 32 complex up to n = 512; 32 real / 8 complex up to
+// n = 1024, where 16 waves share the register file).
+template <class Wd> int block_cpt(int n) {
+    if (sizeof(Wd) == 8) return n <= 512 ? 16 : 8;
+    return n <= 512 ? 8 : 2;
 }
 
 inline WorkLayout work_layout(int n, size_t ws) {
@@ -276,110 +275,309 @@ __global__ __launch_bounds__(kT) void parlett_reid_kernel(FA a) {
     }
 }
 
-// ------------------------------------------------------------------ GJ panel
-template <class Wd, int NB>
-__global__ __launch_bounds__(kT) void gj_panel_kernel(FA a, int j0, int nb) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double s_val[kT / 64];
-    __shared__ int s_idx[kT / 64];
-    const int w = blockIdx.x, n = a.n, m = n - j0;
-    Wd *X = wX<Wd>(a, w);
-    Wd *Z = wZ<Wd>(a, w);
-    int *piv = wPiv(a, w);
-    DetAcc *d = wAcc(a, w);
-    const int ps = nb + 1;                             // padded row stride (bank spread)
-    Wd *sP = reinterpret_cast<Wd *>(smem);            // [m][ps]
-    Wd *sLinv = sP + (size_t)m * ps;                   // [nb][nb]
-    Wd *sYinv = sLinv + nb * nb;                       // [nb][nb]
+// ------------------------------------------------------------------ GJ block
+// In-place Gauss-Jordan elimination of the column block [j0, j0 + nbw) of X
+// (the rows at positions >= j0 not yet used are the pivot candidates), with
+// the whole n x nbw block in registers.  Column c: pivot row p (largest |x|),
+// pi = x[p][c]; every other row r takes x[r] -= (x[r][c] / pi) x[p] and stores
+// -x[r][c] / pi in column c, row p becomes x[p] / pi with 1 / pi in column c.
+// After nbw columns the block holds the transform's columns Zt + E_P of the
+// elimination, the rows written in their pivoted positions (explicit swaps and
+// implicit pivoting give the same numbers up to that row order).  The division
+// of a pivot row by pi is deferred to the write-out: the elimination is linear
+// in each row, so the row is carried unscaled (1 in column c) with its factor
+// 1 / pi kept beside it.
+//
+// Layout: wave wv, lane l holds rows wv*64 + 4 (l/4) + {0..3} and the columns
+// q*CPT .. q*CPT + CPT-1 of the block, q = l % 4, so a row lives in one lane
+// quad.  One barrier per column: the quad holding each wave's best candidate
+// posts that row to the wave's LDS slot, lane 0 the key, row, position, pivot
+// value and its reciprocal (two sets of slots, alternating); after the
+// barrier every wave picks the winner over the waves and reads the pivot-row
+// segment of its lane's quarter back as broadcasts.  The next column is
+// updated first and sent round its quads before the rest of the update.  A
+// zero column (singular block) turns the update into x += 0 * u.
+template <class Wd, int CPT> constexpr int blk_qse() { return CPT + (int)(16 / sizeof(Wd)); }
+template <class Wd, int CPT> size_t blk_lds(int nw) {
+    return (size_t)2 * nw * (16 * blk_qse<Wd, CPT>() * sizeof(Wd) + 2 * sizeof(double) + 2 * sizeof(Wd)) +
+           (size_t)4 * CPT * (sizeof(Wd) + sizeof(int));
+}
 
-    for (int idx = threadIdx.x; idx < m * nb; idx += kT) {
-        const int i = idx / nb, c = idx - i * nb;
-        sP[i * ps + c] = X[(size_t)(j0 + i) * n + j0 + c];
+__device__ __forceinline__ double bperm(double v, int addr) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ cf64 bperm(cf64 v, int addr) { return {bperm(v.x, addr), bperm(v.y, addr)}; }
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ cf64 readlane_d(cf64 v, int l) { return {readlane_d(v.x, l), readlane_d(v.y, l)}; }
+__device__ __forceinline__ double rfl_double(double v) { return readlane_d(v, __builtin_amdgcn_readfirstlane(0)); }
+// Pivot key: |x| for real, |x|^2 for complex (same order, no square root).
+__device__ __forceinline__ double pivkey(double v) { return fabs(v); }
+__device__ __forceinline__ double pivkey(cf64 v) { return v.x * v.x + v.y * v.y; }
+__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+__device__ __forceinline__ cf64 recip(cf64 v) { return divv(one<cf64>(), v); }
+template <class Wd> __device__ __forceinline__ Wd sel(bool c, Wd a, Wd b) { return c ? a : b; }
+
+// State of one block elimination, shared by its column steps.
+template <class Wd, int CPT, int MAXT> struct BlkState {
+    static constexpr int QSE = blk_qse<Wd, CPT>();   // quarter stride (elements): 16 bytes of bank padding
+    static constexpr int RS = 4 * QSE;               // slot row stride
+    static constexpr int MAXW = MAXT / 64;
+    Wd x[4][CPT];
+    Wd rsc[4];       // 1 / pi of the rows that have been pivots, 1 otherwise
+    Wd v[4];         // the current column's values of the quad's rows
+    int pos[4];
+    unsigned elig;
+    bool sing;
+    int NW, j0, nbw, tid, lane, wv, q, gq, rbase, cq;
+    Wd *slots;       // [2][NW][4 rows][RS]
+    double *keys;    // [2][NW]
+    int2 *rowpos;    // [2][NW]
+    Wd *pvinv;       // [2][NW][2]
+    Wd *s_pv;        // [4 CPT] pivot values
+    int *s_piv;      // [4 CPT] swap partners
+};
+
+// Post the wave's best candidate for the current column (slot set PAR), then
+// the barrier.
+template <int PAR, class Wd, int CPT, int MAXT>
+__device__ __forceinline__ void blk_post(BlkState<Wd, CPT, MAXT> &S) {
+    using St = BlkState<Wd, CPT, MAXT>;
+    constexpr int RS = St::RS;
+    const int NW = S.NW, lane = S.lane, wv = S.wv;
+    double bk = -1.0;
+    int bi = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double kv = ((S.elig >> i) & 1u) ? pivkey(S.v[i]) : -1.0;
+        const bool tk = kv > bk;
+        bk = tk ? kv : bk;
+        bi = tk ? i : bi;
+    }
+    // the four lanes of a quad agree; rotate over the quads of each 16-lane row, then the rows
+    double m = fmax(bk, dpp_d<0x124>(bk));   // row_ror:4
+    m = fmax(m, dpp_d<0x128>(m));            // row_ror:8
+    m = fmax(fmax(readlane_d(m, 0), readlane_d(m, 16)), fmax(readlane_d(m, 32), readlane_d(m, 48)));
+    const unsigned long long bal = __ballot(bk == m);
+    const int wl = __builtin_ctzll(bal);
+    const int wbi = __builtin_amdgcn_readlane(bi, wl);
+    // (values, not lvalues: a select of addresses would keep the state in memory)
+    const int pb = sel(wbi == 0, S.pos[0], sel(wbi == 1, S.pos[1], sel(wbi == 2, S.pos[2], S.pos[3])));
+    const Wd vb = sel(wbi == 0, S.v[0], sel(wbi == 1, S.v[1], sel(wbi == 2, S.v[2], S.v[3])));
+    const int wpos = __builtin_amdgcn_readlane(pb, wl);
+    const Wd pv = readlane_d(vb, wl);
+    Wd *slot = S.slots + (size_t)(PAR * NW + wv) * 4 * RS + S.q * St::QSE;
+    if (S.gq == (wl >> 2)) {
+        // the winner row only; the distinct empty asm statement ending each
+        // case keeps the compiler from merging the four store sequences into
+        // one with selected operands
+        switch (wbi) {
+            case 0:
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) slot[k] = S.x[0][k];
+                asm volatile("; post row 0");
+                break;
+            case 1:
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) slot[RS + k] = S.x[1][k];
+                asm volatile("; post row 1");
+                break;
+            case 2:
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) slot[2 * RS + k] = S.x[2][k];
+                asm volatile("; post row 2");
+                break;
+            default:
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) slot[3 * RS + k] = S.x[3][k];
+                asm volatile("; post row 3");
+                break;
+        }
+    }
+    if (lane == 0) {
+        S.keys[PAR * NW + wv] = m;
+        S.rowpos[PAR * NW + wv] = make_int2(wv * 64 + (wl & ~3) + wbi, wpos);
+        S.pvinv[2 * (PAR * NW + wv)] = pv;
+        S.pvinv[2 * (PAR * NW + wv) + 1] = m > 0.0 ? recip(pv) : zero<Wd>();
     }
     __syncthreads();
-    double la = 0.0;
-    Wd ph = one<Wd>();
-    bool sing = false;
-    for (int c = 0; c < nb; ++c) {
-        double bv = -1.0;
-        int bi = -1;
-        for (int i = c + threadIdx.x; i < m; i += kT) {
-            double v = absv(sP[i * ps + c]);
-            if (bi < 0 || v > bv) { bv = v; bi = i; }
-        }
-        const int p = block_argmax(bv, bi, s_val, s_idx);
-        if (p != c) {
-            for (int cc = threadIdx.x; cc < nb; cc += kT) {
-                Wd t = sP[c * ps + cc];
-                sP[c * ps + cc] = sP[p * ps + cc];
-                sP[p * ps + cc] = t;
-            }
-            ph = -ph;
-        }
-        if (threadIdx.x == 0) piv[j0 + c] = j0 + p;
-        __syncthreads();
-        const Wd pv = sP[c * ps + c];
-        if (is_zero(pv)) { sing = true; continue; }
-        la += log(absv(pv));
-        ph = ph * unit(pv);
-        for (int i = c + 1 + threadIdx.x; i < m; i += kT) {
-            const Wd l = divv(sP[i * ps + c], pv);
-            sP[i * ps + c] = l;
-            for (int cc = c + 1; cc < nb; ++cc) sP[i * ps + cc] = fmsc(l, sP[c * ps + cc], sP[i * ps + cc]);
-        }
-        __syncthreads();
+}
+
+// Finish column c = cq * CPT + KK (KK a compile-time constant, so x[.][KK]
+// stays in registers): winner over the waves, update, bookkeeping; leaves the
+// next column's values in S.v.
+template <int KK, class Wd, int CPT, int MAXT>
+__device__ __forceinline__ void blk_finish(BlkState<Wd, CPT, MAXT> &S) {
+    using St = BlkState<Wd, CPT, MAXT>;
+    constexpr int PAR = KK & 1;      // = c & 1 (CPT is even)
+    constexpr int NK = KK + 1 < CPT ? KK + 1 : 0;
+    const int c = S.cq * CPT + KK;
+    const int NW = S.NW, q = S.q, rbase = S.rbase;
+    // winner over the waves: largest key, lowest wave on ties
+    double bkey = S.keys[PAR * NW];
+    int wb = 0;
+#pragma unroll
+    for (int u = 1; u < St::MAXW; ++u) {
+        const double o = S.keys[PAR * NW + min(u, NW - 1)];
+        const bool tk = u < NW && o > bkey;
+        bkey = tk ? o : bkey;
+        wb = tk ? u : wb;
     }
-    if (threadIdx.x == 0) {
-        if (sing) d->singular = 1;
-        d->logabs += la;
-        Wd old = get_ph<Wd>(d->ph);
-        set_ph(d->ph, old * ph);
+    wb = __builtin_amdgcn_readfirstlane(wb);
+    bkey = rfl_double(bkey);
+    const int2 rpv = S.rowpos[PAR * NW + wb];
+    const int p = __builtin_amdgcn_readfirstlane(rpv.x);
+    const int ppos = __builtin_amdgcn_readfirstlane(rpv.y);
+    const Wd pv = S.pvinv[2 * (PAR * NW + wb)];
+    const Wd inv = S.pvinv[2 * (PAR * NW + wb) + 1];
+    const bool sg = !(bkey > 0.0);
+    const Wd *ur = S.slots + (size_t)(PAR * NW + wb) * 4 * St::RS + (p & 3) * St::RS + q * St::QSE;
+    Wd u[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) u[k] = ur[k];
+    // g = -x[c] / pi; the pivot row is left as it is (unscaled)
+    Wd g[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[i] = sel(rbase + i == p, zero<Wd>(), -(S.v[i] * inv));
+    // next column first, and round the quads
+    const int nsrc = ((S.lane & ~3) | (KK + 1 < CPT ? S.cq : S.cq + 1)) << 2;
+    Wd vn[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        S.x[i][NK] = fmac(g[i], u[NK], S.x[i][NK]);
+        vn[i] = bperm(S.x[i][NK], nsrc);
     }
-    // L11^-1 (unit lower) and Y_P^-1 = U11^-1 L11^-1, one column per thread,
-    // solved directly in LDS (column e is private to thread e).
-    if (threadIdx.x < nb) {
-        const int e = threadIdx.x;
-        for (int r = 0; r < nb; ++r) {
-            Wd s = (r == e) ? one<Wd>() : zero<Wd>();
-            for (int q = 0; q < r; ++q) s = fmsc(sP[r * ps + q], sLinv[q * nb + e], s);
-            sLinv[r * nb + e] = s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+            if (k != NK) S.x[i][k] = fmac(g[i], u[k], S.x[i][k]);
+    // column c: -x[c] / pi (1 on the unscaled pivot row); positions: the pivot
+    // row moves to t, the row at t to the pivot's old place
+    const int t = S.j0 + c;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool isp = rbase + i == p && !sg;
+        if (q == S.cq && !sg) S.x[i][KK] = sel(isp, one<Wd>(), g[i]);
+        S.rsc[i] = sel(isp, inv, S.rsc[i]);
+        const bool at_t = S.pos[i] == t;
+        const bool clr = sg ? at_t : isp;
+        S.pos[i] = isp ? t : ((!sg && at_t) ? ppos : S.pos[i]);
+        S.elig = clr ? (S.elig & ~(1u << i)) : S.elig;
+        S.v[i] = vn[i];
+    }
+    S.sing = S.sing || sg;
+    if (S.tid == 0) { S.s_piv[c] = sg ? t : ppos; S.s_pv[c] = sg ? zero<Wd>() : pv; }
+}
+
+template <int KK, class Wd, int CPT, int MAXT>
+__device__ __forceinline__ void blk_run(BlkState<Wd, CPT, MAXT> &S) {
+    if constexpr (KK < CPT) {
+        const int c = S.cq * CPT + KK;
+        if (c < S.nbw) {
+            blk_finish<KK>(S);
+            if (c + 1 < S.nbw) blk_post<(KK + 1) & 1>(S);
+            blk_run<KK + 1>(S);
         }
-        for (int r = nb - 1; r >= 0; --r) {
-            Wd s = sLinv[r * nb + e];
-            for (int q = r + 1; q < nb; ++q) s = fmsc(sP[r * ps + q], sYinv[q * nb + e], s);
-            const Wd dg = sP[r * ps + r];
-            sYinv[r * nb + e] = is_zero(dg) ? zero<Wd>() : divv(s, dg);
+    }
+}
+
+template <class Wd, int CPT, int MAXT>
+__global__ __launch_bounds__(MAXT) void gj_block_kernel(FA a, int j0, int nbw, int write_z) {
+    using St = BlkState<Wd, CPT, MAXT>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    St S;
+    S.NW = blockDim.x >> 6;
+    const int w = blockIdx.x, n = a.n;
+    S.j0 = j0;
+    S.nbw = nbw;
+    S.tid = threadIdx.x;
+    S.lane = S.tid & 63;
+    S.wv = __builtin_amdgcn_readfirstlane(S.tid >> 6);
+    S.q = S.lane & 3;
+    S.gq = S.lane >> 2;
+    S.rbase = S.wv * 64 + S.gq * 4;
+    const int q = S.q, rbase = S.rbase, NW = S.NW;
+    Wd *X = wX<Wd>(a, w);
+    S.slots = reinterpret_cast<Wd *>(smem);
+    S.keys = reinterpret_cast<double *>(S.slots + (size_t)2 * NW * 4 * St::RS);
+    S.rowpos = reinterpret_cast<int2 *>(S.keys + 2 * NW);
+    S.pvinv = reinterpret_cast<Wd *>(S.rowpos + 2 * NW);
+    S.s_pv = S.pvinv + 4 * NW;
+    S.s_piv = reinterpret_cast<int *>(S.s_pv + 4 * CPT);
+    S.elig = 0;
+    S.sing = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = rbase + i;
+        S.pos[i] = r;
+        S.rsc[i] = one<Wd>();
+        const bool ok = r < n;
+        if (ok && r >= j0) S.elig |= 1u << i;
+        const Wd *row = X + (size_t)min(r, n - 1) * n + j0;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int cc = q * CPT + k;
+            const Wd xv = row[min(cc, nbw - 1)];
+            S.x[i][k] = (ok && cc < nbw) ? xv : zero<Wd>();
         }
+    }
+    S.cq = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.v[i] = bperm(S.x[i][0], (S.lane & ~3) << 2);
+    blk_post<0>(S);
+    for (int cq = 0; cq < 4; ++cq) {
+        S.cq = cq;
+        blk_run<0>(S);
     }
     __syncthreads();
-    // Z rows and the new panel columns of X.
-    for (int i = threadIdx.x; i < n; i += kT) {
-        Wd z[NB];
+    Wd *Z = wZ<Wd>(a, w);
 #pragma unroll
-        for (int c = 0; c < NB; ++c) z[c] = zero<Wd>();
-        if (i < j0) {
-            for (int q = 0; q < nb; ++q) {
-                const Wd yq = X[(size_t)i * n + j0 + q];
+    for (int i = 0; i < 4; ++i) {
+        if (rbase + i >= n) continue;
+        Wd *row = X + (size_t)S.pos[i] * n + j0;
+        Wd *zr = Z + (size_t)S.pos[i] * nbw;
 #pragma unroll
-                for (int c = 0; c < NB; ++c) if (c < nb) z[c] = fmsc(yq, sYinv[q * nb + c], z[c]);
-            }
-        } else if (i < j0 + nb) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < nb) z[c] = sYinv[(i - j0) * nb + c] - ((i - j0 == c) ? one<Wd>() : zero<Wd>());
-        } else {
-            for (int q = 0; q < nb; ++q) {
-                const Wd lq = sP[(i - j0) * ps + q];
-#pragma unroll
-                for (int c = 0; c < NB; ++c) if (c < nb) z[c] = fmsc(lq, sLinv[q * nb + c], z[c]);
-            }
+        for (int k = 0; k < CPT; ++k) {
+            const int cc = q * CPT + k;
+            const Wd xv = S.x[i][k] * S.rsc[i];
+            if (cc < nbw) row[cc] = xv;
+            if (write_z && cc < nbw) zr[cc] = xv - ((S.pos[i] == j0 + cc) ? one<Wd>() : zero<Wd>());
         }
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            if (c < nb) {
-                Z[(size_t)i * nb + c] = z[c];
-                X[(size_t)i * n + j0 + c] = z[c] + ((i == j0 + c) ? one<Wd>() : zero<Wd>());
+    }
+    if (S.wv == 0) {
+        const int lane = S.lane;
+        double la = 0.0;
+        if (lane < nbw) {
+            const Wd pv = S.s_pv[lane];
+            if (!is_zero(pv)) la = log(absv(pv));
+            wPiv(a, w)[j0 + lane] = S.s_piv[lane];
+        }
+        la = wave_sum(la);
+        if (lane == 0) {
+            Wd ph = one<Wd>();
+            for (int c = 0; c < nbw; ++c) {
+                const Wd pv = S.s_pv[c];
+                if (!is_zero(pv)) ph = ph * unit(pv);
+                if (S.s_piv[c] != j0 + c) ph = -ph;
             }
+            DetAcc *d = wAcc(a, w);
+            if (S.sing) d->singular = 1;
+            d->logabs += la;
+            set_ph(d->ph, get_ph<Wd>(d->ph) * ph);
         }
     }
 }
@@ -773,6 +971,23 @@ hipError_t launch_update(const FA &fa, int j0, int nb, int c_lo, int c_hi, hipSt
     return hipGetLastError();
 }
 
+template <class Wd>
+hipError_t launch_block(const FA &fa, int j0, int nbw, int write_z, hipStream_t s) {
+    const int nw = (fa.n + 63) / 64;
+    const dim3 grid((unsigned)fa.W), block((unsigned)(64 * nw));
+    constexpr int CW = sizeof(Wd) == 8 ? 16 : 8;     // n <= 512
+    constexpr int CN = sizeof(Wd) == 8 ? 8 : 2;      // n <= 1024
+    if (block_cpt<Wd>(fa.n) == CW) {
+        const size_t lds = blk_lds<Wd, CW>(nw);
+        if (nw <= 4) hipLaunchKernelGGL((gj_block_kernel<Wd, CW, 256>), grid, block, lds, s, fa, j0, nbw, write_z);
+        else hipLaunchKernelGGL((gj_block_kernel<Wd, CW, 512>), grid, block, lds, s, fa, j0, nbw, write_z);
+    } else {
+        const size_t lds = blk_lds<Wd, CN>(nw);
+        hipLaunchKernelGGL((gj_block_kernel<Wd, CN, 1024>), grid, block, lds, s, fa, j0, nbw, write_z);
+    }
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     using Wd = typename Wide<T>::type;
@@ -783,7 +998,6 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     a.L = work_layout(in.n, sizeof(Wd));
     a.inv = in.inv; a.logabs = in.logabs; a.phase = in.phase; a.flags = in.flags;
     a.report = in.report; a.refresh = in.refresh;
-    a.nb = panel_nb(in.n, sizeof(Wd));
     const int n = in.n, W = in.W;
     const int tiles = (n + 31) / 32;
     hipError_t e;
@@ -795,24 +1009,19 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     constexpr int kOuter = 64;
+    const int pwb = 4 * block_cpt<Wd>(n);
+    a.nb = pwb;
     for (int o0 = 0; o0 < n; o0 += kOuter) {
-      const int nbo = min(kOuter, n - o0);
-      for (int j0 = o0; j0 < o0 + nbo; j0 += a.nb) {
-        const int nb = min(a.nb, o0 + nbo - j0);
-        const size_t lds = sizeof(Wd) * ((size_t)(n - j0) * (nb + 1) + 2 * (size_t)nb * nb);
-        switch (a.nb) {
-            case 32: hipLaunchKernelGGL((gj_panel_kernel<Wd, 32>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
-            case 16: hipLaunchKernelGGL((gj_panel_kernel<Wd, 16>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
-            case 8: hipLaunchKernelGGL((gj_panel_kernel<Wd, 8>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
-            case 4: hipLaunchKernelGGL((gj_panel_kernel<Wd, 4>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
-            case 2: hipLaunchKernelGGL((gj_panel_kernel<Wd, 2>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
-            default: hipLaunchKernelGGL((gj_panel_kernel<Wd, 1>), dim3(W), dim3(kT), lds, s, a, j0, nb); break;
+        const int nbo = min(kOuter, n - o0);
+        for (int j0 = o0; j0 < o0 + nbo; j0 += pwb) {
+            const int nbw = min(pwb, o0 + nbo - j0);
+            e = launch_block<Wd>(a, j0, nbw, nbw < nbo ? 1 : 0, s);
+            if (e != hipSuccess) return e;
+            e = launch_update<Wd>(a, j0, nbw, o0, o0 + nbo, s);
+            if (e != hipSuccess) return e;
         }
-        e = launch_update<Wd>(a, j0, nb, o0, o0 + nbo, s);
+        e = launch_outer<Wd>(a, o0, nbo, s);
         if (e != hipSuccess) return e;
-      }
-      e = launch_outer<Wd>(a, o0, nbo, s);
-      if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(src_perm_kernel, dim3(W), dim3(kT), sizeof(int) * 2 * (size_t)n, s, a);
     if (a.kind == LRX_DET) {
