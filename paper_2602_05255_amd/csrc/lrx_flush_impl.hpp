@@ -61,16 +61,25 @@ __device__ __forceinline__ void mac(T a, T b, typename Acc<typename Real<T>::typ
 // ------------------------------------------------------------------ DET
 // Live slot columns: slot t holds k_t = kslot[t] columns t*KM + c (c < k_t);
 // rejected steps (k_t = 0) and the zero padding beyond k_t contribute nothing
-// to M0 -= B A^T, so the flush contracts over the live columns only.
-// All threads of the block call this; s_live must hold tau*KM ints.
+// to M0 -= B A^T, so the flush contracts over the live columns only.  The
+// first wave builds the list, one lane per slot (tau <= 64): an inclusive
+// scan of the k_t gives each slot its place.  All threads of the block call
+// this; s_live must hold tau*KM ints.
+template <int D> __device__ __forceinline__ int scan_up(int s, int t) {
+    if constexpr (D < LRX_WAVE) {
+        const int o = __shfl_up(s, D, LRX_WAVE);
+        return scan_up<D * 2>(t >= D ? s + o : s, t);
+    } else {
+        return s;
+    }
+}
 __device__ __forceinline__ int det_live_columns(const int *kslot, int tau, int KM, int *s_live, int *s_n) {
-    if (threadIdx.x == 0) {
-        int nl = 0;
-        for (int t = 0; t < tau; ++t) {
-            const int kt = min(max(kslot[t], 0), KM);
-            for (int c = 0; c < kt; ++c) s_live[nl++] = t * KM + c;
-        }
-        *s_n = nl;
+    if (threadIdx.x < LRX_WAVE) {
+        const int t = threadIdx.x;
+        const int kt = t < tau ? min(max(kslot[max(min(t, tau - 1), 0)], 0), KM) : 0;
+        const int incl = scan_up<1>(kt, t);
+        for (int c = 0; c < kt; ++c) s_live[incl - kt + c] = t * KM + c;
+        if (t == LRX_WAVE - 1) *s_n = incl;
     }
     __syncthreads();
     return *s_n;
