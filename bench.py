@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recompute", action="store_true")
+    ap.add_argument("--sizes", default=None, help="n-sweep sizes, comma separated (default 64,...,1024)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -486,6 +487,63 @@ def bench_uneven(wl, args, torch):
             "refresh_ms": refresh_s * 1e3}
 
 
+def bench_nsweep(wl, args, torch):
+    """Single-hop determinant LRU against full recompute on the same GPU, n = 64 .. 1024
+    (the shape of the paper's speedup-vs-n figure).  Per n: the delayed LRU (K near the
+    byte-model optimum, forced accept, FP64 refresh every 128 steps amortised) in FP64 and
+    FP32 bulk, and torch.linalg.slogdet of the gathered Phi[occ] (rocSOLVER LU) in FP64."""
+    from paper_2602_05255_amd import inputs as gen
+    sizes = [int(x) for x in args.sizes.split(",")] if args.sizes else list(wl.extra["sizes"])
+    W = args.walkers or wl.walkers
+    rows = []
+    for n in sizes:
+        wn = gen.nsweep_workload(n)
+        log(f"n-sweep n={n}: W={W} L={wn.sites} K={wn.delay} refresh={wn.refresh}")
+        run64, r64 = measure(wn, torch.float64, W, args, torch, f"f64 n={n}")
+        err64 = rel_error(run64, torch, np.linspace(0, W - 1, 4).astype(int))
+        rc = recompute(wn, run64, torch, reps=3)
+        del run64
+        torch.cuda.empty_cache()
+        row = {"n": n, "delay": wn.delay,
+               "lru_f64": r64["value"], "accept_gbs_f64": r64["accept_gbs"],
+               "accept_hbm_frac_f64": r64["accept_gbs"] / HBM_PEAK_GBS, "refresh_ms": r64["refresh_ms"],
+               "rel_error_f64": err64, "recompute": rc}
+        if not args.no_fp32:
+            run32, r32 = measure(wn, torch.float32, W, args, torch, f"f32 n={n}")
+            row["lru_f32"] = r32["value"]
+            row["accept_gbs_f32"] = r32["accept_gbs"]
+            del run32
+            torch.cuda.empty_cache()
+        # this library's own full recompute: the FP64 refresh (gather, Gauss-Jordan inverse
+        # and log|det| of every walker), timed inside the LRU run
+        own = W / (r64["refresh_ms"] * 1e-3)
+        row["recompute_own_gj"] = {"walker_steps_per_s": own, "what": "slogdet + inverse, FP64 Gauss-Jordan refresh"}
+        row["speedup_f64_vs_own_gj"] = r64["value"] / own
+        if "lru_f32" in row:
+            row["speedup_f32_bulk_vs_own_gj"] = row["lru_f32"] / own
+        rs = rc.get("slogdet", {}).get("walker_steps_per_s")
+        if rs:
+            row["speedup_f64"] = r64["value"] / rs
+            row["recompute_tflops"] = rc["slogdet"]["tflops"]
+            row["recompute_fp64_frac"] = rc["slogdet"]["tflops"] / FP64_PEAK_TFS
+            if "lru_f32" in row:
+                row["speedup_f32_bulk"] = row["lru_f32"] / rs
+        log(f"  n={n}: LRU f64 {r64['value']:.4g}/s, recompute rocSOLVER {rs if rs else float('nan'):.4g}/s "
+            f"(speedup {row.get('speedup_f64', float('nan')):.1f}x, f32 bulk {row.get('speedup_f32_bulk', float('nan')):.1f}x), "
+            f"own GJ {own:.4g}/s (speedup {row['speedup_f64_vs_own_gj']:.1f}x, "
+            f"f32 bulk {row.get('speedup_f32_bulk_vs_own_gj', float('nan')):.1f}x)")
+        rows.append(row)
+    top = rows[-1]
+    return {"metric": METRIC, "value": top["lru_f64"], "unit": "walker-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": wl.name, "walkers": W, "sizes": sizes, "ranks": [1],
+                       "delay_per_n": {str(r["n"]): r["delay"] for r in rows}, "refresh_every": wl.refresh,
+                       "mode": "forced-accept"},
+            "speedup_vs_recompute_at_largest_n": top.get("speedup_f64"),
+            "speedup_vs_own_gj_recompute_at_largest_n": top.get("speedup_f64_vs_own_gj"), "sweep": rows}
+
+
 def copy_calibration(torch, nbytes=1 << 30, reps=5):
     """A plain device copy of nbytes (read nbytes, write nbytes): the reference
     that scales the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -527,6 +585,9 @@ def main():
         return
     if wl.name == "uneven_n64_1024_fp32":
         print(json.dumps(bench_uneven(wl, args, torch)), flush=True)
+        return
+    if wl.name == "nsweep_det_k1":
+        print(json.dumps(bench_nsweep(wl, args, torch)), flush=True)
         return
     assert wl.kind == "det" and wl.n > 0, "the default benchmark drives a uniform-n determinant workload"
     W = args.walkers or wl.walkers

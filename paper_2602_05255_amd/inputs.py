@@ -15,6 +15,7 @@ Complex normal CN(0, s2): real and imaginary parts iid N(0, s2/2).
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -132,10 +133,29 @@ WORKLOADS = {
     "uneven_n64_1024_fp32": Workload("uneven_n64_1024_fp32", "det", 0, 0, 4096, (1, 2, 4, 8), 8, 16, 128,
                                      False, "f32", steps=128, seed=SEED_BASE + 4,
                                      extra={"sizes": (64, 128, 256, 512, 1024)}),
+    # n-sweep of the single-hop determinant LRU (the shape of the paper's speedup-vs-n figure):
+    # 1024 walkers, k = 1, L = 2n, n in {64 .. 1024}; one workload per n from nsweep_workload.
+    "nsweep_det_k1": Workload("nsweep_det_k1", "det", 0, 0, 1024, (1,), 1, 0, 128,
+                              False, "f64", steps=128, seed=SEED_BASE + 6,
+                              extra={"sizes": (64, 128, 256, 512, 1024)}),
     # Differentiated log-psi: c64 Phi 1024x512 + rank-8 B C^T per sample, 512 samples.
     "logpsi_grad_n512_c64": Workload("logpsi_grad_n512_c64", "det", 1024, 512, 512, (8,), 8, 0, 0,
                                      True, "c64", seed=SEED_BASE + 5, extra={"rank": 8, "bc_var": 0.1}),
 }
+
+
+def nsweep_delay(n: int, kbar: float = 1.0) -> int:
+    """Delay for the n-sweep: the power of two nearest (in log scale) to the byte-model
+    optimum K* = sqrt(2 n / kbar), capped at 64."""
+    k_star = math.sqrt(2.0 * n / kbar)
+    return int(min(64, 2 ** round(math.log2(k_star))))
+
+
+def nsweep_workload(n: int) -> Workload:
+    """One size of the n-sweep: Phi (2n x n) N(0,1), 1024 walkers, single hops, FP64 refresh every 128."""
+    base = WORKLOADS["nsweep_det_k1"]
+    return Workload(f"nsweep_det_k1_n{n}", "det", 2 * n, n, base.walkers, (1,), 1, nsweep_delay(n),
+                    base.refresh, False, "f64", steps=base.steps, seed=base.seed + n)
 
 
 def slater_inputs(wl: Workload, walkers: int | None = None, seed_offset: int = 0):
