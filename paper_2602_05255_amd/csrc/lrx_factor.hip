@@ -209,64 +209,169 @@ __device__ int block_argmax(double val, int idx, double *s_val, int *s_idx) {
 }
 
 // ------------------------------------------------------------------ Parlett-Reid
-// Unblocked, one work-group per matrix, on the workspace copy of A (PF only).
-// Uses the skew symmetry of every trailing block: column j below the
-// diagonal is minus row j to the right of it, so the pivot search reads a
-// contiguous row.
+// One work-group per matrix, on the workspace copy X of A (PF only), in the
+// every-other-column form: for j = 0, 2, ...: pivot p = argmax_{i>j} |A[j][i]|
+// (|A[i][j]| by skewness), swap index j+1 <-> p (rows and columns, sign flip),
+// alpha = A[j][j+1] (the Pfaffian gains the factor alpha), then the skew
+// rank-2 update A[r][s] += w_r c_s - c_r w_s (r, s >= j+2) with
+// c = A[j][j+2:] / alpha and w = A[j+1][j+2:]  (Appendix A: pf(B A B^T) =
+// det(B) pf(A), and the block Schur step of Eq. pf_block).
+//
+// Blocked: the rank-2 updates of kPrPairs consecutive pairs are kept as
+// pending vectors (c_t, w_t) in the workspace; the two rows each pair needs
+// are rebuilt from X plus the pending terms, swaps are applied to X and to
+// the pending vectors alike, and at the end of the block the trailing matrix
+// takes all pending terms in one MFMA GEMM of inner dimension 2 kPrPairs
+// (X[J][J] += P Q^T with P = [w_t, -c_t], Q = [c_t, w_t]).  X is then read and
+// written once per block instead of once per pair.
+constexpr int kPrPairs = 16;
+constexpr int kPrThreads = 256;
+
+// Pivot key: |x| for real, |x|^2 for complex (same order, no square root).
+__device__ __forceinline__ double pivkey(double v) { return fabs(v); }
+__device__ __forceinline__ double pivkey(cf64 v) { return v.x * v.x + v.y * v.y; }
+__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+__device__ __forceinline__ cf64 recip(cf64 v) { return divv(one<cf64>(), v); }
+
+// X[r][s] += sum_{t<T} w_t[r] c_t[s] - c_t[r] w_t[s] for r, s in [j0, n).
+// 64 x 64 tiles, wave wv owns 16 rows of the tile as four 16x16 MFMA blocks.
 template <class Wd>
-__global__ __launch_bounds__(kT) void parlett_reid_kernel(FA a) {
-    __shared__ double s_val[kT / 64];
-    __shared__ int s_idx[kT / 64];
-    const int w = blockIdx.x, n = a.n;
+__device__ __forceinline__ void pr_trailing_update(Wd *X, const Wd *Cp, const Wd *Wp, int n, int T, int j0) {
+    using R = typename Real<Wd>::type;
+    using A4 = typename Acc<R>::type;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kq = lane >> 4, lc = lane & 15;
+    const int m = n - j0, nt = (m + 63) / 64, K2 = 2 * T;
+    for (int tile = 0; tile < nt * nt; ++tile) {
+        const int r0 = j0 + (tile / nt) * 64, s0 = j0 + (tile % nt) * 64;
+        const int rbase = r0 + wv * 16;
+        A4 re[4], im[4];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            const int sc = min(s0 + jb * 16 + lc, n - 1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const Wd v = X[(size_t)min(rbase + acc_row<R>(lane, r), n - 1) * n + sc];
+                re[jb][r] = re_(v);
+                im[jb][r] = im_(v);
+            }
+        }
+        const int ra = min(rbase + lc, n - 1);
+        for (int k0 = 0; k0 < K2; k0 += 4) {
+            const int k = k0 + kq;
+            const bool kin = k < K2;
+            const int t = kin ? (k < T ? k : k - T) : 0;
+            // P[r][k]: w_k[r] (k < T), -c_{k-T}[r]; Q[k][s]: c_k[s] (k < T), w_{k-T}[s]
+            const Wd *pa = (k < T ? Wp : Cp) + (size_t)t * n;
+            const Wd *qb = (k < T ? Cp : Wp) + (size_t)t * n;
+            Wd av = pa[ra];
+            av = !kin ? zero<Wd>() : (k < T ? av : -av);
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const Wd bv = kin ? qb[min(s0 + jb * 16 + lc, n - 1)] : zero<Wd>();
+                mac<Wd>(av, bv, re[jb], im[jb]);
+            }
+        }
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            const int sc = s0 + jb * 16 + lc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int q = rbase + acc_row<R>(lane, r);
+                if (q < n && sc < n) X[(size_t)q * n + sc] = make_<Wd>(re[jb][r], im[jb][r]);
+            }
+        }
+    }
+}
+
+template <class Wd>
+__global__ __launch_bounds__(kPrThreads) void parlett_reid_kernel(FA a) {
+    __shared__ Wd s_rj[LRX_MAX_N];                // row j of the current matrix (entries > j)
+    __shared__ Wd s_cf[2 * kPrPairs];            // c_t[i], w_t[i] at the row being rebuilt
+    __shared__ double s_val[kPrThreads / 64];
+    __shared__ int s_idx[kPrThreads / 64];
+    const int w = blockIdx.x, n = a.n, tid = threadIdx.x;
     Wd *X = wX<Wd>(a, w);
+    Wd *Cp = wZ<Wd>(a, w);                       // [kPrPairs][n]
+    Wd *Wp = Cp + (size_t)kPrPairs * n;          // [kPrPairs][n]
     DetAcc *d = wAcc(a, w);
     double la = 0.0;
     Wd ph = one<Wd>();
     bool zero_pf = (n & 1) != 0;
+    int T = 0;
+    // row i of the current matrix at entry e: X[i][e] + sum_t (w_t[i] c_t[e] - c_t[i] w_t[e]),
+    // with s_cf holding c_t[i], w_t[i]
+    auto cur = [&](int i, int e) {
+        Wd v = X[(size_t)i * n + e];
+        for (int t = 0; t < T; ++t) v = v + (s_cf[kPrPairs + t] * Cp[(size_t)t * n + e] - s_cf[t] * Wp[(size_t)t * n + e]);
+        return v;
+    };
     for (int j = 0; j + 1 < n && !zero_pf; j += 2) {
-        // pivot: argmax_{i > j} |X[j][i]|
+        if (tid < T) { s_cf[tid] = Cp[(size_t)tid * n + j]; s_cf[kPrPairs + tid] = Wp[(size_t)tid * n + j]; }
+        __syncthreads();
         double bv = -1.0;
         int bi = -1;
-        for (int i = j + 1 + threadIdx.x; i < n; i += kT) {
-            double v = absv(X[(size_t)j * n + i]);
-            if (bi < 0 || v > bv) { bv = v; bi = i; }
+        for (int i = j + 1 + tid; i < n; i += kPrThreads) {
+            const Wd v = cur(j, i);
+            s_rj[i] = v;
+            const double kv = pivkey(v);
+            if (bi < 0 || kv > bv) { bv = kv; bi = i; }
         }
         const int p = block_argmax(bv, bi, s_val, s_idx);
         const int q = j + 1;
         if (p != q) {
-            // swap rows q, p (columns >= j) and columns q, p (rows >= j)
-            for (int c = j + threadIdx.x; c < n; c += kT) {
-                Wd t = X[(size_t)q * n + c];
+            // swap index q <-> p: rows of X (entries >= j), the pending vectors, row j
+            for (int c = j + tid; c < n; c += kPrThreads) {
+                const Wd t0 = X[(size_t)q * n + c];
                 X[(size_t)q * n + c] = X[(size_t)p * n + c];
-                X[(size_t)p * n + c] = t;
+                X[(size_t)p * n + c] = t0;
+            }
+            if (tid < T) {
+                Wd t0 = Cp[(size_t)tid * n + q];
+                Cp[(size_t)tid * n + q] = Cp[(size_t)tid * n + p];
+                Cp[(size_t)tid * n + p] = t0;
+                t0 = Wp[(size_t)tid * n + q];
+                Wp[(size_t)tid * n + q] = Wp[(size_t)tid * n + p];
+                Wp[(size_t)tid * n + p] = t0;
+            }
+            if (tid == 0) {
+                const Wd t0 = s_rj[q];
+                s_rj[q] = s_rj[p];
+                s_rj[p] = t0;
             }
             __syncthreads();
-            for (int r = j + threadIdx.x; r < n; r += kT) {
-                Wd t = X[(size_t)r * n + q];
+            // columns of X (rows >= j)
+            for (int r = j + tid; r < n; r += kPrThreads) {
+                const Wd t0 = X[(size_t)r * n + q];
                 X[(size_t)r * n + q] = X[(size_t)r * n + p];
-                X[(size_t)r * n + p] = t;
+                X[(size_t)r * n + p] = t0;
             }
-            __syncthreads();
             ph = -ph;
         }
-        const Wd alpha = X[(size_t)j * n + j + 1];
+        __syncthreads();
+        const Wd alpha = s_rj[q];
         if (is_zero(alpha)) { zero_pf = true; break; }
         la += log(absv(alpha));
         ph = ph * unit(alpha);
-        // Trailing update X[r][s] += w_r c_s - c_r w_s, r, s >= j+2, with
-        // c = X[j][j+2:]/alpha (stored over row j, which is not needed again)
-        // and w = X[j+1][j+2:].
+        if (tid < T) { s_cf[tid] = Cp[(size_t)tid * n + q]; s_cf[kPrPairs + tid] = Wp[(size_t)tid * n + q]; }
         __syncthreads();
-        for (int r = j + 2 + threadIdx.x; r < n; r += kT) X[(size_t)j * n + r] = divv(X[(size_t)j * n + r], alpha);
-        __syncthreads();
-        const int m = n - j - 2;
-        for (int idx = threadIdx.x; idx < m * m; idx += kT) {
-            const int r = j + 2 + idx / m, s = j + 2 + idx % m;
-            const Wd cr = X[(size_t)j * n + r], wr = X[(size_t)(j + 1) * n + r];
-            const Wd cs = X[(size_t)j * n + s], ws = X[(size_t)(j + 1) * n + s];
-            X[(size_t)r * n + s] = X[(size_t)r * n + s] + (wr * cs - cr * ws);
+        // the new pending pair: c = row j / alpha, w = row j+1, on entries > j+1
+        const Wd inva = recip(alpha);
+        for (int i = tid; i < n; i += kPrThreads) {
+            Wd c = zero<Wd>(), wv = zero<Wd>();
+            if (i > q) {
+                wv = cur(q, i);
+                c = s_rj[i] * inva;
+            }
+            Cp[(size_t)T * n + i] = c;
+            Wp[(size_t)T * n + i] = wv;
         }
+        ++T;
         __syncthreads();
+        if (T == kPrPairs || j + 3 >= n) {
+            if (j + 2 < n) pr_trailing_update<Wd>(X, Cp, Wp, n, T, j + 2);
+            T = 0;
+            __syncthreads();
+        }
     }
     if (threadIdx.x == 0) {
         d->pf_zero = zero_pf ? 1 : 0;
@@ -324,11 +429,6 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 }
 __device__ __forceinline__ cf64 readlane_d(cf64 v, int l) { return {readlane_d(v.x, l), readlane_d(v.y, l)}; }
 __device__ __forceinline__ double rfl_double(double v) { return readlane_d(v, __builtin_amdgcn_readfirstlane(0)); }
-// Pivot key: |x| for real, |x|^2 for complex (same order, no square root).
-__device__ __forceinline__ double pivkey(double v) { return fabs(v); }
-__device__ __forceinline__ double pivkey(cf64 v) { return v.x * v.x + v.y * v.y; }
-__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
-__device__ __forceinline__ cf64 recip(cf64 v) { return divv(one<cf64>(), v); }
 template <class Wd> __device__ __forceinline__ Wd sel(bool c, Wd a, Wd b) { return c ? a : b; }
 
 // State of one block elimination, shared by its column steps.
@@ -1004,7 +1104,7 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     hipLaunchKernelGGL(init_acc_kernel<Wd>, dim3((W + 255) / 256), dim3(256), 0, s, a);
     if (a.kind == LRX_PF) {
         hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
-        hipLaunchKernelGGL(parlett_reid_kernel<Wd>, dim3(W), dim3(kT), 0, s, a);
+        hipLaunchKernelGGL(parlett_reid_kernel<Wd>, dim3(W), dim3(kPrThreads), 0, s, a);
     }
     hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
