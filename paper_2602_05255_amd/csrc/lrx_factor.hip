@@ -683,85 +683,140 @@ __global__ __launch_bounds__(MAXT) void gj_block_kernel(FA a, int j0, int nbw, i
 }
 
 // ------------------------------------------------------------------ GJ update
-// Columns [c_lo, c_hi) outside the panel: X_new[i] = X_old[pi(i)] + Z[i] . X_old[pi(P)].
-// A work-group owns 64 of those columns (one per lane) for all rows.  Rows
-// moved by the panel's pivoting (at most 2 nb) and the pivot rows are staged
-// in LDS first, so every other row is read and written in place by one lane.
-// Z[i][:] is wave-uniform and is read through the scalar cache.
+// Columns [c_lo, c_hi) outside the block: X_new[i] = X_old[pi(i)] + Z[i] . X_old[pi(P)].
+// A work-group owns 64 of those columns for all rows, in 64-row chunks; each
+// wave takes 16 rows of a chunk as four 16x16 MFMA blocks over the block's nb
+// columns (zero-padded to NB).  Rows moved by the pivoting (at most 2 nb) and
+// the pivot rows X_old[pi(P)] are staged in LDS first, so every other row is
+// read and written in place.
+template <class Wd> constexpr int upd_zs(int NB) { return NB + 1; }   // padded LDS stride of the Z rows
+template <class Wd, int NB> size_t upd_lds(int n, int nb) {
+    return (((size_t)(2 * n + 1 + 2 * nb) * 4 + 15) / 16) * 16 +
+           sizeof(Wd) * ((size_t)NB * 64 + (size_t)2 * nb * 64 + (size_t)64 * upd_zs<Wd>(NB));
+}
+
 template <class Wd, int NB>
 __global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int ncb, int c_lo, int c_hi) {
+    using R = typename Real<Wd>::type;
+    using A4 = typename Acc<R>::type;
+    constexpr int ZS = upd_zs<Wd>(NB);
+    constexpr int NS = (NB + 3) / 4;                                   // 4-deep MFMA steps
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int w = lb / ncb, cb = lb - w * ncb;
     if (w >= a.W) return;
     const int n = a.n, others = (c_hi - c_lo) - nb;
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = threadIdx.x, lane = tid & 63, kq = lane >> 4, lc = lane & 15;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     Wd *X = wX<Wd>(a, w);
     const Wd *Z = wZ<Wd>(a, w);
     const int *piv = wPiv(a, w);
     int *perm = reinterpret_cast<int *>(smem);                         // [n]
     int *sslot = perm + n;                                             // [n]
     int *s_cnt = sslot + n;                                            // [1]
-    Wd *sXP = reinterpret_cast<Wd *>(smem + (((2 * n + 1) * 4 + 15) / 16) * 16);   // [nb][64]
-    Wd *sS = sXP + (size_t)nb * 64;                                    // [2 nb][64]
-    for (int i = threadIdx.x; i < n; i += kT) { perm[i] = i; sslot[i] = -1; }
-    if (threadIdx.x == 0) *s_cnt = 0;
+    int *s_mrow = s_cnt + 1;                                           // [2 nb] moved rows, by slot
+    Wd *sXP = reinterpret_cast<Wd *>(smem + (((2 * n + 1 + 2 * nb) * 4 + 15) / 16) * 16);   // [NB][64]
+    Wd *sS = sXP + (size_t)NB * 64;                                    // [2 nb][64]
+    Wd *sZ = sS + (size_t)2 * nb * 64;                                 // [64][ZS]
+    __shared__ int s_pv[64];
+    if (tid < nb) s_pv[tid] = piv[j0 + tid];                           // all pivots fetched at once
+    for (int i = tid; i < n; i += kT) { perm[i] = i; sslot[i] = -1; }
+    if (tid == 0) *s_cnt = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         for (int c = 0; c < nb; ++c) {
-            const int r = j0 + c, p = piv[r];
+            const int r = j0 + c, p = s_pv[c];
             const int t = perm[r]; perm[r] = perm[p]; perm[p] = t;
         }
     }
     __syncthreads();
-    for (int i = j0 + threadIdx.x; i < n; i += kT)
-        if (perm[i] != i) sslot[i] = atomicAdd(s_cnt, 1);
+    for (int i = j0 + tid; i < n; i += kT)
+        if (perm[i] != i) {
+            const int sl = atomicAdd(s_cnt, 1);
+            sslot[i] = sl;
+            s_mrow[sl] = i;
+        }
     __syncthreads();
-    const int ci = cb * 64 + lane;
-    const bool live = ci < others;
-    const int col = c_lo + ci < j0 ? c_lo + ci : c_lo + ci + nb;   // columns [c_lo, c_hi) minus the panel
-    // pivot rows and moved rows, from the pre-update matrix
-    for (int c = wv; c < nb; c += kT / 64)
-        sXP[c * 64 + lane] = live ? X[(size_t)perm[j0 + c] * n + col] : zero<Wd>();
-    for (int i = j0 + wv; i < n; i += kT / 64) {
-        const int sl = sslot[i];
-        if (sl >= 0) sS[sl * 64 + lane] = live ? X[(size_t)perm[i] * n + col] : zero<Wd>();
+    // the column this lane stages (one per lane), and the four it computes
+    auto colof = [&](int cc) {
+        const int ci = min(cb * 64 + cc, others - 1);                  // clamped: dead columns load, never store
+        return c_lo + ci < j0 ? c_lo + ci : c_lo + ci + nb;           // columns [c_lo, c_hi) minus the block
+    };
+    const int scol = colof(lane);
+    // pivot rows and moved rows, from the pre-update matrix; every load of a
+    // wave is issued before the first store
+    {
+        constexpr int PW = (NB + kT / 64 - 1) / (kT / 64), MW = (2 * NB + kT / 64 - 1) / (kT / 64);
+        const int cnt = *s_cnt;
+        Wd pv[PW], mv[MW];
+#pragma unroll
+        for (int u = 0; u < PW; ++u) pv[u] = X[(size_t)perm[j0 + min(wv + u * (kT / 64), nb - 1)] * n + scol];
+#pragma unroll
+        for (int u = 0; u < MW; ++u) {
+            const int sl = min(wv + u * (kT / 64), max(cnt - 1, 0));
+            mv[u] = X[(size_t)perm[cnt > 0 ? s_mrow[sl] : 0] * n + scol];
+        }
+#pragma unroll
+        for (int u = 0; u < PW; ++u) {
+            const int c = wv + u * (kT / 64);
+            if (c < NB) sXP[c * 64 + lane] = c < nb ? pv[u] : zero<Wd>();
+        }
+#pragma unroll
+        for (int u = 0; u < MW; ++u) {
+            const int sl = wv + u * (kT / 64);
+            if (sl < cnt) sS[sl * 64 + lane] = mv[u];
+        }
     }
-    __syncthreads();
-    Wd xp[NB];
+    int col[4];
+    bool live[4];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) xp[c] = (c < nb) ? sXP[c * 64 + lane] : zero<Wd>();
-    // Rows in chunks of 64: the chunk's Z rows are staged in LDS (read back as
-    // broadcasts), each wave issues its 16 row loads together.
-    Wd *sZ = sS + (size_t)2 * nb * 64;                                 // [64][nb]
+    for (int jb = 0; jb < 4; ++jb) {
+        col[jb] = colof(jb * 16 + lc);
+        live[jb] = cb * 64 + jb * 16 + lc < others;
+    }
     for (int i0 = 0; i0 < n; i0 += 64) {
-        __syncthreads();
-        const int rows = min(64, n - i0);
-        for (int idx = threadIdx.x; idx < rows * nb; idx += kT) sZ[idx] = Z[(size_t)i0 * nb + idx];
-        __syncthreads();
-        Wd v[16];
+        const int rbase = i0 + wv * 16;
+        // the rows this lane holds in the MFMA accumulators, loaded before the
+        // Z rows are staged (moved rows are replaced by their staged copies)
+        Wd xv[4][4];
+        int sl[4];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = i0 + wv * 16 + r;
-            v[r] = zero<Wd>();
-            if (live && i < n) {
-                const int sl = sslot[i];
-                v[r] = sl >= 0 ? sS[sl * 64 + lane] : X[(size_t)i * n + col];
+        for (int r = 0; r < 4; ++r) {
+            const int q = min(rbase + acc_row<R>(lane, r), n - 1);
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) xv[jb][r] = X[(size_t)q * n + col[jb]];
+            sl[r] = sslot[q];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < 64 * NB; idx += kT) {
+            const int r = idx / NB, c = idx - r * NB;
+            const Wd zv = Z[(size_t)min(i0 + r, n - 1) * nb + min(c, nb - 1)];
+            sZ[r * ZS + c] = c < nb ? zv : zero<Wd>();
+        }
+        __syncthreads();
+        A4 re[4], im[4];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const Wd v = sl[r] >= 0 ? sS[sl[r] * 64 + jb * 16 + lc] : xv[jb][r];
+                re[jb][r] = re_(v);
+                im[jb][r] = im_(v);
             }
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const int k = 4 * st + kq;
+            const Wd zv = sZ[(wv * 16 + lc) * ZS + k];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) mac<Wd>(zv, sXP[k * 64 + jb * 16 + lc], re[jb], im[jb]);
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const Wd *zr = sZ + (wv * 16 + r) * nb;
+        for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < nb) v[r] = fmac(zr[c], xp[c], v[r]);
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = i0 + wv * 16 + r;
-            if (live && i < n) X[(size_t)i * n + col] = v[r];
-        }
+            for (int r = 0; r < 4; ++r) {
+                const int q = rbase + acc_row<R>(lane, r);
+                if (live[jb] && q < n) X[(size_t)q * n + col[jb]] = make_<Wd>(re[jb][r], im[jb][r]);
+            }
     }
 }
 
@@ -805,11 +860,13 @@ __global__ __launch_bounds__(kT) void gj_outer_kernel(FA a, int j0, int nbo, int
     const int *piv = wPiv(a, w);
     int *perm = reinterpret_cast<int *>(smem);                                   // [n]
     Wd *sXP = reinterpret_cast<Wd *>(smem + (((size_t)n * 4 + 15) / 16) * 16);    // [64][SP]: X_old[pi(j0+c)]
+    __shared__ int s_pv[64];
+    if (tid < nbo) s_pv[tid] = piv[j0 + tid];       // all pivots fetched at once
     for (int i = tid; i < n; i += kT) perm[i] = i;
     __syncthreads();
     if (tid == 0) {
         for (int c = 0; c < nbo; ++c) {
-            const int r = j0 + c, p = piv[r];
+            const int r = j0 + c, p = s_pv[c];
             const int t = perm[r]; perm[r] = perm[p]; perm[p] = t;
         }
     }
@@ -1058,15 +1115,12 @@ hipError_t launch_update(const FA &fa, int j0, int nb, int c_lo, int c_hi, hipSt
     const int others = (c_hi - c_lo) - nb;
     if (others <= 0) return hipSuccess;
     const int ncb = (others + 63) / 64;
-    const size_t lds = (((2 * fa.n + 1) * 4 + 15) / 16) * 16 + sizeof(Wd) * (size_t)4 * nb * 64;
     const dim3 grid((unsigned)(fa.W * ncb)), block(kT);
     switch (fa.nb) {
-        case 32: hipLaunchKernelGGL((gj_update_kernel<Wd, 32>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
-        case 16: hipLaunchKernelGGL((gj_update_kernel<Wd, 16>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
-        case 8: hipLaunchKernelGGL((gj_update_kernel<Wd, 8>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
-        case 4: hipLaunchKernelGGL((gj_update_kernel<Wd, 4>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
-        case 2: hipLaunchKernelGGL((gj_update_kernel<Wd, 2>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
-        default: hipLaunchKernelGGL((gj_update_kernel<Wd, 1>), grid, block, lds, s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        case 32: hipLaunchKernelGGL((gj_update_kernel<Wd, 32>), grid, block, (upd_lds<Wd, 32>(fa.n, nb)), s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        case 16: hipLaunchKernelGGL((gj_update_kernel<Wd, 16>), grid, block, (upd_lds<Wd, 16>(fa.n, nb)), s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        case 8: hipLaunchKernelGGL((gj_update_kernel<Wd, 8>), grid, block, (upd_lds<Wd, 8>(fa.n, nb)), s, fa, j0, nb, ncb, c_lo, c_hi); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
