@@ -55,7 +55,7 @@ struct DetAcc {          // per-walker accumulators in the workspace
 };
 
 struct WorkLayout {
-    size_t x, z, piv, src, acc, stride;
+    size_t x, z, piv, src, perm, acc, stride;
 };
 
 // Columns per lane of the register-resident block kernel: the block is 4 CPT
@@ -73,6 +73,7 @@ inline WorkLayout work_layout(int n, size_t ws) {
     L.z = off; off += al((size_t)n * 32 * ws);
     L.piv = off; off += al((size_t)n * 4);
     L.src = off; off += al((size_t)n * 4);
+    L.perm = off; off += al((size_t)n * 4);
     L.acc = off; off += al(sizeof(DetAcc));
     L.stride = off;
     return L;
@@ -103,6 +104,11 @@ __device__ __forceinline__ int *wPiv(const FA &a, int w) {
 }
 __device__ __forceinline__ int *wSrc(const FA &a, int w) {
     return reinterpret_cast<int *>(a.work + (size_t)w * a.L.stride + a.L.src);
+}
+// Row source of every position after the current outer panel's swaps so far
+// (written by the block kernels, read by the outer update).
+__device__ __forceinline__ int *wPerm(const FA &a, int w) {
+    return reinterpret_cast<int *>(a.work + (size_t)w * a.L.stride + a.L.perm);
 }
 __device__ __forceinline__ DetAcc *wAcc(const FA &a, int w) {
     return reinterpret_cast<DetAcc *>(a.work + (size_t)w * a.L.stride + a.L.acc);
@@ -596,7 +602,7 @@ __device__ __forceinline__ void blk_run(BlkState<Wd, CPT, MAXT> &S) {
 }
 
 template <class Wd, int CPT, int MAXT>
-__global__ __launch_bounds__(MAXT) void gj_block_kernel(FA a, int j0, int nbw, int write_z) {
+__global__ __launch_bounds__(MAXT) void gj_block_kernel(FA a, int j0, int nbw, int write_z, int o0) {
     using St = BlkState<Wd, CPT, MAXT>;
     extern __shared__ __align__(16) unsigned char smem[];
     St S;
@@ -643,7 +649,19 @@ __global__ __launch_bounds__(MAXT) void gj_block_kernel(FA a, int j0, int nbw, i
         S.cq = cq;
         blk_run<0>(S);
     }
+    // the outer panel's row sources: position pos[i] now holds what position
+    // rbase + i held, whose source is the identity at the panel's first block
+    int *gperm = wPerm(a, w);
+    int src4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        src4[i] = j0 == o0 ? rbase + i : gperm[min(rbase + i, n - 1)];
+        asm volatile("" ::"v"(src4[i]));              // the read has completed before any thread writes
+    }
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (rbase + i < n) gperm[S.pos[i]] = src4[i];
     Wd *Z = wZ<Wd>(a, w);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -821,9 +839,10 @@ __global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int
 }
 
 // ------------------------------------------------------------------ GJ outer update
-// After the last sub-panel of the outer panel [j0, j0 + nbo), its columns hold
-// Zt + E_P; with pi the row swaps piv[j0 .. j0+nbo) in order, every column
-// outside the outer panel becomes
+// After the last block of the outer panel [j0, j0 + nbo), its columns hold
+// Zt + E_P; with pi the row swaps piv[j0 .. j0+nbo) in order (their composite,
+// the source row of every position, written by the block kernels), every
+// column outside the outer panel becomes
 //   X_new[i] = X_old[pi(i)] + Zt[i] . X_old[pi(P)],   P = rows j0 .. j0+nbo-1,
 // an MFMA GEMM (v_mfma_f64_16x16x4f64; four real products per complex one)
 // with inner dimension nbo.  Two facts keep it a plain streaming GEMM:
@@ -857,19 +876,10 @@ __global__ __launch_bounds__(kT) void gj_outer_kernel(FA a, int j0, int nbo, int
     const int n = a.n, others = n - nbo;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     Wd *X = wX<Wd>(a, w);
-    const int *piv = wPiv(a, w);
-    int *perm = reinterpret_cast<int *>(smem);                                   // [n]
+        int *perm = reinterpret_cast<int *>(smem);                                   // [n]
     Wd *sXP = reinterpret_cast<Wd *>(smem + (((size_t)n * 4 + 15) / 16) * 16);    // [64][SP]: X_old[pi(j0+c)]
-    __shared__ int s_pv[64];
-    if (tid < nbo) s_pv[tid] = piv[j0 + tid];       // all pivots fetched at once
-    for (int i = tid; i < n; i += kT) perm[i] = i;
-    __syncthreads();
-    if (tid == 0) {
-        for (int c = 0; c < nbo; ++c) {
-            const int r = j0 + c, p = s_pv[c];
-            const int t = perm[r]; perm[r] = perm[p]; perm[p] = t;
-        }
-    }
+    const int *gperm = wPerm(a, w);                   // row sources, from the block kernels
+    for (int i = tid; i < n; i += kT) perm[i] = gperm[i];
     __syncthreads();
     const int ci0 = cb * CB;
     auto colof = [&](int jj) {
@@ -1126,18 +1136,18 @@ hipError_t launch_update(const FA &fa, int j0, int nb, int c_lo, int c_hi, hipSt
 }
 
 template <class Wd>
-hipError_t launch_block(const FA &fa, int j0, int nbw, int write_z, hipStream_t s) {
+hipError_t launch_block(const FA &fa, int j0, int nbw, int write_z, int o0, hipStream_t s) {
     const int nw = (fa.n + 63) / 64;
     const dim3 grid((unsigned)fa.W), block((unsigned)(64 * nw));
     constexpr int CW = sizeof(Wd) == 8 ? 16 : 8;     // n <= 512
     constexpr int CN = sizeof(Wd) == 8 ? 8 : 2;      // n <= 1024
     if (block_cpt<Wd>(fa.n) == CW) {
         const size_t lds = blk_lds<Wd, CW>(nw);
-        if (nw <= 4) hipLaunchKernelGGL((gj_block_kernel<Wd, CW, 256>), grid, block, lds, s, fa, j0, nbw, write_z);
-        else hipLaunchKernelGGL((gj_block_kernel<Wd, CW, 512>), grid, block, lds, s, fa, j0, nbw, write_z);
+        if (nw <= 4) hipLaunchKernelGGL((gj_block_kernel<Wd, CW, 256>), grid, block, lds, s, fa, j0, nbw, write_z, o0);
+        else hipLaunchKernelGGL((gj_block_kernel<Wd, CW, 512>), grid, block, lds, s, fa, j0, nbw, write_z, o0);
     } else {
         const size_t lds = blk_lds<Wd, CN>(nw);
-        hipLaunchKernelGGL((gj_block_kernel<Wd, CN, 1024>), grid, block, lds, s, fa, j0, nbw, write_z);
+        hipLaunchKernelGGL((gj_block_kernel<Wd, CN, 1024>), grid, block, lds, s, fa, j0, nbw, write_z, o0);
     }
     return hipGetLastError();
 }
@@ -1169,7 +1179,7 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
         const int nbo = min(kOuter, n - o0);
         for (int j0 = o0; j0 < o0 + nbo; j0 += pwb) {
             const int nbw = min(pwb, o0 + nbo - j0);
-            e = launch_block<Wd>(a, j0, nbw, nbw < nbo ? 1 : 0, s);
+            e = launch_block<Wd>(a, j0, nbw, nbw < nbo ? 1 : 0, o0, s);
             if (e != hipSuccess) return e;
             e = launch_update<Wd>(a, j0, nbw, o0, o0 + nbo, s);
             if (e != hipSuccess) return e;
