@@ -998,7 +998,7 @@ __global__ __launch_bounds__(kT) void final_det_kernel(FA a, int rows_per_block,
     for (int i = q0; i < q1; ++i) {
         for (int c = threadIdx.x; c < n; c += kT) {
             const Wd v = X[(size_t)i * n + src[c]];
-            if (a.refresh) {
+            if (a.report) {
                 const Wd o = conv<Wd>(M[(size_t)i * n + c]);
                 dsq += abs2(o - v);
                 nsq += abs2(v);
@@ -1006,7 +1006,7 @@ __global__ __launch_bounds__(kT) void final_det_kernel(FA a, int rows_per_block,
             M[(size_t)i * n + c] = conv<T>(v);
         }
     }
-    if (a.refresh) {
+    if (a.report) {
         dsq = wave_sum(dsq);
         nsq = wave_sum(nsq);
         if ((threadIdx.x & 63) == 0) { s_d[threadIdx.x >> 6] = dsq; s_nrm[threadIdx.x >> 6] = nsq; }
@@ -1052,7 +1052,7 @@ __global__ __launch_bounds__(kT) void final_pf_kernel(FA a, int tiles) {
             // upper entry (i, j): (X'[i][j] - X'[j][i]) / 2
             const Wd h = half_of(t1[r][tx] - t2[tx][r]);
             const Wd nh = -h;
-            if (a.refresh) {
+            if (a.report) {
                 const Wd o1 = conv<Wd>(M[(size_t)i * n + j]);
                 const Wd o2 = conv<Wd>(M[(size_t)j * n + i]);
                 dsq += abs2(o1 - h) + abs2(o2 - nh);
@@ -1061,11 +1061,11 @@ __global__ __launch_bounds__(kT) void final_pf_kernel(FA a, int tiles) {
             M[(size_t)i * n + j] = conv<T>(h);
             M[(size_t)j * n + i] = conv<T>(nh);
         } else if (i < n && j < n && ti == tj && r == tx) {
-            if (a.refresh) dsq += abs2(conv<Wd>(M[(size_t)i * n + i]));
+            if (a.report) dsq += abs2(conv<Wd>(M[(size_t)i * n + i]));
             M[(size_t)i * n + i] = zero<T>();
         }
     }
-    if (a.refresh) {
+    if (a.report) {
         dsq = wave_sum(dsq);
         nsq = wave_sum(nsq);
         if ((threadIdx.x & 63) == 0) { s_d[threadIdx.x >> 6] = dsq; s_nrm[threadIdx.x >> 6] = nsq; }
