@@ -49,10 +49,13 @@ def test_init_inverse_matches_oracle(dt, n):
     assert (wk.st.flags.cpu().numpy() == 0).all()
 
 
-@pytest.mark.parametrize("dt,n", [("f64", 1024), ("c128", 520)])
+@pytest.mark.parametrize("dt,n", [("f64", 1024), ("c128", 520), ("f64", 616), ("c128", 616)])
 def test_init_inverse_large(dt, n):
-    """The largest sizes: several 64-column outer panels, each eliminated in LDS
-    sub-panels and applied to the rest of the matrix by the MFMA outer update."""
+    """The largest sizes: several 64-column outer panels, each eliminated in
+    register-resident blocks (32 columns real / 8 complex above n = 512, with the
+    MFMA sub-block update between them; n = 616 ends on a 40-column outer panel,
+    so its second block is 8 wide) and applied to the rest of the matrix by the
+    MFMA outer update."""
     say(f"init_inverse large dt={dt} n={n}")
     cplx = dt == "c128"
     g = gen.generator(150 + n)

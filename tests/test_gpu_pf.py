@@ -27,9 +27,12 @@ def pf_inputs(seed, L, n, W, cplx):
     return g, f, occ, emp
 
 
-@pytest.mark.parametrize("dt", ["c128", "f64", "c64"])
-@pytest.mark.parametrize("n", [2, 8, 34, 100, 256])
+@pytest.mark.parametrize("dt,n", [(dt, n) for dt in ("c128", "f64", "c64") for n in (2, 8, 34, 100, 256)] +
+                         [("c128", 520), ("f64", 616)])
 def test_pf_init_matches_oracle(dt, n):
+    """Pfaffian init: blocked Parlett-Reid (more than one block of 16 pairs from n = 34 on; a ragged
+    last block at 34, 100, 520, 616) and the Gauss-Jordan inverse (n > 512: 32- or 8-wide
+    register blocks with the MFMA sub-block update)."""
     say(f"pf init dt={dt} n={n}")
     cplx = dt.startswith("c")
     g, f, occ, emp = pf_inputs(300 + n, 2 * n, n, 4, cplx)
