@@ -35,9 +35,10 @@ FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
 
-def counter_traffic(profile, sources):
+def counter_traffic(profile, sources, walkers_per_launch):
     """HBM bytes per launch measured by the FETCH_SIZE / WRITE_SIZE counter passes
-    recorded in profiles/<profile>, or None when the kernel sources changed since."""
+    recorded in profiles/<profile>, or None when the kernel sources changed since or the
+    launch size differs."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -52,6 +53,8 @@ def counter_traffic(profile, sources):
         if len(part) == 2:
             keys[part[0].strip()] = part[1].strip()
     if keys.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in keys:
+        return None
+    if keys.get("walkers_per_launch") != str(int(walkers_per_launch)):
         return None
     return float(keys["traffic_bytes_per_launch"])
 
@@ -75,6 +78,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recompute", action="store_true")
+    ap.add_argument("--streams", type=int, default=None,
+                    help="independent sub-batches of the walker batch, one HIP stream each (1 = one launch "
+                         "per step); default 3 for the determinant workload, 2 for the Pfaffian one, 1 for the n-sweep")
     ap.add_argument("--sizes", default=None, help="n-sweep sizes, comma separated (default 64,...,1024)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -84,9 +90,15 @@ def parse():
 
 
 class Run:
-    """One walker batch with its pre-generated draws, stepping one refresh period at a time."""
+    """One walker batch with its pre-generated draws, stepping one refresh period at a time.
 
-    def __init__(self, wl, dtype, walkers, seed_offset=0):
+    With streams > 1 the batch is split into that many independent sub-batches (their own
+    states), each driven on its own HIP stream (default priority) and forked from / joined to
+    the calling stream every period: one sub-batch's latency-bound launches (propose, flush,
+    refresh blocks) then run beside another's bandwidth-bound accept.  The walkers and their
+    arithmetic are the same as with one stream."""
+
+    def __init__(self, wl, dtype, walkers, seed_offset=0, streams=1):
         import torch
         from paper_2602_05255_amd import inputs as gen
         from paper_2602_05255_amd import lrx
@@ -108,45 +120,78 @@ class Run:
         self.e = torch.as_tensor(e).to(dev)
         self.s = torch.as_tensor(s).to(dev)
         kind = lrx.LRX_DET if wl.kind == "det" else lrx.LRX_PF
-        self.wk = Walkers(kind, dtype, phi, occ, emp, wl.k_max, wl.delay, refresh_period=0)
+        bounds = np.linspace(0, walkers, max(1, streams) + 1).astype(int)
+        self.parts = []
+        for a0, a1 in zip(bounds[:-1], bounds[1:]):
+            wk = Walkers(kind, dtype, phi, occ[a0:a1], emp[a0:a1], wl.k_max, wl.delay, refresh_period=0)
+            self.parts.append((wk, int(a0), int(a1), torch.cuda.Stream() if streams > 1 else None))
+        self.wk = self.parts[0][0]
         self.graph = None
 
+    @property
+    def occ(self):
+        return self.torch.cat([wk.occ for wk, _, _, _ in self.parts])
+
+    def _step(self, wk, a0, a1, t, timer):
+        lrx = self.lrx
+        k, e, s = self.k[t, a0:a1], self.e[t, a0:a1], self.s[t, a0:a1]
+        if timer is not None:
+            timer.begin("propose", wk.st.slot)
+        if wk.kind == lrx.LRX_DET:
+            lrx.lrx_det_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
+                                    wk.ratio)
+        else:
+            wk.use_draws(k, e, s)
+            wk.propose()
+            lrx.lrx_metropolis(wk.st, wk.ratio, None, 0, t, lrx.LRX_MH_FORCE, wk.accept)
+        if timer is not None:
+            timer.end("propose")
+            timer.begin("accept", wk.st.slot, wk.W)
+        if wk.kind == lrx.LRX_DET:
+            lrx.lrx_det_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
+                                   wk.empty, wk.n_empty)
+        else:
+            lrx.lrx_pf_accept_update(wk.st, k, e, wk.u, wk.accept)
+            lrx.lrx_hop_commit(wk.W, wk.n, wk.n_empty, wk.k_max, k, e, s, wk.accept, wk.occ, wk.empty)
+        if timer is not None:
+            timer.end("accept")
+        if wk.delay and wk.st.slot == wk.delay:
+            if timer is not None:
+                timer.begin("flush", wk.st.slot)
+            wk.flush()
+            if timer is not None:
+                timer.end("flush")
+
     def period(self, timer=None):
-        """One refresh period: P steps with forced accept, flushes every K, then refresh."""
-        wk, lrx = self.wk, self.lrx
+        """One refresh period: P steps with forced accept, flushes every K, then refresh.
+        With a timer every launch runs on the calling stream (one at a time, so that each
+        launch's own duration is measured); otherwise the sub-batches run on their streams."""
+        torch = self.torch
+        split = timer is None and len(self.parts) > 1
+        cur = torch.cuda.current_stream()
+        if split:
+            for _, _, _, st in self.parts:
+                st.wait_stream(cur)
         for t in range(self.P):
-            k, e, s = self.k[t], self.e[t], self.s[t]
-            if timer is not None:
-                timer.begin("propose", wk.st.slot)
-            if wk.kind == lrx.LRX_DET:
-                lrx.lrx_det_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
-                                        wk.ratio)
-            else:
-                wk.use_draws(k, e, s)
-                wk.propose()
-                lrx.lrx_metropolis(wk.st, wk.ratio, None, 0, t, lrx.LRX_MH_FORCE, wk.accept)
-            if timer is not None:
-                timer.end("propose")
-                timer.begin("accept", wk.st.slot)
-            if wk.kind == lrx.LRX_DET:
-                lrx.lrx_det_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
-                                       wk.empty, wk.n_empty)
-            else:
-                lrx.lrx_pf_accept_update(wk.st, k, e, wk.u, wk.accept)
-                lrx.lrx_hop_commit(wk.W, wk.n, wk.n_empty, wk.k_max, k, e, s, wk.accept, wk.occ, wk.empty)
-            if timer is not None:
-                timer.end("accept")
-            if wk.delay and wk.st.slot == wk.delay:
-                if timer is not None:
-                    timer.begin("flush", wk.st.slot)
-                wk.flush()
-                if timer is not None:
-                    timer.end("flush")
+            for wk, a0, a1, st in self.parts:
+                if split:
+                    with torch.cuda.stream(st):
+                        self._step(wk, a0, a1, t, None)
+                else:
+                    self._step(wk, a0, a1, t, timer)
         if timer is not None:
             timer.begin("refresh", 0)
-        wk.refresh(report=False)
+        for wk, _, _, st in self.parts:
+            if split:
+                with torch.cuda.stream(st):
+                    wk.refresh(report=False)
+            else:
+                wk.refresh(report=False)
         if timer is not None:
             timer.end("refresh")
+        if split:
+            for _, _, _, st in self.parts:
+                cur.wait_stream(st)
 
     def capture(self):
         torch = self.torch
@@ -177,22 +222,22 @@ class EventTimer:
         self.rec = []
         self.cur = {}
 
-    def begin(self, name, tau):
+    def begin(self, name, tau, walkers=0):
         ev = self.torch.cuda.Event(enable_timing=True)
         ev.record()
-        self.cur[name] = (ev, tau)
+        self.cur[name] = (ev, tau, walkers)
 
     def end(self, name):
         ev = self.torch.cuda.Event(enable_timing=True)
         ev.record()
-        b, tau = self.cur.pop(name)
-        self.rec.append((name, tau, b, ev))
+        b, tau, walkers = self.cur.pop(name)
+        self.rec.append((name, tau, walkers, b, ev))
 
     def results(self):
         self.torch.cuda.synchronize()
         out = {}
-        for name, tau, b, e in self.rec:
-            out.setdefault(name, []).append((tau, b.elapsed_time(e) * 1e-3))
+        for name, tau, walkers, b, e in self.rec:
+            out.setdefault(name, []).append((tau, b.elapsed_time(e) * 1e-3, walkers))
         return out
 
 
@@ -208,21 +253,33 @@ def accept_bytes(wl, s, W, tau):
     return W * s * (n * n + n * km * tau + 4 * n * km)
 
 
+def queue_filler(torch, ms=60.0):
+    """About `ms` of GPU work (FP64 GEMMs) on the current stream, enqueued at once."""
+    a = torch.ones(4096, 4096, dtype=torch.float64, device="cuda") / 4096.0
+    reps = max(1, int(ms / 3.0))             # one 4096^3 FP64 GEMM is about 3 ms here or more
+    for _ in range(reps):
+        a = a @ a
+
+
 def measure(wl, dtype, walkers, args, torch, label):
-    run = Run(wl, dtype, walkers)
+    run = Run(wl, dtype, walkers, streams=args.streams)
     elem = torch.empty((), dtype=dtype).element_size()
-    # roofline pass: eager, HIP events around every accept launch of one period
+    wl_launch = walkers / len(run.parts)      # walkers per launch (one sub-batch)
+    # roofline pass: eager, HIP events around every accept launch of one period.  A filler
+    # (FP64 GEMMs) keeps the GPU busy while the host enqueues the period, so that no event
+    # pair brackets host launch time.
     run.period()
     torch.cuda.synchronize()
+    queue_filler(torch)
     timer = EventTimer(torch)
     run.period(timer)
     res = timer.results()
     acc = res["accept"]
-    bytes_tot = sum(accept_bytes(wl, elem, walkers, tau) for tau, _ in acc)
-    t_tot = sum(dt for _, dt in acc)
+    bytes_tot = sum(accept_bytes(wl, elem, wp, tau) for tau, _, wp in acc)
+    t_tot = sum(dt for _, dt, _ in acc)
     fl = res.get("flush", [])
-    flush_t = np.mean([dt for _, dt in fl]) if fl else None
-    refresh_t = np.mean([dt for _, dt in res["refresh"]])
+    flush_t = np.mean([dt for _, dt, _ in fl]) if fl else None
+    refresh_t = np.mean([dt for _, dt, _ in res["refresh"]])
     if not args.no_graph:
         run.capture()
     for _ in range(args.warmup):
@@ -245,13 +302,13 @@ def measure(wl, dtype, walkers, args, torch, label):
     flush = None
     if flush_t:
         if wl.kind == "pf":
-            fflops = walkers * 8.0 * n * n * 2 * K / 2
-            fbytes = walkers * elem * (1.5 * n * n + 2 * n * K)
+            fflops = wl_launch * 8.0 * n * n * 2 * K / 2
+            fbytes = wl_launch * elem * (1.5 * n * n + 2 * n * K)
             elem_peak = FP32_PEAK_TFS if elem <= 8 else FP64_PEAK_TFS
         else:
             kbar = float(np.mean(wl.ranks))    # live slot columns per step (padding is skipped)
-            fflops = walkers * 2.0 * n * n * K * kbar * (4 if elem == 16 else 1)
-            fbytes = walkers * elem * (2 * n * n + 2 * n * K * kbar)
+            fflops = wl_launch * 2.0 * n * n * K * kbar * (4 if elem == 16 else 1)
+            fbytes = wl_launch * elem * (2 * n * n + 2 * n * K * kbar)
             elem_peak = FP64_PEAK_TFS if elem == 8 else FP32_PEAK_TFS
         flush = {"avg_us": flush_t * 1e6, "tflops": fflops / flush_t / 1e12,
                  "gbs": fbytes / flush_t / 1e9,
@@ -271,7 +328,8 @@ def rel_error(run, torch, sample):
     """Max relative error of the LRU inverse and log|det| (log|pf|) on sampled walkers against the
     full FP64 / complex128 recompute on the same GPU (torch.linalg: rocSOLVER LU).  For the
     Pfaffian, log|pf| = log|det| / 2 (the phase is checked against the oracle by the tests)."""
-    wk = run.wk
+    wk = run.wk                      # the first sub-batch; sample spread over its walkers
+    sample = np.linspace(0, wk.W - 1, len(sample)).astype(int)
     idx = torch.as_tensor(sample, device=wk.occ.device)
     inv = wk.inverse()[idx]
     occ = wk.occ[idx].long()
@@ -318,7 +376,7 @@ def cpu_baseline(wl, seconds):
 def recompute(wl, run, torch, reps=5):
     """Full recompute on the same GPU: gather Phi[occ] + torch.linalg.slogdet (rocSOLVER), FP64."""
     phi = torch.as_tensor(run.phi).cuda()
-    occ = run.wk.occ.long()
+    occ = run.occ.long()
     out = {}
     chunk = 128     # batched getrf on the whole 1024-matrix batch fails to allocate its workspace
     for name, fn in (("slogdet", lambda a: torch.linalg.slogdet(a)),
@@ -354,7 +412,8 @@ def bench_secondary(wl, args, torch, dtype):
             "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": str(dtype).replace("torch.", ""), "data": "synthetic",
             "config": {"workload": wl.name, "walkers": W, "n": wl.n, "sites": wl.sites, "delay": wl.delay,
-                       "refresh_every": wl.refresh, "mode": "forced-accept"},
+                       "refresh_every": wl.refresh, "mode": "forced-accept",
+                       "streams": args.streams},
             "accept_avg_us": r["accept_avg_us"], "accept_gbs": r["accept_gbs"], "refresh_ms": r["refresh_ms"],
             "flush": r["flush"], "rel_error": err}
 
@@ -586,6 +645,8 @@ def main():
         print(json.dumps(copy_calibration(torch)), flush=True)
         return
     wl = gen.WORKLOADS[args.workload]
+    if args.streams is None:
+        args.streams = {"slater_n256_k124": 3, "pfaffian_n512_c64": 2}.get(wl.name, 1)
     if wl.name == "logpsi_grad_n512_c64":
         print(json.dumps(bench_adjoint(wl, args, torch)), flush=True)
         return
@@ -627,10 +688,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "walkers": W, "n": wl.n, "sites": wl.sites, "ranks": list(wl.ranks),
                    "delay": wl.delay, "refresh_every": wl.refresh, "mc_steps_per_bench_step": wl.refresh,
-                   "mode": "forced-accept", "graph": not args.no_graph},
+                   "mode": "forced-accept", "graph": not args.no_graph, "streams": args.streams},
         "roofline": {"bound": "hbm", "kernel": "det_accept_kernel (delayed)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic("det_accept_kernel_slater_n256_k124_counters.md", DET_SOURCES),
+                     "traffic": counter_traffic("det_accept_kernel_slater_n256_k124_counters.md", DET_SOURCES,
+                                                W // max(1, args.streams)),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "avg_us": r64["accept_avg_us"], "bytes_per_launch": r64["accept_bytes_per_launch"]},
         "cpu_baseline": cpu,

@@ -59,12 +59,12 @@ template <class T, int KM, int NEL, bool D> hipError_t accept_t(const StepArgs &
         return hipErrorInvalidValue;
     } else {
     constexpr int RB = rows_per_batch<T, NEL, KM>();
-    // Rows per block: long-lived blocks (set-up amortised over many rows) with
-    // still about eight blocks per compute unit.
+    // Rows per block: long-lived blocks (set-up amortised over at least 128 rows)
+    // with still about eight blocks per compute unit.
     const int n = a.n;
     int rpb = kWaves * RB;
     long long blocks = (long long)a.W * ((n + rpb - 1) / rpb);
-    while (rpb < n && blocks > 8 * 256) {
+    while (rpb < n && (blocks > 8 * 256 || rpb < 128)) {
         rpb *= 2;
         blocks = (long long)a.W * ((n + rpb - 1) / rpb);
     }

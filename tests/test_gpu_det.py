@@ -232,20 +232,63 @@ def test_refresh_reports_and_removes_drift():
     assert rep2[:, 0].max() < 1e-14 and rep2[:, 1].max() < 1e-12
 
 
-def test_scale_workload_full_size_sampled():
-    """Phi 512x256, 1024 walkers, k in {1,2,4}, K=16, FP64 at full size; the launch
-    shapes the benchmark times.  Sampled walkers are recomputed by the oracle."""
+class _Split:
+    """The benchmark's launch shape: the walker batch cut into sub-batches with their own
+    states, each driven on its own stream."""
+
+    def __init__(self, parts, phi, occ, emp, wl):
+        bounds = np.linspace(0, occ.shape[0], parts + 1).astype(int)
+        self.b = list(zip(bounds[:-1], bounds[1:]))
+        self.wks = [Walkers(lrx.LRX_DET, torch.float64, phi, occ[a:b], emp[a:b], wl.k_max, wl.delay, wl.refresh)
+                    for a, b in self.b]
+        self.streams = [torch.cuda.Stream() for _ in self.b] if parts > 1 else [None]
+
+    def _each(self, fn):
+        cur = torch.cuda.current_stream()
+        out = []
+        for wk, st, (a, b) in zip(self.wks, self.streams, self.b):
+            if st is None:
+                out.append(fn(wk, a, b))
+                continue
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                out.append(fn(wk, a, b))
+        for st in self.streams:
+            if st is not None:
+                cur.wait_stream(st)
+        return out
+
+    def propose(self, k, elec, slot):
+        def f(wk, a, b):
+            wk.set_draws(k[a:b], elec[a:b], slot[a:b])
+            return wk.propose()
+        return torch.cat(self._each(f))
+
+    def accept_all(self):
+        def f(wk, a, b):
+            wk.decide(mask=np.ones(b - a, bool))
+            wk.apply()
+        self._each(f)
+
+    def cat(self, fn):
+        return np.concatenate([fn(wk) for wk in self.wks])
+
+
+@pytest.mark.parametrize("parts", [1, 3])
+def test_scale_workload_full_size_sampled(parts):
+    """Phi 512x256, 1024 walkers, k in {1,2,4}, K=16, FP64 at full size, in one batch and
+    in the benchmark's launch shape (three sub-batches on three streams).  Sampled
+    walkers are recomputed by the oracle."""
     wl = gen.WORKLOADS["slater_n256_k124"]
-    say(f"full-size {wl.name}")
+    say(f"full-size {wl.name} parts={parts}")
     phi, occ, emp, g = gen.slater_inputs(wl)
-    wk = Walkers(lrx.LRX_DET, torch.float64, phi, occ, emp, wl.k_max, wl.delay, wl.refresh)
+    run = _Split(parts, phi, occ, emp, wl)
     steps = 2 * wl.delay + 5
-    sample = np.array([0, 1, 255, 511, 512, 700, 1022, 1023])
+    sample = np.array([0, 1, 255, 340, 341, 511, 512, 700, 1022, 1023])
     book = orc.Occupancy(occ, emp)
     for t in range(steps):
         k, elec, slot = gen.hop_draws(g, wl.walkers, wl.n, wl.sites - wl.n, wl.ranks, wl.k_max)
-        wk.set_draws(k, elec, slot)
-        r = wk.propose().cpu().numpy()
+        r = run.propose(k, elec, slot).cpu().numpy()
         prop = book.proposed(k, elec, slot)
         la0, ph0, inv0 = orc.slogdet(orc.slater_matrices(phi, book.occ[sample]))
         la1, ph1, _ = orc.slogdet(orc.slater_matrices(phi, prop[sample]), want_inv=False)
@@ -258,12 +301,10 @@ def test_scale_workload_full_size_sampled():
         tol = np.maximum(1e-10, 8 * EPS64 * np.sqrt(1.0 + since) *
                          det_ratio_bound(phi, book.occ[sample], prop[sample], inv0, k[sample], elec[sample]))
         assert np.all(err <= tol), (t, err, tol)
-        mask = np.ones(wl.walkers, bool)
-        wk.decide(mask=mask)
-        wk.apply()
-        book.commit(k, elec, slot, mask)
-    np.testing.assert_array_equal(wk.occ.cpu().numpy(), book.occ)
-    inv = wk.inverse().cpu().numpy()
+        run.accept_all()
+        book.commit(k, elec, slot, np.ones(wl.walkers, bool))
+    np.testing.assert_array_equal(run.cat(lambda wk: wk.occ.cpu().numpy()), book.occ)
+    inv = run.cat(lambda wk: wk.inverse().cpu().numpy())
     a_fin = orc.slater_matrices(phi, book.occ[sample])
     la, ph, oinv = orc.slogdet(a_fin)
     # The inverse of an ill-conditioned walker carries about sqrt(n) cond_1(A) eps relative
@@ -273,8 +314,9 @@ def test_scale_workload_full_size_sampled():
     tol_inv = np.maximum(1e-10, np.sqrt(wl.n) * EPS64 * np.sqrt(1.0 + steps % wl.refresh) * cond)
     err_inv = rel_err(inv[sample], oinv, axis=(1, 2))
     assert np.all(err_inv <= tol_inv), (err_inv, cond)
-    np.testing.assert_allclose(wk.st.logabs.cpu().numpy()[sample], la, atol=1e-8)
-    assert np.isfinite(wk.st.logabs.cpu().numpy()).all()
+    logabs = run.cat(lambda wk: wk.st.logabs.cpu().numpy())
+    np.testing.assert_allclose(logabs[sample], la, atol=1e-8)
+    assert np.isfinite(logabs).all()
 
 
 def test_metropolis_modes():
