@@ -186,32 +186,39 @@ __global__ void init_acc_kernel(FA a) {
     d->singular = 0; d->pf_zero = 0;
 }
 
-// Block-wide argmax of |v| with ties to the lowest index.  Returns the index
-// on every thread (or -1 when the block saw no candidate).
+// Block-wide argmax of a key with ties to the lowest index (NT threads).
+// Returns the index on every thread (-1 when the block saw no candidate).  One
+// barrier: every thread reduces the per-wave results itself; the caller must
+// pass another barrier before calling again (s_val / s_idx are reused).
+__device__ __forceinline__ void argmax_pair(double &val, int &idx, int m) {
+    const double ov = __shfl_xor(val, m, 64);
+    const int oi = __shfl_xor(idx, m, 64);
+    const bool take = (oi >= 0) && (idx < 0 || ov > val || (ov == val && oi < idx));
+    val = take ? ov : val;
+    idx = take ? oi : idx;
+}
+template <int NT>
 __device__ int block_argmax(double val, int idx, double *s_val, int *s_idx) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int m = 32; m >= 1; m >>= 1) {
-        double ov = __shfl_xor(val, m, 64);
-        int oi = __shfl_xor(idx, m, 64);
-        bool take = (oi >= 0) && (idx < 0 || ov > val || (ov == val && oi < idx));
-        if (take) { val = ov; idx = oi; }
-    }
+    argmax_pair(val, idx, 32);
+    argmax_pair(val, idx, 16);
+    argmax_pair(val, idx, 8);
+    argmax_pair(val, idx, 4);
+    argmax_pair(val, idx, 2);
+    argmax_pair(val, idx, 1);
     if (lane == 0) { s_val[wv] = val; s_idx[wv] = idx; }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double bv = s_val[0];
-        int bi = s_idx[0];
-        for (int q = 1; q < kT / 64; ++q) {
-            double ov = s_val[q];
-            int oi = s_idx[q];
-            if (oi >= 0 && (bi < 0 || ov > bv || (ov == bv && oi < bi))) { bv = ov; bi = oi; }
-        }
-        s_idx[0] = bi;
+    double bv = s_val[0];
+    int bi = s_idx[0];
+#pragma unroll
+    for (int q = 1; q < NT / 64; ++q) {
+        const double ov = s_val[q];
+        const int oi = s_idx[q];
+        const bool take = oi >= 0 && (bi < 0 || ov > bv || (ov == bv && oi < bi));
+        bv = take ? ov : bv;
+        bi = take ? oi : bi;
     }
-    __syncthreads();
-    int r = s_idx[0];
-    __syncthreads();
-    return r;
+    return bi;
 }
 
 // ------------------------------------------------------------------ Parlett-Reid
@@ -231,7 +238,7 @@ __device__ int block_argmax(double val, int idx, double *s_val, int *s_idx) {
 // (X[J][J] += P Q^T with P = [w_t, -c_t], Q = [c_t, w_t]).  X is then read and
 // written once per block instead of once per pair.
 constexpr int kPrPairs = 16;
-constexpr int kPrThreads = 256;
+constexpr int kPrThreads = 512;
 
 // Pivot key: |x| for real, |x|^2 for complex (same order, no square root).
 __device__ __forceinline__ double pivkey(double v) { return fabs(v); }
@@ -240,14 +247,15 @@ __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
 __device__ __forceinline__ cf64 recip(cf64 v) { return divv(one<cf64>(), v); }
 
 // X[r][s] += sum_{t<T} w_t[r] c_t[s] - c_t[r] w_t[s] for r, s in [j0, n).
-// 64 x 64 tiles, wave wv owns 16 rows of the tile as four 16x16 MFMA blocks.
+// 64 x 64 tiles, one per four waves; wave wv % 4 owns 16 rows of its tile as
+// four 16x16 MFMA blocks.
 template <class Wd>
 __device__ __forceinline__ void pr_trailing_update(Wd *X, const Wd *Cp, const Wd *Wp, int n, int T, int j0) {
     using R = typename Real<Wd>::type;
     using A4 = typename Acc<R>::type;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kq = lane >> 4, lc = lane & 15;
+    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3, kq = lane >> 4, lc = lane & 15;
     const int m = n - j0, nt = (m + 63) / 64, K2 = 2 * T;
-    for (int tile = 0; tile < nt * nt; ++tile) {
+    for (int tile = threadIdx.x >> 8; tile < nt * nt; tile += kPrThreads / 256) {
         const int r0 = j0 + (tile / nt) * 64, s0 = j0 + (tile % nt) * 64;
         const int rbase = r0 + wv * 16;
         A4 re[4], im[4];
@@ -322,7 +330,7 @@ __global__ __launch_bounds__(kPrThreads) void parlett_reid_kernel(FA a) {
             const double kv = pivkey(v);
             if (bi < 0 || kv > bv) { bv = kv; bi = i; }
         }
-        const int p = block_argmax(bv, bi, s_val, s_idx);
+        const int p = block_argmax<kPrThreads>(bv, bi, s_val, s_idx);
         const int q = j + 1;
         if (p != q) {
             // swap index q <-> p: rows of X (entries >= j), the pending vectors, row j
