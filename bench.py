@@ -18,6 +18,7 @@ recompute on the same GPU.  Only the cpu_baseline leg runs the oracle.
 from __future__ import annotations
 
 import argparse
+import contextlib
 import json
 import os
 import sys
@@ -80,7 +81,7 @@ def parse():
     ap.add_argument("--no-recompute", action="store_true")
     ap.add_argument("--streams", type=int, default=None,
                     help="independent sub-batches of the walker batch, one HIP stream each (1 = one launch "
-                         "per step); default 3 for the determinant workload, 2 for the Pfaffian one, 1 for the n-sweep")
+                         "per step); default 4 for the determinant and Pfaffian workloads, 1 for the n-sweep")
     ap.add_argument("--sizes", default=None, help="n-sweep sizes, comma separated (default 64,...,1024)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -127,6 +128,11 @@ class Run:
             self.parts.append((wk, int(a0), int(a1), torch.cuda.Stream() if streams > 1 else None))
         self.wk = self.parts[0][0]
         self.graph = None
+        # Sub-batch p runs offsets[p] steps ahead (a multiple of K), so the sub-batches reach
+        # their refresh at different steps and each refresh overlaps the others' steps.
+        K = max(1, wl.delay)
+        self.offsets = [(p * (self.P // len(self.parts))) // K * K for p in range(len(self.parts))]
+        self.primed = False
 
     @property
     def occ(self):
@@ -162,33 +168,39 @@ class Run:
             if timer is not None:
                 timer.end("flush")
 
+    def prime(self):
+        """Advance every sub-batch by its offset (once, before the first period)."""
+        if self.primed:
+            return
+        for (wk, a0, a1, _), off in zip(self.parts, self.offsets):
+            for t in range(off):
+                self._step(wk, a0, a1, t, None)
+        self.torch.cuda.synchronize()
+        self.primed = True
+
     def period(self, timer=None):
-        """One refresh period: P steps with forced accept, flushes every K, then refresh.
-        With a timer every launch runs on the calling stream (one at a time, so that each
-        launch's own duration is measured); otherwise the sub-batches run on their streams."""
+        """One refresh period: P steps of every sub-batch with forced accept, flushes every
+        K, and each sub-batch's refresh after its own P-th step.  With a timer every launch
+        runs on the calling stream (one at a time, so that each launch's own duration is
+        measured); otherwise the sub-batches run on their streams."""
         torch = self.torch
+        self.prime()
         split = timer is None and len(self.parts) > 1
         cur = torch.cuda.current_stream()
         if split:
             for _, _, _, st in self.parts:
                 st.wait_stream(cur)
         for t in range(self.P):
-            for wk, a0, a1, st in self.parts:
-                if split:
-                    with torch.cuda.stream(st):
-                        self._step(wk, a0, a1, t, None)
-                else:
-                    self._step(wk, a0, a1, t, timer)
-        if timer is not None:
-            timer.begin("refresh", 0)
-        for wk, _, _, st in self.parts:
-            if split:
-                with torch.cuda.stream(st):
-                    wk.refresh(report=False)
-            else:
-                wk.refresh(report=False)
-        if timer is not None:
-            timer.end("refresh")
+            for (wk, a0, a1, st), off in zip(self.parts, self.offsets):
+                local = (t + off) % self.P
+                with torch.cuda.stream(st) if split else contextlib.nullcontext():
+                    self._step(wk, a0, a1, local, None if split else timer)
+                    if local == self.P - 1:
+                        if timer is not None:
+                            timer.begin("refresh", 0)
+                        wk.refresh(report=False)
+                        if timer is not None:
+                            timer.end("refresh")
         if split:
             for _, _, _, st in self.parts:
                 cur.wait_stream(st)
@@ -253,7 +265,7 @@ def accept_bytes(wl, s, W, tau):
     return W * s * (n * n + n * km * tau + 4 * n * km)
 
 
-def queue_filler(torch, ms=60.0):
+def queue_filler(torch, ms=150.0):
     """About `ms` of GPU work (FP64 GEMMs) on the current stream, enqueued at once."""
     a = torch.ones(4096, 4096, dtype=torch.float64, device="cuda") / 4096.0
     reps = max(1, int(ms / 3.0))             # one 4096^3 FP64 GEMM is about 3 ms here or more
@@ -646,7 +658,7 @@ def main():
         return
     wl = gen.WORKLOADS[args.workload]
     if args.streams is None:
-        args.streams = {"slater_n256_k124": 3, "pfaffian_n512_c64": 2}.get(wl.name, 1)
+        args.streams = {"slater_n256_k124": 4, "pfaffian_n512_c64": 4}.get(wl.name, 1)
     if wl.name == "logpsi_grad_n512_c64":
         print(json.dumps(bench_adjoint(wl, args, torch)), flush=True)
         return

@@ -274,17 +274,18 @@ class _Split:
         return np.concatenate([fn(wk) for wk in self.wks])
 
 
-@pytest.mark.parametrize("parts", [1, 3])
+@pytest.mark.parametrize("parts", [1, 4])
 def test_scale_workload_full_size_sampled(parts):
     """Phi 512x256, 1024 walkers, k in {1,2,4}, K=16, FP64 at full size, in one batch and
-    in the benchmark's launch shape (three sub-batches on three streams).  Sampled
-    walkers are recomputed by the oracle."""
+    in the benchmark's launch shape (four sub-batches of 256 walkers on four streams).
+    Sampled walkers, among them both sides of every sub-batch boundary, are recomputed
+    by the oracle."""
     wl = gen.WORKLOADS["slater_n256_k124"]
     say(f"full-size {wl.name} parts={parts}")
     phi, occ, emp, g = gen.slater_inputs(wl)
     run = _Split(parts, phi, occ, emp, wl)
     steps = 2 * wl.delay + 5
-    sample = np.array([0, 1, 255, 340, 341, 511, 512, 700, 1022, 1023])
+    sample = np.array([0, 1, 255, 256, 340, 511, 512, 700, 767, 768, 1022, 1023])
     book = orc.Occupancy(occ, emp)
     for t in range(steps):
         k, elec, slot = gen.hop_draws(g, wl.walkers, wl.n, wl.sites - wl.n, wl.ranks, wl.k_max)
