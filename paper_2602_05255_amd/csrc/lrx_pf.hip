@@ -137,6 +137,15 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
     }
 }
 
+// Slot columns covered by one round of slot-correction loads of a wave in
+// pf_rowdot_kernel with RB rows per batch (8 per lane); the staged h is padded
+// to a multiple of it.
+template <int RB> constexpr int pf_slot_round() { return 8 * (64 / RB); }
+
+// Value select (a conditional on two named complex values would select their
+// addresses and push them to scratch memory).
+template <class T> __device__ __forceinline__ T pick(bool c, T a, T b) { return c ? a : b; }
+
 // ------------------------------------------------------------------ row dots
 // ax[q] = M[q,:] . x (+ sum_te fa[te][q] h[te] in the delayed form).
 // DELAYED: writes slot tau = [ax, col] and R_tau^-1; else stores ax in the stash.
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(kThreads) void pf_rowdot_kernel(StepArgs a, int row
     if (w >= a.W) return;
     const int n = a.n, tau = a.tau, TE = tau * KA;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int q0 = rb * rows_per_block, q1 = min(n, q0 + rows_per_block), nq = q1 - q0;
+    const int q0 = rb * rows_per_block, q1 = min(n, q0 + rows_per_block);
     const T *M = static_cast<const T *>(a.inv) + (size_t)w * n * n;
     const T *x = static_cast<const T *>(a.u) + (size_t)w * n;
     T *fa = static_cast<T *>(a.fa) + (size_t)w * a.K * KA * n;
@@ -192,20 +201,46 @@ __global__ __launch_bounds__(kThreads) void pf_rowdot_kernel(StepArgs a, int row
     }
     const int npad = NCH * V * 64;
     T *s_x = reinterpret_cast<T *>(smem);        // [npad]
-    T *s_corr = s_x + npad;                      // [rows_per_block]
+    // Slot correction sum_te fa[te][q] h[te] of the batch's rows, spread over
+    // the wave: lane l takes row l mod RB and the slot columns te = l / RB
+    // (mod 64 / RB), CU of them per round of loads.  Its loads go out with the
+    // batch's row loads and its partial joins the row's dot partial before the
+    // one reduction.  h is staged in LDS padded with zeros to whole rounds, so
+    // a padded column (its fa load clamped to a live one) adds nothing.
+    constexpr int NSL = 64 / RB;
+    constexpr int CU = pf_slot_round<RB>() / NSL;
+    const int TEp = DELAYED ? (TE + pf_slot_round<RB>() - 1) / pf_slot_round<RB>() * pf_slot_round<RB>() : 0;
+    T *s_h = s_x + npad;                         // [TEp], delayed form only
     for (int j = tid; j < npad; j += kThreads) s_x[j] = j < n ? x[j] : zero<T>();
-    for (int q = q0 + tid; q < q1; q += kThreads) {
-        T c = zero<T>();
-        if (DELAYED)
-            for (int te = 0; te < TE; ++te) c = fmac(fa[(size_t)te * n + q], h[te], c);
-        s_corr[q - q0] = c;
+    for (int te = tid; te < TEp; te += kThreads) {
+        T v = zero<T>();
+        if (te < TE) v = h[te];
+        s_h[te] = v;
     }
     __syncthreads();
     const bool vec_ok = a.aligned != 0;
+    const int cr = lane % RB, csl = lane / RB;
     for (int qb = q0 + wv * RB; qb < q1; qb += kWaves * RB) {
         T p[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) p[r] = zero<T>();
+        if (DELAYED) {
+            const int qc = min(qb + cr, q1 - 1);     // rows past q1 are never stored
+            T corr = zero<T>();
+            for (int t0 = 0; t0 < TE; t0 += CU * NSL) {
+                T fv[CU], hv[CU];
+#pragma unroll
+                for (int j = 0; j < CU; ++j) {
+                    const int te = t0 + csl + j * NSL;
+                    fv[j] = fa[(size_t)min(te, TE - 1) * n + qc];
+                    hv[j] = s_h[te];
+                }
+#pragma unroll
+                for (int j = 0; j < CU; ++j) corr = fmac(fv[j], hv[j], corr);
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) p[r] = pick(cr == r, corr, p[r]);
+        }
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int j0 = ch * V * 64 + lane * V;
@@ -226,17 +261,16 @@ __global__ __launch_bounds__(kThreads) void pf_rowdot_kernel(StepArgs a, int row
                 for (int v = 0; v < V; ++v) p[r] = fmac(tmp[v], xv[v], p[r]);
             }
         }
-        T tot = wave_sum_multi<T, RB>(p);
-        // lane r (< RB) holds the dot of row qb + r
+        const T tot = wave_sum_multi<T, RB>(p);
+        // lane r (< RB) holds the dot of row qb + r, slot correction included
         if (lane < RB) {
             const int q = qb + lane;
             if (q < q1) {
-                const T v = tot + s_corr[q - q0];
                 if (DELAYED) {
-                    fa[(size_t)(tau * KA) * n + q] = v;
+                    fa[(size_t)(tau * KA) * n + q] = tot;
                     fa[(size_t)(tau * KA + 1) * n + q] = col[q];
                 } else {
-                    ax[q] = v;
+                    ax[q] = tot;
                 }
             }
         }
@@ -349,7 +383,7 @@ template <class T, int NEL> hipError_t accept_nel(const StepArgs &a, hipStream_t
     int rpb, bpw;
     block_shape(a.W, a.n, kWaves * RB, rpb, bpw);
     const dim3 grid((unsigned)(a.W * bpw));
-    const size_t lds1 = sizeof(T) * ((size_t)npad + rpb);
+    const size_t lds1 = sizeof(T) * ((size_t)npad + ((size_t)a.tau * KA + pf_slot_round<RB>() - 1) / pf_slot_round<RB>() * pf_slot_round<RB>());
     if (a.K > 0) {
         hipLaunchKernelGGL((pf_rowdot_kernel<T, NEL, RB, true>), grid, dim3(kThreads), lds1, s, a, rpb, bpw);
         return hipGetLastError();
