@@ -381,7 +381,9 @@ template <class T, int NEL> hipError_t accept_nel(const StepArgs &a, hipStream_t
     constexpr int V = vec16<T>();
     const int npad = (NEL / V) * V * 64;
     int rpb, bpw;
-    block_shape(a.W, a.n, kWaves * RB, rpb, bpw);
+    // at least two row batches per wave: the block's set-up (x and h staged
+    // in LDS) is shared by twice the rows, and half as many blocks queue up
+    block_shape(a.W, a.n, 2 * kWaves * RB, rpb, bpw);
     const dim3 grid((unsigned)(a.W * bpw));
     const size_t lds1 = sizeof(T) * ((size_t)npad + ((size_t)a.tau * KA + pf_slot_round<RB>() - 1) / pf_slot_round<RB>() * pf_slot_round<RB>());
     if (a.K > 0) {
