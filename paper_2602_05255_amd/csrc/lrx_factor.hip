@@ -865,9 +865,13 @@ __global__ __launch_bounds__(kT) void gj_update_kernel(FA a, int j0, int nb, int
 // blocks (16 rows per wave), loading the next block while the current one is
 // on the matrix cores.  Loads are unconditional from clamped addresses
 // (rows past n and columns past the batch are computed and not stored).
-template <class Wd> constexpr int outer_cb() { return sizeof(Wd) == 8 ? 32 : 16; }
-template <class Wd> size_t outer_lds(int n) {
-    return (((size_t)n * 4 + 15) / 16) * 16 + (size_t)64 * (outer_cb<Wd>() + 1) * sizeof(Wd);
+// Columns per work-group: every work-group of a walker re-reads the whole Zt
+// panel, so wider groups cut that re-read traffic; 64 real columns from
+// n = 512 on, where a walker still has at least 7 groups.
+template <class Wd> constexpr int outer_cb_max() { return sizeof(Wd) == 8 ? 64 : 16; }
+template <class Wd> int outer_cb(int n) { return sizeof(Wd) == 8 ? (n >= 512 ? 64 : 32) : 16; }
+template <class Wd> size_t outer_lds(int n, int cb) {
+    return (((size_t)n * 4 + 15) / 16) * 16 + (size_t)64 * (cb + 1) * sizeof(Wd);
 }
 
 template <class Wd, int CB>
@@ -1121,10 +1125,20 @@ template <class Wd>
 hipError_t launch_outer(const FA &fa, int j0, int nbo, hipStream_t s) {
     const int others = fa.n - nbo;
     if (others <= 0) return hipSuccess;
-    constexpr int CB = outer_cb<Wd>();
-    const int ncb = (others + CB - 1) / CB;
-    hipLaunchKernelGGL((gj_outer_kernel<Wd, CB>), dim3((unsigned)(fa.W * ncb)), dim3(kT), outer_lds<Wd>(fa.n), s,
-                       fa, j0, nbo, ncb);
+    const int cb = outer_cb<Wd>(fa.n);
+    const int ncb = (others + cb - 1) / cb;
+    const size_t lds = outer_lds<Wd>(fa.n, cb);
+    if (cb == 64) {
+        if constexpr (outer_cb_max<Wd>() >= 64)
+            hipLaunchKernelGGL((gj_outer_kernel<Wd, 64>), dim3((unsigned)(fa.W * ncb)), dim3(kT), lds, s, fa, j0, nbo,
+                               ncb);
+    } else if (cb == 32) {
+        if constexpr (outer_cb_max<Wd>() >= 32)
+            hipLaunchKernelGGL((gj_outer_kernel<Wd, 32>), dim3((unsigned)(fa.W * ncb)), dim3(kT), lds, s, fa, j0, nbo,
+                               ncb);
+    } else {
+        hipLaunchKernelGGL((gj_outer_kernel<Wd, 16>), dim3((unsigned)(fa.W * ncb)), dim3(kT), lds, s, fa, j0, nbo, ncb);
+    }
     return hipGetLastError();
 }
 
