@@ -63,6 +63,9 @@ __global__ __launch_bounds__(kThreads) void pf_build_hop_kernel(HopArgs a) {
 }
 
 // ------------------------------------------------------------------ propose
+// Slot columns per unrolled round of loads in the column pass of the propose.
+constexpr int kPfPropRound = 16;
+
 template <class T>
 __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
     using Wd = typename Wide<T>::type;
@@ -78,8 +81,13 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
     T *h = reinterpret_cast<T *>(st + a.L.g);
     Wd *ratio_st = reinterpret_cast<Wd *>(st + a.L.ratio);
 
-    T *s_m = reinterpret_cast<T *>(smem);      // [TE] R_t^-1 a_t[i,:]^T
-    T *s_red = s_m + TE;                       // [kWaves]
+    // Loads go out in unrolled rounds from clamped addresses; the LDS operands
+    // they meet are zero-padded to whole rounds, so padded terms add nothing.
+    const int TEp = (TE + kPfPropRound - 1) / kPfPropRound * kPfPropRound;
+    const int npx = (n + 8 * 64 - 1) / (8 * 64) * (8 * 64);
+    T *s_m = reinterpret_cast<T *>(smem);      // [TEp] R_t^-1 a_t[i,:]^T
+    T *s_red = s_m + TEp;                      // [kWaves]
+    T *s_x = s_red + kWaves;                   // [npx] x
     __shared__ int s_i, s_bad;
     if (tid == 0) {
         int i = a.rows[w * a.KM];
@@ -87,21 +95,33 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
         s_i = bad ? 0 : i;
         s_bad = bad;
     }
+    for (int j = tid; j < npx; j += kThreads) {
+        T v = zero<T>();
+        if (j < n) v = x[j];
+        s_x[j] = v;
+    }
     __syncthreads();
     const int i = s_i;
-    for (int te = tid; te < TE; te += kThreads) {
+    for (int te = tid; te < TEp; te += kThreads) {
         const int t = te / KA, s = te - t * KA;
         T v = zero<T>();
-        for (int sp = 0; sp < KA; ++sp) v = fmac(rinv[(size_t)t * KA * KA + s * KA + sp], fa[(size_t)(t * KA + sp) * n + i], v);
+        if (te < TE)
+            for (int sp = 0; sp < KA; ++sp) v = fmac(rinv[(size_t)t * KA * KA + s * KA + sp], fa[(size_t)(t * KA + sp) * n + i], v);
         s_m[te] = v;
     }
     __syncthreads();
     T part = zero<T>();
     for (int q = tid; q < n; q += kThreads) {
         T c = -M[(size_t)i * n + q];
-        for (int te = 0; te < TE; ++te) c = fmac(fa[(size_t)te * n + q], s_m[te], c);
+        for (int t0 = 0; t0 < TE; t0 += kPfPropRound) {
+            T fv[kPfPropRound];
+#pragma unroll
+            for (int j = 0; j < kPfPropRound; ++j) fv[j] = fa[(size_t)min(t0 + j, TE - 1) * n + q];
+#pragma unroll
+            for (int j = 0; j < kPfPropRound; ++j) c = fmac(fv[j], s_m[t0 + j], c);
+        }
         col[q] = c;
-        part = fmac(x[q], c, part);
+        part = fmac(s_x[q], c, part);
     }
     part = wave_sum(part);
     if (lane == 0) s_red[wv] = part;
@@ -111,9 +131,19 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
             T g[KA];
 #pragma unroll
             for (int s = 0; s < KA; ++s) g[s] = zero<T>();
-            for (int q = lane; q < n; q += 64)
+            for (int q0 = 0; q0 < n; q0 += 8 * 64) {
+                T fv[8][KA];
 #pragma unroll
-                for (int s = 0; s < KA; ++s) g[s] = fmac(fa[(size_t)(t * KA + s) * n + q], x[q], g[s]);
+                for (int j = 0; j < 8; ++j) {
+                    const int q = min(q0 + j * 64 + lane, n - 1);
+#pragma unroll
+                    for (int s = 0; s < KA; ++s) fv[j][s] = fa[(size_t)(t * KA + s) * n + q];
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+#pragma unroll
+                    for (int s = 0; s < KA; ++s) g[s] = fmac(fv[j][s], s_x[q0 + j * 64 + lane], g[s]);
+            }
 #pragma unroll
             for (int s = 0; s < KA; ++s) g[s] = wave_sum(g[s]);
             if (lane < KA) {
@@ -356,7 +386,9 @@ template <class T> hipError_t build_hop_t(const HopArgs &a, hipStream_t s) {
 }
 
 template <class T> hipError_t propose_t(const StepArgs &a, hipStream_t s) {
-    size_t lds = sizeof(T) * ((size_t)a.tau * KA + kWaves);
+    const size_t tep = ((size_t)a.tau * KA + kPfPropRound - 1) / kPfPropRound * kPfPropRound;
+    const size_t npx = ((size_t)a.n + 8 * 64 - 1) / (8 * 64) * (8 * 64);
+    size_t lds = sizeof(T) * (tep + kWaves + npx);
     hipLaunchKernelGGL(pf_propose_kernel<T>, dim3(a.W), dim3(kThreads), lds, s, a);
     return hipGetLastError();
 }
