@@ -149,7 +149,6 @@ class Run:
         else:
             wk.use_draws(k, e, s)
             wk.propose()
-            lrx.lrx_metropolis(wk.st, wk.ratio, None, 0, t, lrx.LRX_MH_FORCE, wk.accept)
         if timer is not None:
             timer.end("propose")
             timer.begin("accept", wk.st.slot, wk.W)
@@ -157,8 +156,8 @@ class Run:
             lrx.lrx_det_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
                                    wk.empty, wk.n_empty)
         else:
-            lrx.lrx_pf_accept_update(wk.st, k, e, wk.u, wk.accept)
-            lrx.lrx_hop_commit(wk.W, wk.n, wk.n_empty, wk.k_max, k, e, s, wk.accept, wk.occ, wk.empty)
+            lrx.lrx_pf_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
+                                  wk.empty, wk.n_empty)
         if timer is not None:
             timer.end("accept")
         if wk.delay and wk.st.slot == wk.delay:

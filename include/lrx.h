@@ -403,6 +403,24 @@ int lrx_pf_accept_update(lrx_state *st, const int32_t *k, const int32_t *cols,
                          const void *x, uint8_t *accept, void *stream);
 
 /*
+ * lrx_metropolis, lrx_pf_accept_update and lrx_hop_commit in one launch
+ * sequence: every block of the row pass takes the same Metropolis decision
+ * from the stashed ratio (mode LRX_MH_UNIFORMS with u01, LRX_MH_DEVICE_RNG
+ * with seed/counter, or LRX_MH_FORCE), applies the update of
+ * lrx_pf_accept_update, and one block commits the occupancy (the swap of
+ * occ[w][cols[w]] and empty[w][slot[w]] for an accepted walker).
+ *   slot: int32 [W][k_max] index into empty of the target site (device);
+ *   accept: uint8 [W] out (the decision actually applied).
+ * Errors as for lrx_pf_accept_update; LRX_EINVAL also for an unknown mode or
+ * LRX_MH_UNIFORMS without u01, LRX_ESHAPE for n_empty < 1.
+ */
+int lrx_pf_accept_hop(lrx_state *st, const int32_t *k, const int32_t *cols,
+                      const int32_t *slot, const void *x, int32_t mode,
+                      const double *u01, uint64_t seed, uint64_t counter,
+                      uint8_t *accept, int32_t *occ, int32_t *empty,
+                      int32_t n_empty, void *stream);
+
+/*
  * Flush (Eq. pf_delayed_Ainv): M0 += sum_t a_t R_t^-1 a_t^T on MFMA, computing
  * only tiles on and above the diagonal and writing the lower triangle as the
  * exact negative transpose, so M0 stays exactly skew.  Zeroes the slots and

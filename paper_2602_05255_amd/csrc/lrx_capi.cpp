@@ -436,6 +436,34 @@ int lrx_pf_accept_update(lrx_state *st, const int32_t *k, const int32_t *cols, c
     return rc;
 }
 
+int lrx_pf_accept_hop(lrx_state *st, const int32_t *k, const int32_t *cols, const int32_t *slot, const void *x,
+                      int32_t mode, const double *u01, uint64_t seed, uint64_t counter, uint8_t *accept,
+                      int32_t *occ, int32_t *empty, int32_t n_empty, void *stream) {
+    int rc = check_kind(st, LRX_PF);
+    if (rc) return rc;
+    if (!k || !cols || !slot || !x || !accept || !occ || !empty) return LRX_EINVAL;
+    if (mode != LRX_MH_UNIFORMS && mode != LRX_MH_DEVICE_RNG && mode != LRX_MH_FORCE) return LRX_EINVAL;
+    if (mode == LRX_MH_UNIFORMS && !u01) return LRX_EINVAL;
+    if (n_empty < 1) return LRX_ESHAPE;
+    if (st->shape.delay > 0 && st->slot >= st->shape.delay) return LRX_ENEEDFLUSH;
+    StepArgs a = step_args(st);
+    a.k = k;
+    a.rows = cols;
+    a.u = x;
+    a.accept = accept;
+    a.slot = slot;
+    a.occ = occ;
+    a.empty = empty;
+    a.n_empty = n_empty;
+    a.mh_mode = mode;
+    a.u01 = u01;
+    a.seed = seed;
+    a.counter = counter;
+    rc = hip_rc(pf_accept(st->shape.dtype, a, as_stream(stream)));
+    if (rc == LRX_OK && st->shape.delay > 0) st->slot += 1;
+    return rc;
+}
+
 int lrx_pf_flush_delayed(lrx_state *st, void *stream) {
     int rc = check_kind(st, LRX_PF);
     if (rc) return rc;

@@ -201,10 +201,33 @@ __global__ __launch_bounds__(kThreads) void pf_rowdot_kernel(StepArgs a, int row
     T *ax = reinterpret_cast<T *>(st + a.L.ax);
     int *kslot = reinterpret_cast<int *>(st + a.L.kslot);
     const Wd ratio = *reinterpret_cast<const Wd *>(st + a.L.ratio);
-    const bool take = a.accept[w] != 0 && a.flags[w] == 0 && !is_zero(ratio);
+    const uint32_t fl = a.flags[w];
+    uint8_t acc;
+    if (a.mh_mode >= 0) {   // fused Metropolis decision (identical in every block of the walker)
+        acc = mh_decide<Wd>(ratio, fl, a.mh_mode, a.mh_mode == LRX_MH_UNIFORMS ? a.u01[w] : 0.0, a.seed,
+                            a.counter, (uint32_t)w + a.rng_base);
+    } else {
+        acc = a.accept[w];
+    }
+    const bool take = acc != 0 && fl == 0 && !is_zero(ratio);
+    if (rb == 0 && tid == 0) {
+        if (a.mh_mode >= 0 || (!take && acc)) a.accept[w] = take ? 1 : 0;   // skipped: no occupancy commit
+        if (take && a.occ) {   // fused occupancy commit of the hop
+            int kw = a.k[w];
+            kw = (kw < 1 || kw > a.KM) ? 0 : kw;
+            for (int c = 0; c < kw; ++c) {
+                const int e = a.rows[w * a.KM + c], sl = a.slot[w * a.KM + c];
+                if (e < 0 || e >= n || sl < 0 || sl >= a.n_empty) continue;
+                int32_t *po = a.occ + (size_t)w * n + e;
+                int32_t *pe = a.empty + (size_t)w * a.n_empty + sl;
+                const int32_t t = *po;
+                *po = *pe;
+                *pe = t;
+            }
+        }
+    }
 
     if (!take) {
-        if (rb == 0 && tid == 0 && a.accept[w]) a.accept[w] = 0;   // skipped: no occupancy commit
         if (DELAYED) {
             for (int q = q0 + tid; q < q1; q += kThreads) {
                 fa[(size_t)(tau * KA) * n + q] = zero<T>();

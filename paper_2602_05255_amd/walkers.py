@@ -113,18 +113,19 @@ class Walkers:
             self.refresh(report=False)
 
     def step_device(self, mode=lrx.LRX_MH_FORCE, u01=None, seed=0, counter=0):
-        """One step with the decision taken on the device: two fused launches for
-        determinants (propose_hop, accept_hop); the Pfaffian path uses the separate calls."""
+        """One step with the decision taken on the device: for determinants two fused
+        launches (propose_hop, accept_hop); for Pfaffians build + propose, then the
+        accept with the decision and the occupancy commit fused (accept_hop)."""
         k, elec, slot = self._k, self._elec, self._slot
-        if self.kind != lrx.LRX_DET:
+        if self.kind == lrx.LRX_DET:
+            lrx.lrx_det_propose_hop(self.st, self.table, self.sites, self.occ, self.empty, self.n_empty,
+                                    k, elec, slot, self.u, self.ratio)
+            lrx.lrx_det_accept_hop(self.st, k, elec, slot, self.u, mode, u01, seed, counter, self.accept,
+                                   self.occ, self.empty, self.n_empty)
+        else:
             self.propose()
-            self.decide(mode=mode, u01=u01, seed=seed, counter=counter)
-            self.apply()
-            return
-        lrx.lrx_det_propose_hop(self.st, self.table, self.sites, self.occ, self.empty, self.n_empty,
-                                k, elec, slot, self.u, self.ratio)
-        lrx.lrx_det_accept_hop(self.st, k, elec, slot, self.u, mode, u01, seed, counter, self.accept,
-                               self.occ, self.empty, self.n_empty)
+            lrx.lrx_pf_accept_hop(self.st, k, elec, slot, self.u, mode, u01, seed, counter, self.accept,
+                                  self.occ, self.empty, self.n_empty)
         self.steps += 1
         if self.delay and self.st.slot == self.delay:
             self.flush()

@@ -119,6 +119,8 @@ def test_kind_mismatch():
     assert lib.lrx_det_propose_ratio(ctypes.byref(pf), P, P, P, P, None) == lrx.LRX_EKIND
     assert lib.lrx_det_flush_delayed(ctypes.byref(pf), None) == lrx.LRX_EKIND
     assert lib.lrx_pf_accept_update(ctypes.byref(det), P, P, P, P, None) == lrx.LRX_EKIND
+    assert lib.lrx_pf_accept_hop(ctypes.byref(det), P, P, P, P, lrx.LRX_MH_FORCE, None, 0, 0, P, P, P, 8,
+                                 None) == lrx.LRX_EKIND
     assert lib.lrx_pf_init_inverse(ctypes.byref(det), P, 8, P, None) == lrx.LRX_EKIND
 
 
@@ -142,6 +144,8 @@ def test_delay_window_bookkeeping():
     assert lib.lrx_det_refresh(ctypes.byref(pending), P, 16, P, None, None) == lrx.LRX_ENEEDFLUSH
     pf_full = fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64, delay=2, slot=2)
     assert lib.lrx_pf_accept_update(ctypes.byref(pf_full), P, P, P, P, None) == lrx.LRX_ENEEDFLUSH
+    assert lib.lrx_pf_accept_hop(ctypes.byref(pf_full), P, P, P, P, lrx.LRX_MH_FORCE, None, 0, 0, P, P, P, 8,
+                                 None) == lrx.LRX_ENEEDFLUSH
     # flushing an empty window is a no-op that never touches the GPU
     empty = fake_state(delay=4, slot=0)
     assert lib.lrx_det_flush_delayed(ctypes.byref(empty), None) == lrx.LRX_OK
@@ -158,6 +162,12 @@ def test_metropolis_and_commit_validation():
     assert lib.lrx_hop_commit(0, 8, 8, 1, P, P, P, P, P, P, None) == lrx.LRX_ESHAPE
     assert lib.lrx_hop_commit(4, 8, 8, 9, P, P, P, P, P, P, None) == lrx.LRX_ESHAPE
     assert lib.lrx_hop_commit(4, 8, 8, 1, P, P, P, P, None, P, None) == lrx.LRX_EINVAL
+    pf = fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64)
+    hop = lib.lrx_pf_accept_hop
+    assert hop(ctypes.byref(pf), P, P, P, P, 7, None, 0, 0, P, P, P, 8, None) == lrx.LRX_EINVAL
+    assert hop(ctypes.byref(pf), P, P, P, P, lrx.LRX_MH_UNIFORMS, None, 0, 0, P, P, P, 8, None) == lrx.LRX_EINVAL
+    assert hop(ctypes.byref(pf), P, P, None, P, lrx.LRX_MH_FORCE, None, 0, 0, P, P, P, 8, None) == lrx.LRX_EINVAL
+    assert hop(ctypes.byref(pf), P, P, P, P, lrx.LRX_MH_FORCE, None, 0, 0, P, P, P, 0, None) == lrx.LRX_ESHAPE
 
 
 def test_pf_refresh_sites_check():

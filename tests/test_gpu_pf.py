@@ -74,6 +74,33 @@ def test_pf_chain(dt, n, K, W, steps):
     assert np.array_equal(m, -np.swapaxes(m, 1, 2)), "updates and flushes keep M exactly skew"
 
 
+@pytest.mark.parametrize("K", [0, 5])
+def test_pf_fused_accept_hop_matches_oracle(K):
+    """build + propose, then accept_hop (device Metropolis with the given uniforms,
+    fused occupancy commit) follow the oracle's chain."""
+    say(f"pf fused accept_hop K={K}")
+    g, f, occ, emp = pf_inputs(700 + K, 96, 48, 5, True)
+    steps = 17
+    wk = Walkers(lrx.LRX_PF, torch.complex128, f, occ, emp, 1, K)
+    chain = orc.PfChain(f, occ, emp)
+    u01 = torch.zeros(5, dtype=torch.float64, device="cuda")
+    for t in range(steps):
+        k, elec, slot = gen.hop_draws(g, 5, 48, 48, (1,), 1)
+        u = gen.uniforms(g, 5)
+        wk.set_draws(k, elec, slot)
+        u01.copy_(torch.as_tensor(u))
+        wk.step_device(mode=lrx.LRX_MH_UNIFORMS, u01=u01)
+        r_orc = chain.propose(k, elec, slot)
+        assert ratio_err(wk.ratio.cpu().numpy(), r_orc).max() <= 1e-10, t
+        mask = orc.metropolis(r_orc, u)
+        np.testing.assert_array_equal(wk.accept.cpu().numpy().astype(bool), mask)
+        chain.accept(k, elec, slot, mask)
+    np.testing.assert_array_equal(wk.occ.cpu().numpy(), chain.book.occ)
+    np.testing.assert_array_equal(wk.empty.cpu().numpy(), chain.book.empty)
+    assert rel_err(wk.inverse().cpu().numpy(), chain.inv, axis=(1, 2)).max() <= 1e-10
+    np.testing.assert_allclose(wk.st.logabs.cpu().numpy(), chain.logabs, atol=1e-9)
+
+
 def test_pf_c64_bulk_error_is_bounded():
     say("pf c64 chain")
     g, f, occ, emp = pf_inputs(500, 256, 128, 4, True)
