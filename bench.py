@@ -147,8 +147,8 @@ class Run:
             lrx.lrx_det_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
                                     wk.ratio)
         else:
-            wk.use_draws(k, e, s)
-            wk.propose()
+            lrx.lrx_pf_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
+                                   wk.ratio)
         if timer is not None:
             timer.end("propose")
             timer.begin("accept", wk.st.slot, wk.W)

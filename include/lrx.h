@@ -403,6 +403,18 @@ int lrx_pf_accept_update(lrx_state *st, const int32_t *k, const int32_t *cols,
                          const void *x, uint8_t *accept, void *stream);
 
 /*
+ * lrx_pf_build_hop followed by lrx_pf_propose_ratio in one launch: the hop
+ * vector x (Sec. III.B, Eq. pf_rank2: x_j = f[s'][occ_j] - f[s][occ_j] for
+ * j != i, x_i = 0) is built inside the ratio kernel and written to x for the
+ * accept that follows.  Arguments as for the two calls; cols are the electron
+ * labels.
+ */
+int lrx_pf_propose_hop(lrx_state *st, const void *f, int32_t sites,
+                       const int32_t *occ, const int32_t *empty, int32_t n_empty,
+                       const int32_t *k, const int32_t *cols, const int32_t *slot,
+                       void *x, void *ratio, void *stream);
+
+/*
  * lrx_metropolis, lrx_pf_accept_update and lrx_hop_commit in one launch
  * sequence: every block of the row pass takes the same Metropolis decision
  * from the stashed ratio (mode LRX_MH_UNIFORMS with u01, LRX_MH_DEVICE_RNG

@@ -436,6 +436,28 @@ int lrx_pf_accept_update(lrx_state *st, const int32_t *k, const int32_t *cols, c
     return rc;
 }
 
+int lrx_pf_propose_hop(lrx_state *st, const void *f, int32_t sites, const int32_t *occ, const int32_t *empty,
+                       int32_t n_empty, const int32_t *k, const int32_t *cols, const int32_t *slot, void *x,
+                       void *ratio, void *stream) {
+    int rc = check_kind(st, LRX_PF);
+    if (rc) return rc;
+    if (!f || !occ || !empty || !k || !cols || !slot || !x || !ratio) return LRX_EINVAL;
+    if (sites < st->shape.n || n_empty < 1) return LRX_ESHAPE;
+    if (st->shape.delay > 0 && st->slot >= st->shape.delay) return LRX_ENEEDFLUSH;
+    StepArgs a = step_args(st);
+    a.k = k;
+    a.rows = cols;
+    a.u = x;
+    a.ratio = ratio;
+    a.hop_table = f;
+    a.sites = sites;
+    a.n_empty = n_empty;
+    a.occ = const_cast<int32_t *>(occ);
+    a.empty = const_cast<int32_t *>(empty);
+    a.slot = slot;
+    return hip_rc(pf_propose(st->shape.dtype, a, as_stream(stream)));
+}
+
 int lrx_pf_accept_hop(lrx_state *st, const int32_t *k, const int32_t *cols, const int32_t *slot, const void *x,
                       int32_t mode, const double *u01, uint64_t seed, uint64_t counter, uint8_t *accept,
                       int32_t *occ, int32_t *empty, int32_t n_empty, void *stream) {

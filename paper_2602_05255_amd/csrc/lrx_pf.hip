@@ -88,20 +88,52 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
     T *s_m = reinterpret_cast<T *>(smem);      // [TEp] R_t^-1 a_t[i,:]^T
     T *s_red = s_m + TEp;                      // [kWaves]
     T *s_x = s_red + kWaves;                   // [npx] x
-    __shared__ int s_i, s_bad;
+    // With a hop table the hop vector is built here, x[j] = f[s'][occ_j] -
+    // f[s][occ_j] (j != i), and written to x for the accept that follows.
+    const bool fused = a.hop_table != nullptr;
+    __shared__ int s_i, s_bad, s_src, s_dst;
     if (tid == 0) {
         int i = a.rows[w * a.KM];
         int bad = (a.k[w] != 1) || i < 0 || i >= n;
+        int src = 0, dst = 0;
+        if (fused && !bad) {
+            const int sl = a.slot[w * a.KM];
+            if (sl < 0 || sl >= a.n_empty) {
+                bad = 1;
+            } else {
+                src = a.occ[(size_t)w * n + i];
+                dst = a.empty[(size_t)w * a.n_empty + sl];
+                if (src < 0 || src >= a.sites || dst < 0 || dst >= a.sites) bad = 1;
+            }
+        }
         s_i = bad ? 0 : i;
         s_bad = bad;
-    }
-    for (int j = tid; j < npx; j += kThreads) {
-        T v = zero<T>();
-        if (j < n) v = x[j];
-        s_x[j] = v;
+        s_src = bad ? 0 : src;
+        s_dst = bad ? 0 : dst;
     }
     __syncthreads();
     const int i = s_i;
+    if (fused) {
+        const Wd *tab = static_cast<const Wd *>(a.hop_table);
+        const Wd *fs = tab + (size_t)s_src * a.sites, *fd = tab + (size_t)s_dst * a.sites;
+        const int32_t *occ = a.occ + (size_t)w * n;
+        T *xw = const_cast<T *>(x);
+        for (int j = tid; j < npx; j += kThreads) {
+            T v = zero<T>();
+            if (j < n && !s_bad && j != i) {
+                const int oj = occ[j];
+                if (oj >= 0 && oj < a.sites) v = conv<T>(fd[oj] - fs[oj]);
+            }
+            if (j < n) xw[j] = v;
+            s_x[j] = v;
+        }
+    } else {
+        for (int j = tid; j < npx; j += kThreads) {
+            T v = zero<T>();
+            if (j < n) v = x[j];
+            s_x[j] = v;
+        }
+    }
     for (int te = tid; te < TEp; te += kThreads) {
         const int t = te / KA, s = te - t * KA;
         T v = zero<T>();

@@ -90,6 +90,7 @@ _SIGS = {
     "lrx_pf_build_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], ctypes.c_int),
     "lrx_pf_propose_ratio": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _P], ctypes.c_int),
     "lrx_pf_accept_update": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_pf_propose_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "lrx_pf_accept_hop": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _I, _P, ctypes.c_uint64, ctypes.c_uint64,
                            _P, _P, _P, _I, _P], ctypes.c_int),
     "lrx_pf_flush_delayed": ([ctypes.POINTER(lrx_state), _P], ctypes.c_int),
@@ -359,6 +360,19 @@ def lrx_pf_accept_update(st: State, k, cols, x, accept, stream=None):
     _dev(accept, "accept", torch.uint8, (st.walkers,))
     _check(_lib.lrx_pf_accept_update(st.ptr(), _dev(k, "k"), _dev(cols, "cols"), _dev(x, "x"),
                                      _dev(accept, "accept"), _stream(stream)), "lrx_pf_accept_update")
+
+
+def lrx_pf_propose_hop(st: State, f, sites, occ, empty, n_empty, k, cols, slot, x, ratio, stream=None):
+    _dev(occ, "occ", torch.int32, (st.walkers, st.n))
+    _dev(empty, "empty", torch.int32, (st.walkers, n_empty))
+    _kvec(st, k, cols, "cols")
+    _dev(slot, "slot", torch.int32, (st.walkers, st.k_max))
+    _dev(x, "x", st.dtype, (st.walkers, st.n))
+    _dev(ratio, "ratio", st.wide, (st.walkers,))
+    _check(_lib.lrx_pf_propose_hop(st.ptr(), _dev(f, "f", st.wide), int(sites), _dev(occ, "occ"),
+                                   _dev(empty, "empty"), int(n_empty), _dev(k, "k"), _dev(cols, "cols"),
+                                   _dev(slot, "slot"), _dev(x, "x"), _dev(ratio, "ratio"), _stream(stream)),
+           "lrx_pf_propose_hop")
 
 
 def lrx_pf_accept_hop(st: State, k, cols, slot, x, mode, u01, seed, counter, accept, occ, empty, n_empty,

@@ -113,9 +113,9 @@ class Walkers:
             self.refresh(report=False)
 
     def step_device(self, mode=lrx.LRX_MH_FORCE, u01=None, seed=0, counter=0):
-        """One step with the decision taken on the device: for determinants two fused
-        launches (propose_hop, accept_hop); for Pfaffians build + propose, then the
-        accept with the decision and the occupancy commit fused (accept_hop)."""
+        """One step with the decision taken on the device, for determinants and Pfaffians
+        alike in two fused calls: propose_hop (hop vector and ratio) and accept_hop
+        (decision, update and occupancy commit)."""
         k, elec, slot = self._k, self._elec, self._slot
         if self.kind == lrx.LRX_DET:
             lrx.lrx_det_propose_hop(self.st, self.table, self.sites, self.occ, self.empty, self.n_empty,
@@ -123,7 +123,8 @@ class Walkers:
             lrx.lrx_det_accept_hop(self.st, k, elec, slot, self.u, mode, u01, seed, counter, self.accept,
                                    self.occ, self.empty, self.n_empty)
         else:
-            self.propose()
+            lrx.lrx_pf_propose_hop(self.st, self.table, self.sites, self.occ, self.empty, self.n_empty,
+                                   k, elec, slot, self.u, self.ratio)
             lrx.lrx_pf_accept_hop(self.st, k, elec, slot, self.u, mode, u01, seed, counter, self.accept,
                                   self.occ, self.empty, self.n_empty)
         self.steps += 1

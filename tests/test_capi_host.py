@@ -163,6 +163,10 @@ def test_metropolis_and_commit_validation():
     assert lib.lrx_hop_commit(4, 8, 8, 9, P, P, P, P, P, P, None) == lrx.LRX_ESHAPE
     assert lib.lrx_hop_commit(4, 8, 8, 1, P, P, P, P, None, P, None) == lrx.LRX_EINVAL
     pf = fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64)
+    ph = lib.lrx_pf_propose_hop
+    assert ph(ctypes.byref(pf), P, 16, P, P, 8, P, P, None, P, P, None) == lrx.LRX_EINVAL
+    assert ph(ctypes.byref(pf), P, 4, P, P, 8, P, P, P, P, P, None) == lrx.LRX_ESHAPE      # sites < n
+    assert ph(ctypes.byref(st), P, 16, P, P, 8, P, P, P, P, P, None) == lrx.LRX_EKIND
     hop = lib.lrx_pf_accept_hop
     assert hop(ctypes.byref(pf), P, P, P, P, 7, None, 0, 0, P, P, P, 8, None) == lrx.LRX_EINVAL
     assert hop(ctypes.byref(pf), P, P, P, P, lrx.LRX_MH_UNIFORMS, None, 0, 0, P, P, P, 8, None) == lrx.LRX_EINVAL

@@ -75,10 +75,11 @@ def test_pf_chain(dt, n, K, W, steps):
 
 
 @pytest.mark.parametrize("K", [0, 5])
-def test_pf_fused_accept_hop_matches_oracle(K):
-    """build + propose, then accept_hop (device Metropolis with the given uniforms,
-    fused occupancy commit) follow the oracle's chain."""
-    say(f"pf fused accept_hop K={K}")
+def test_pf_fused_hop_step_matches_oracle(K):
+    """propose_hop (hop vector built in the ratio kernel), then accept_hop (device
+    Metropolis with the given uniforms, fused occupancy commit) follow the oracle's
+    chain; the x written by propose_hop equals the separately built one."""
+    say(f"pf fused hop step K={K}")
     g, f, occ, emp = pf_inputs(700 + K, 96, 48, 5, True)
     steps = 17
     wk = Walkers(lrx.LRX_PF, torch.complex128, f, occ, emp, 1, K)
@@ -89,7 +90,11 @@ def test_pf_fused_accept_hop_matches_oracle(K):
         u = gen.uniforms(g, 5)
         wk.set_draws(k, elec, slot)
         u01.copy_(torch.as_tensor(u))
+        x_sep = torch.zeros_like(wk.u)
+        lrx.lrx_pf_build_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, wk._k, wk._elec,
+                             wk._slot, x_sep)
         wk.step_device(mode=lrx.LRX_MH_UNIFORMS, u01=u01)
+        assert torch.equal(wk.u, x_sep), t
         r_orc = chain.propose(k, elec, slot)
         assert ratio_err(wk.ratio.cpu().numpy(), r_orc).max() <= 1e-10, t
         mask = orc.metropolis(r_orc, u)
