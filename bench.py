@@ -74,7 +74,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed refresh periods")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="slater_n256_k124")
+    ap.add_argument("--workload", default="uneven_n64_1024_fp32",
+                    help="default: the uneven batch as the headline with every other configuration as extra keys")
     ap.add_argument("--walkers", type=int, default=0, help="override the walker count")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -91,19 +92,16 @@ def parse():
 
 
 class Run:
-    """One walker batch with its pre-generated draws, stepping one refresh period at a time.
-
-    With streams > 1 the batch is split into that many independent sub-batches (their own
-    states), each driven on its own HIP stream (default priority) and forked from / joined to
-    the calling stream every period: one sub-batch's latency-bound launches (propose, flush,
-    refresh blocks) then run beside another's bandwidth-bound accept.  The walkers and their
-    arithmetic are the same as with one stream."""
+    """One walker batch of a uniform-n workload with its pre-generated draws for one refresh
+    period, driven by the package's PeriodDriver (sub-batches on their own streams,
+    staggered refreshes, one HIP graph per period).  Workloads without a refresh (the plain
+    Sherman-Morrison chain) use their step count as the period and never refresh."""
 
     def __init__(self, wl, dtype, walkers, seed_offset=0, streams=1):
         import torch
         from paper_2602_05255_amd import inputs as gen
         from paper_2602_05255_amd import lrx
-        from paper_2602_05255_amd.walkers import Walkers
+        from paper_2602_05255_amd.driver import PeriodDriver
         self.torch, self.lrx = torch, lrx
         self.wl = wl
         if wl.kind == "det":
@@ -112,117 +110,29 @@ class Run:
             phi, occ, emp, g = gen.pairing_inputs(wl, walkers=walkers, seed_offset=seed_offset)
         self.phi = phi
         self.W = walkers
-        self.P = wl.refresh
+        self.P = wl.refresh if wl.refresh else wl.steps
         t0 = time.time()
         k, e, s = gen.hop_draws_batch(g, self.P, walkers, wl.n, wl.sites - wl.n, wl.ranks, wl.k_max)
         log(f"  draws {self.P} x {walkers}: {time.time() - t0:.1f}s")
-        dev = torch.device("cuda")
-        self.k = torch.as_tensor(k).to(dev)
-        self.e = torch.as_tensor(e).to(dev)
-        self.s = torch.as_tensor(s).to(dev)
+        draws = tuple(torch.as_tensor(x).cuda() for x in (k, e, s))
         kind = lrx.LRX_DET if wl.kind == "det" else lrx.LRX_PF
-        bounds = np.linspace(0, walkers, max(1, streams) + 1).astype(int)
-        self.parts = []
-        for a0, a1 in zip(bounds[:-1], bounds[1:]):
-            wk = Walkers(kind, dtype, phi, occ[a0:a1], emp[a0:a1], wl.k_max, wl.delay, refresh_period=0)
-            self.parts.append((wk, int(a0), int(a1), torch.cuda.Stream() if streams > 1 else None))
+        self.drv = PeriodDriver(kind, dtype, phi, occ, emp, wl.k_max, wl.delay, self.P, draws, streams=streams,
+                                refresh=bool(wl.refresh))
+        self.parts = self.drv.parts
         self.wk = self.parts[0][0]
-        self.graph = None
-        # Sub-batch p runs offsets[p] steps ahead (a multiple of K), so the sub-batches reach
-        # their refresh at different steps and each refresh overlaps the others' steps.
-        K = max(1, wl.delay)
-        self.offsets = [(p * (self.P // len(self.parts))) // K * K for p in range(len(self.parts))]
-        self.primed = False
 
     @property
     def occ(self):
-        return self.torch.cat([wk.occ for wk, _, _, _ in self.parts])
+        return self.drv.occ
 
-    def _step(self, wk, a0, a1, t, timer):
-        lrx = self.lrx
-        k, e, s = self.k[t, a0:a1], self.e[t, a0:a1], self.s[t, a0:a1]
-        if timer is not None:
-            timer.begin("propose", wk.st.slot)
-        if wk.kind == lrx.LRX_DET:
-            lrx.lrx_det_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
-                                    wk.ratio)
-        else:
-            lrx.lrx_pf_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k, e, s, wk.u,
-                                   wk.ratio)
-        if timer is not None:
-            timer.end("propose")
-            timer.begin("accept", wk.st.slot, wk.W)
-        if wk.kind == lrx.LRX_DET:
-            lrx.lrx_det_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
-                                   wk.empty, wk.n_empty)
-        else:
-            lrx.lrx_pf_accept_hop(wk.st, k, e, s, wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
-                                  wk.empty, wk.n_empty)
-        if timer is not None:
-            timer.end("accept")
-        if wk.delay and wk.st.slot == wk.delay:
-            if timer is not None:
-                timer.begin("flush", wk.st.slot)
-            wk.flush()
-            if timer is not None:
-                timer.end("flush")
-
-    def prime(self):
-        """Advance every sub-batch by its offset (once, before the first period)."""
-        if self.primed:
-            return
-        for (wk, a0, a1, _), off in zip(self.parts, self.offsets):
-            for t in range(off):
-                self._step(wk, a0, a1, t, None)
-        self.torch.cuda.synchronize()
-        self.primed = True
-
-    def period(self, timer=None):
-        """One refresh period: P steps of every sub-batch with forced accept, flushes every
-        K, and each sub-batch's refresh after its own P-th step.  With a timer every launch
-        runs on the calling stream (one at a time, so that each launch's own duration is
-        measured); otherwise the sub-batches run on their streams."""
-        torch = self.torch
-        self.prime()
-        split = timer is None and len(self.parts) > 1
-        cur = torch.cuda.current_stream()
-        if split:
-            for _, _, _, st in self.parts:
-                st.wait_stream(cur)
-        for t in range(self.P):
-            for (wk, a0, a1, st), off in zip(self.parts, self.offsets):
-                local = (t + off) % self.P
-                with torch.cuda.stream(st) if split else contextlib.nullcontext():
-                    self._step(wk, a0, a1, local, None if split else timer)
-                    if local == self.P - 1:
-                        if timer is not None:
-                            timer.begin("refresh", 0)
-                        wk.refresh(report=False)
-                        if timer is not None:
-                            timer.end("refresh")
-        if split:
-            for _, _, _, st in self.parts:
-                cur.wait_stream(st)
+    def period(self, timer=None, probe=None):
+        self.drv.period(timer, probe)
 
     def capture(self):
-        torch = self.torch
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            self.period()
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.period()
-        torch.cuda.synchronize()
-        self.graph = g
+        self.drv.capture()
 
     def step(self):
-        if self.graph is not None:
-            self.graph.replay()
-        else:
-            self.period()
+        self.drv.step()
 
 
 class EventTimer:
@@ -253,15 +163,20 @@ class EventTimer:
 
 
 def accept_bytes(wl, s, W, tau):
-    """Algorithmic HBM bytes of one delayed accept launch (all walkers accepted).
-    DET: read A_0^-1 (n^2), the tau live b-slot rows (n k_max tau), u and C
-    (2 n k_max); write slot tau of a and b (2 n k_max).
-    PF: read A_0^-1 (n^2), x, col and the 2 tau a-slot columns; write the two
-    new a-slot columns."""
-    n, km = wl.n, wl.k_max
+    """Algorithmic HBM bytes of one accept launch (all walkers accepted), kbar = mean rank.
+    Delayed DET: read A_0^-1 (n^2), the tau live b-slot rows (n kbar tau), u and C
+    (2 n kbar); write slot tau of a and b (2 n kbar).
+    Delayed PF: read A_0^-1 (n^2), x, col and the 2 tau a-slot columns; write the two
+    new a-slot columns.
+    Plain DET (K = 0): read and write A^-1 (2 n^2), read u, C (2 n kbar), read R^-1.
+    Plain PF: three passes over A^-1 (3 n^2)."""
+    n = wl.n
+    kbar = float(np.mean(wl.ranks))
     if wl.kind == "pf":
-        return W * s * (n * n + 2 * n * tau + 4 * n)
-    return W * s * (n * n + n * km * tau + 4 * n * km)
+        return W * s * (3 * n * n if not wl.delay else n * n + 2 * n * tau + 4 * n)
+    if not wl.delay:
+        return W * s * (2 * n * n + 3 * n * kbar)
+    return W * s * (n * n + n * kbar * tau + 4 * n * kbar)
 
 
 def queue_filler(torch, ms=150.0):
@@ -290,7 +205,7 @@ def measure(wl, dtype, walkers, args, torch, label):
     t_tot = sum(dt for _, dt, _ in acc)
     fl = res.get("flush", [])
     flush_t = np.mean([dt for _, dt, _ in fl]) if fl else None
-    refresh_t = np.mean([dt for _, dt, _ in res["refresh"]])
+    refresh_t = np.mean([dt for _, dt, _ in res["refresh"]]) if "refresh" in res else float("nan")
     if not args.no_graph:
         run.capture()
     for _ in range(args.warmup):
@@ -335,39 +250,108 @@ def measure(wl, dtype, walkers, args, torch, label):
     }
 
 
-def rel_error(run, torch, sample):
-    """Max relative error of the LRU inverse and log|det| (log|pf|) on sampled walkers against the
-    full FP64 / complex128 recompute on the same GPU (torch.linalg: rocSOLVER LU).  For the
-    Pfaffian, log|pf| = log|det| / 2 (the phase is checked against the oracle by the tests)."""
-    wk = run.wk                      # the first sub-batch; sample spread over its walkers
-    sample = np.linspace(0, wk.W - 1, len(sample)).astype(int)
-    idx = torch.as_tensor(sample, device=wk.occ.device)
-    inv = wk.inverse()[idx]
-    occ = wk.occ[idx].long()
-    wide = torch.complex128 if run.wl.complex_ else torch.float64
-    src = torch.as_tensor(run.phi).to(device=inv.device, dtype=wide)
-    if run.wl.kind == "pf":
-        a = src[occ[:, :, None], occ[:, None, :]]
+def _recompute_state(torch, wide, table, occ, kind):
+    """FP64 / complex128 full recompute on the same GPU (torch.linalg: rocSOLVER LU) of the
+    inverse and log|det| (log|pf| = log|det| / 2) at the given occupancies."""
+    src = torch.as_tensor(table).to(device=occ.device, dtype=wide)
+    o = occ.long()
+    if kind == "pf":
+        a = src[o[:, :, None], o[:, None, :]]
         _, la = torch.linalg.slogdet(a)
-        la = 0.5 * la
-        rinv = torch.linalg.inv(a)
-        rinv = 0.5 * (rinv - rinv.transpose(1, 2))
-    else:
-        a = src[occ]
-        _, la = torch.linalg.slogdet(a)
-        rinv = torch.linalg.inv(a)
-    e_inv = torch.linalg.matrix_norm(inv.to(wide) - rinv) / torch.linalg.matrix_norm(rinv)
-    e_la = (wk.st.logabs[idx] - la).abs()
-    return {"inverse_max": float(e_inv.max()), "logdet_abs_max": float(e_la.max()), "walkers": len(sample),
-            "against": "FP64 full recompute on the same GPU (torch.linalg)"}
+        inv = torch.linalg.inv(a)
+        return 0.5 * (inv - inv.transpose(1, 2)), 0.5 * la
+    a = src[o]
+    _, la = torch.linalg.slogdet(a)
+    return torch.linalg.inv(a), la
+
+
+def state_error(torch, wk, idx, table, kind, complex_):
+    """Relative Frobenius error of the stored inverse and absolute error of the tracked
+    log|value| of walkers idx (state flushed) against the same-GPU full recompute."""
+    wide = torch.complex128 if complex_ else torch.float64
+    rinv, la = _recompute_state(torch, wide, table, wk.occ[idx], kind)
+    inv = wk.st.inv[idx].to(wide)
+    if kind == "det":
+        inv = inv.transpose(1, 2)          # the state holds A^-T
+    e_inv = (torch.linalg.matrix_norm(inv - rinv) / torch.linalg.matrix_norm(rinv)).cpu().numpy()
+    e_la = (wk.st.logabs[idx] - la).abs().cpu().numpy()
+    return e_inv, e_la
+
+
+def summarize_errors(rows, against, walkers):
+    """rows: (steps_since_refresh, e_inv[], e_la[]).  The headline figures are those at the
+    largest steps-since-refresh (the state just before its refresh), with the profile."""
+    prof = []
+    for since in sorted({r[0] for r in rows}):
+        ei = np.concatenate([r[1] for r in rows if r[0] == since])
+        el = np.concatenate([r[2] for r in rows if r[0] == since])
+        prof.append([int(since), float(ei.max()), float(np.median(ei)), float(el.max()), float(np.median(el))])
+    last = prof[-1]
+    return {"steps_since_refresh": last[0], "inverse_max": last[1], "inverse_median": last[2],
+            "logdet_abs_max": last[3], "logdet_abs_median": last[4], "walkers": walkers, "against": against,
+            "profile_columns": ["steps_since_refresh", "inverse_max", "inverse_median", "logdet_abs_max",
+                                "logdet_abs_median"],
+            "profile": prof}
+
+
+def error_profile(run, torch, nsample=16):
+    """Error of the LRU state against the same-GPU FP64 / complex128 recompute at every
+    flush boundary of one eager period of the first sub-batch: steps since its refresh
+    K, 2K, ..., P (the last just before the refresh).  The first sub-batch has offset 0,
+    so after the timed periods it stands right after its refresh."""
+    from paper_2602_05255_amd import lrx
+    wk0 = run.parts[0][0]
+    idx = torch.as_tensor(np.linspace(0, wk0.W - 1, min(nsample, wk0.W)).astype(int), device="cuda")
+    every = run.wl.delay if run.wl.delay else max(1, run.P // 8)
+
+    def one(mode, what):
+        rows = []
+
+        def probe(p, wk, since):
+            if p == 0 and (since % every == 0 or since == run.P):
+                e_inv, e_la = state_error(torch, wk, idx, run.phi, run.wl.kind, run.wl.complex_)
+                rows.append((since, e_inv, e_la))
+        saved = run.drv.mode, run.drv.seed
+        run.drv.mode, run.drv.seed = mode, 0x5EED
+        run.period(probe=probe)
+        run.drv.mode, run.drv.seed = saved
+        torch.cuda.synchronize()
+        return summarize_errors(rows, f"FP64/complex128 full recompute on the same GPU (torch.linalg), {what}, "
+                                      "sampled walkers of one sub-batch at each flush boundary of a period",
+                                len(idx))
+    err = one(lrx.LRX_MH_DEVICE_RNG, "Metropolis chain")
+    err["forced_accept"] = one(lrx.LRX_MH_FORCE, "forced-accept chain")
+    return err
 
 
 def cpu_baseline(wl, seconds):
-    """The oracle (full recompute: LU + inverse per walker-step) on the host cores."""
+    """The oracle (full recompute: LU + inverse per walker-step) on the host cores, on a
+    bounded sample of the workload's walkers (all OpenMP threads of the host)."""
     import oracle as orc
     from paper_2602_05255_amd import inputs as gen
     orc.build(force=False)
-    W = 64
+    if wl.n == 0:      # uneven batch: the same number of sampled walkers from every size class
+        classes, g = gen.uneven_inputs(wl, seed_offset=7)
+        per = 8
+        chains = []
+        for c in classes:
+            chains.append((orc.DetChain(c["phi"], c["occ"][:per], c["empty"][:per]), c["n"]))
+        done, t0 = 0, time.perf_counter()
+        while True:
+            for ch, n in chains:
+                k, e, s = gen.hop_draws(g, per, n, n, wl.ranks, wl.k_max)
+                ch.propose(k, e, s)
+                ch.accept(k, e, s, np.ones(per, bool))
+                done += per
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                break
+        sizes = ",".join(str(n) for _, n in chains)
+        return {"value": done / el, "unit": "walker-steps/s", "cores": orc.num_threads(), "kind": "oracle",
+                "sample": f"{per} walkers from each size class n in {{{sizes}}} x {done // (per * len(chains))} "
+                          f"steps of the {wl.name} workload, k in {list(wl.ranks)}, full FP64 LU + inverse per "
+                          f"walker-step (the class mix of the workload), {el:.1f}s"}
+    W = 64 if wl.n > 64 else wl.walkers
     phi, occ, emp, g = gen.slater_inputs(wl, walkers=W, seed_offset=7)
     chain = orc.DetChain(phi, occ, emp)
     done, t0 = 0, time.perf_counter()
@@ -384,49 +368,129 @@ def cpu_baseline(wl, seconds):
                       f"full FP64 LU + inverse per walker-step, {el:.1f}s"}
 
 
-def recompute(wl, run, torch, reps=5):
-    """Full recompute on the same GPU: gather Phi[occ] + torch.linalg.slogdet (rocSOLVER), FP64."""
-    phi = torch.as_tensor(run.phi).cuda()
-    occ = run.occ.long()
+def recompute(wl, run, torch, reps=3, chunks=(1, 16, 128), sample=128, with_inverse=True):
+    """Full recompute on the same GPU: gather the matrices at the walkers' occupancies, then
+    torch.linalg.slogdet (rocSOLVER LU; for the Pfaffian the skew matrix's |det| = pf^2, a
+    lower bound on any O(n^3) Pfaffian, without the sign), FP64 / complex128.  rocSOLVER's
+    batched LU is timed in batches of each size in `chunks` on the first `sample` walkers and
+    the fastest rate is kept (large batches starve it at large n).  A second figure adds
+    torch.linalg.inv."""
+    wide = torch.complex128 if wl.complex_ else torch.float64
+    src = torch.as_tensor(run.phi).to(device="cuda", dtype=wide)
+    occ = run.occ.long()[:min(sample, run.W)]
+    nw = occ.shape[0]
+    n = wl.n
+
+    def gather(o):
+        return src[o[:, :, None], o[:, None, :]] if wl.kind == "pf" else src[o]
     out = {}
-    chunk = 128     # batched getrf on the whole 1024-matrix batch fails to allocate its workspace
-    for name, fn in (("slogdet", lambda a: torch.linalg.slogdet(a)),
-                     ("slogdet+inv", lambda a: (torch.linalg.slogdet(a), torch.linalg.inv(a)))):
-        def batch():
-            for c0 in range(0, run.W, chunk):
-                fn(phi[occ[c0:c0 + chunk]])
-        try:
-            batch()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
+    variants = [("slogdet", lambda a: torch.linalg.slogdet(a))]
+    if with_inverse:
+        variants.append(("slogdet+inv", lambda a: (torch.linalg.slogdet(a), torch.linalg.inv(a))))
+    for name, fn in variants:
+        best = None
+        for chunk in chunks:
+            if chunk > nw:
+                continue
+
+            def batch():
+                for c0 in range(0, nw - nw % chunk, chunk):
+                    fn(gather(occ[c0:c0 + chunk]))
+            try:
                 batch()
-            torch.cuda.synchronize()
-        except RuntimeError as exc:        # report, do not fail the benchmark line
-            out[name] = {"error": str(exc).splitlines()[0]}
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    batch()
+                torch.cuda.synchronize()
+            except RuntimeError as exc:        # report, do not fail the benchmark line
+                out.setdefault("errors", []).append(f"{name} chunk {chunk}: {str(exc).splitlines()[0]}")
+                continue
+            done = (nw - nw % chunk) * reps
+            rate = done / (time.perf_counter() - t0)
+            if best is None or rate > best[0]:
+                best = (rate, chunk)
+        if best is None:
             continue
-        dt = (time.perf_counter() - t0) / reps
-        n = wl.n
-        flops = run.W * (2 * n ** 3 / 3 + (2 * n ** 3 if "inv" in name else 0))
-        out[name] = {"walker_steps_per_s": run.W / dt, "ms_per_batch": dt * 1e3, "tflops": flops / dt / 1e12}
+        cplx = 4 if wl.complex_ else 1
+        flops = cplx * (2 * n ** 3 / 3 + (2 * n ** 3 if "inv" in name else 0))
+        out[name] = {"walker_steps_per_s": best[0], "batch": best[1], "tflops": best[0] * flops / 1e12,
+                     "walkers_timed": nw}
     return out
 
 
-def bench_secondary(wl, args, torch, dtype):
-    """A secondary workload (e.g. the Pfaffian one): same timing, no CPU/recompute legs."""
-    W = args.walkers or wl.walkers
-    log(f"workload {wl.name}: W={W} n={wl.n} L={wl.sites} K={wl.delay} refresh={wl.refresh}")
-    run, r = measure(wl, dtype, W, args, torch, str(dtype).replace("torch.", ""))
-    err = rel_error(run, torch, np.linspace(0, W - 1, 4).astype(int))
-    log(f"  error vs full recompute: {err}")
-    return {"metric": METRIC, "value": r["value"], "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": str(dtype).replace("torch.", ""), "data": "synthetic",
-            "config": {"workload": wl.name, "walkers": W, "n": wl.n, "sites": wl.sites, "delay": wl.delay,
-                       "refresh_every": wl.refresh, "mode": "forced-accept",
-                       "streams": args.streams},
-            "accept_avg_us": r["accept_avg_us"], "accept_gbs": r["accept_gbs"], "refresh_ms": r["refresh_ms"],
-            "flush": r["flush"], "rel_error": err}
+def with_steps(args, steps, warmup):
+    a = argparse.Namespace(**vars(args))
+    a.steps, a.warmup = steps, warmup
+    return a
+
+
+def bench_uniform(wl, dtype, args, torch, label, walkers=None, streams=None, recompute_leg=False):
+    """A uniform-n determinant or Pfaffian workload: timed periods (one HIP graph each), the
+    accept roofline, the flush and refresh times, the error profile against the same-GPU
+    recompute, and optionally the full recompute comparator."""
+    W = walkers or args.walkers or wl.walkers
+    a = argparse.Namespace(**vars(args))
+    a.streams = streams if streams is not None else a.streams
+    log(f"workload {wl.name} [{label}]: W={W} n={wl.n} L={wl.sites} ranks={wl.ranks} K={wl.delay} "
+        f"refresh={wl.refresh} streams={a.streams}")
+    run, r = measure(wl, dtype, W, a, torch, label)
+    err = error_profile(run, torch)
+    log(f"  [{label}] error vs recompute before refresh: inverse max {err['inverse_max']:.2e} median "
+        f"{err['inverse_median']:.2e}; log|value| max {err['logdet_abs_max']:.2e}")
+    out = {"value": r["value"], "unit": "walker-steps/s", "ms_per_period": r["ms_per_step"],
+           "steps_per_period": run.P, "walkers": W, "streams": a.streams, "dtype": label,
+           "accept": {"avg_us": r["accept_avg_us"], "gbs": r["accept_gbs"], "hbm_frac": r["accept_gbs"] / HBM_PEAK_GBS,
+                      "bytes_per_launch": r["accept_bytes_per_launch"]},
+           "flush": r["flush"], "refresh_ms": r["refresh_ms"], "rel_error": err}
+    if recompute_leg:
+        out["recompute"] = recompute(wl, run, torch)
+        rs = out["recompute"].get("slogdet", {}).get("walker_steps_per_s")
+        out["speedup_vs_recompute"] = r["value"] / rs if rs else None
+        if wl.refresh:
+            own = run.parts[0][2] / (r["refresh_ms"] * 1e-3)    # walkers of one sub-batch per refresh
+            out["recompute_own_refresh"] = {"walker_steps_per_s": own,
+                                            "what": "this library's FP64/complex128 refresh of one sub-batch "
+                                                    "(log|value| + inverse), timed alone"}
+            out["speedup_vs_own_refresh"] = r["value"] / own
+    del run
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_plain_chain(wl, args, torch):
+    """The plain Sherman-Morrison chain (16 walkers, n = 32, FP64, K = 0): latency bound, so
+    the figure is microseconds per Markov-chain step of the whole batch."""
+    a = with_steps(args, max(3, args.steps // 4), 2)
+    a.streams = 1
+    run, r = measure(wl, torch.float64, wl.walkers, a, torch, "f64 plain")
+    err = error_profile(run, torch)
+    out = {"us_per_step": r["ms_per_step"] * 1e3 / run.P, "walker_steps_per_s": r["value"],
+           "walkers": wl.walkers, "steps_per_graph": run.P, "rel_error": err}
+    log(f"  [plain n=32] {out['us_per_step']:.2f} us per step of 16 walkers")
+    return out
+
+
+def bench_single_hop(n, args, torch, walkers=1024):
+    """Single-hop (k = 1) determinant LRU at one n against full recompute on the same GPU:
+    the delayed LRU in FP64 and with FP32 bulk (FP64 refresh every 128 steps amortised), the
+    library's own FP64 Gauss-Jordan refresh (log|det| + inverse), and rocSOLVER slogdet at
+    its best batch size."""
+    from paper_2602_05255_amd import inputs as gen
+    wn = gen.nsweep_workload(n)
+    a = with_steps(args, max(2, args.steps // 8), 1)
+    a.streams = 1
+    r64 = bench_uniform(wn, torch.float64, a, torch, f"f64 n={n}", walkers=walkers, streams=1, recompute_leg=True)
+    r32 = bench_uniform(wn, torch.float32, a, torch, f"f32 n={n}", walkers=walkers, streams=1)
+    own = r64["recompute_own_refresh"]["walker_steps_per_s"]
+    rs = r64["recompute"].get("slogdet", {}).get("walker_steps_per_s")
+    out = {"n": n, "walkers": walkers, "delay": wn.delay, "lru_f64": r64, "lru_f32_bulk": r32,
+           "speedup_f64_vs_own_gj": r64["value"] / own, "speedup_f32_bulk_vs_own_gj": r32["value"] / own,
+           "speedup_f64_vs_rocsolver": r64["value"] / rs if rs else None,
+           "speedup_f32_bulk_vs_rocsolver": r32["value"] / rs if rs else None}
+    log(f"  n={n}: LRU f64 {r64['value']:.4g}/s, f32 bulk {r32['value']:.4g}/s; own GJ {own:.4g}/s; "
+        f"rocSOLVER {rs if rs else float('nan'):.4g}/s")
+    return out
 
 
 def bench_adjoint(wl, args, torch):
@@ -465,66 +529,95 @@ def bench_adjoint(wl, args, torch):
 
 
 def bench_uneven(wl, args, torch):
-    """Uneven batch: every size class advanced by one persistent launch per window
-    of K steps; one benchmark step is one refresh period (P / K windows, then the
-    FP64 refresh of every class)."""
+    """Uneven batch (4096 walkers, n in {64..1024}, FP32 bulk): one benchmark step is one
+    refresh period (128 Markov-chain steps of every walker and the FP64 refresh of every
+    class), replayed as one HIP graph.  Each size class runs on the schedule the
+    autotuner measured fastest for it: the persistent window kernel (windows of 16
+    steps, one launch for all such classes, on a side stream) or per-step launches
+    (four sub-batches on their own streams with staggered refreshes)."""
+    from paper_2602_05255_amd import autotune
     from paper_2602_05255_amd import inputs as gen
     from paper_2602_05255_amd import lrx
-    from paper_2602_05255_amd.uneven import UnevenWalkers
+    from paper_2602_05255_amd.uneven import UnevenBatch
     classes, g = gen.uneven_inputs(wl, walkers=args.walkers or None)
     K, P = wl.delay, wl.refresh
-    nwin = P // K
     t0 = time.time()
-    from paper_2602_05255_amd import autotune
     log(f"  autotune cache {autotune.cache_path()}")
-    uw = UnevenWalkers(torch.float32, classes, wl.k_max, "auto", K, ranks=wl.ranks)
-    gt = gen.generator(gen.SEED_BASE + 11)    # draws for the grid search only
-    uw.set_draws([gen.hop_draws_batch(gt, K, p.st.walkers, c["n"], c["n"], wl.ranks, wl.k_max)
-                  for c, p in zip(classes, uw.parts)])
-    autotune.tune_grid(uw)
-    big = []
-    for c, p in zip(classes, uw.parts):
-        k, e, s = gen.hop_draws_batch(g, P, len(c["walkers"]), c["n"], c["n"], wl.ranks, wl.k_max)
-        big.append(tuple(torch.as_tensor(x).cuda() for x in (k, e, s)))
-    log(f"  setup {time.time() - t0:.1f}s; classes " +
-        ", ".join(f"n={p.st.n}:W={p.st.walkers}:K={p.st.delay}" for p in uw.parts) + f"; grid {uw.grid}")
-
-    def window(i):
-        for p, (k, e, s) in zip(uw.parts, big):
-            p.k, p.elec, p.slot = k[i * K:(i + 1) * K], e[i * K:(i + 1) * K], s[i * K:(i + 1) * K]
-        lrx.lrx_det_window(uw.parts, K, lrx.LRX_MH_FORCE, 0, i * K, uw.order, uw.queue, uw.grid)
-
-    def period():
-        for i in range(nwin):
-            window(i)
-        uw.refresh(report=False)
-
-    # eager pass with events around every window launch and the refresh
-    period()
+    plan = [autotune.tune_class(torch.float32, c["n"], wl.k_max, wl.ranks) for c in classes]
+    t_tune = time.time() - t0
+    draws = []
+    for c in classes:
+        k, e, s_ = gen.hop_draws_batch(g, P, len(c["walkers"]), c["n"], c["n"], wl.ranks, wl.k_max)
+        draws.append(tuple(torch.as_tensor(x).cuda() for x in (k, e, s_)))
+    batch = UnevenBatch(torch.float32, classes, wl.k_max, plan, K, P, draws, substreams=4)
+    if batch.uw is not None:
+        autotune.tune_grid(batch.uw)
+    batch.prime()
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nwin + 2)]
-    ev[0].record()
-    for i in range(nwin):
-        window(i)
-        ev[i + 1].record()
-    uw.refresh(report=False)
-    ev[-1].record()
+    log(f"  setup {time.time() - t0:.1f}s (autotune {t_tune:.1f}s); plan " +
+        ", ".join(f"n={c['n']}:W={len(c['walkers'])}:K={p['delay']}:" +
+                  ("window" if p["window"] else f"steps/rows={p['rows_per_block'] or 'auto'}")
+                  for c, p in zip(classes, plan)) +
+        (f"; window grid {batch.uw.grid}" if batch.uw is not None else ""))
+    # roofline pass: every launch of one period of each per-step class timed alone with
+    # HIP events (queue filler ahead so that no event pair brackets host time); window
+    # launches of the window classes timed the same way
+    per_class = {}
+    es = 4
+    kbar = float(np.mean(wl.ranks))
+    for i, d in zip(batch.step_idx, batch.drivers):
+        n = classes[i]["n"]
+        wn = gen.Workload(f"uneven_n{n}", "det", 2 * n, n, d.W, wl.ranks, wl.k_max, plan[i]["delay"], P,
+                          False, "f32")
+        queue_filler(torch, 60.0)
+        timer = EventTimer(torch)
+        d.period(timer)
+        res = timer.results()
+        acc = res["accept"]
+        byt = sum(accept_bytes(wn, es, wp, tau) for tau, _, wp in acc)
+        tt = sum(dt for _, dt, _ in acc)
+        fl = res.get("flush", [])
+        per_class[n] = {"schedule": "per-step", "delay": plan[i]["delay"], "rows_per_block": plan[i]["rows_per_block"],
+                        "accept_us": tt / len(acc) * 1e6, "accept_gbs": byt / tt / 1e9,
+                        "accept_bytes_per_launch": byt / len(acc), "accept_total_ms": tt * 1e3,
+                        "propose_total_ms": sum(dt for _, dt, _ in res["propose"]) * 1e3,
+                        "flush_total_ms": sum(dt for _, dt, _ in fl) * 1e3,
+                        "refresh_total_ms": sum(dt for _, dt, _ in res.get("refresh", [])) * 1e3}
+    if batch.uw is not None:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(P // K + 2)]
+        queue_filler(torch, 60.0)
+        ev[0].record()
+        for i in range(P // K):
+            batch._window(i, lrx.LRX_MH_FORCE)
+            ev[i + 1].record()
+        batch.uw.refresh(report=False)
+        ev[-1].record()
+        torch.cuda.synchronize()
+        win = [ev[i].elapsed_time(ev[i + 1]) * 1e-3 for i in range(P // K)]
+        wbytes = 0.0
+        for p in batch.uw.parts:
+            n, Kc = p.st.n, p.st.delay
+            per_step = n * n + n * kbar * (Kc - 1) / 2.0 + 4 * n * kbar
+            wbytes += p.st.walkers * es * (K * per_step + (K / Kc) * (2 * n * n + 2 * n * Kc * kbar))
+        per_class["window_classes"] = {
+            "schedule": "persistent window", "sizes": [int(p.st.n) for p in batch.uw.parts],
+            "delays": [int(p.st.delay) for p in batch.uw.parts], "grid": batch.uw.grid,
+            "window_ms": float(np.mean(win)) * 1e3, "window_gbs": wbytes / float(np.mean(win)) / 1e9,
+            "refresh_ms": ev[P // K].elapsed_time(ev[-1])}
+    # the whole period in one HIP graph
+    s_ = torch.cuda.Stream()
+    s_.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_):
+        batch.period()
+    torch.cuda.current_stream().wait_stream(s_)
     torch.cuda.synchronize()
-    win_s = [ev[i].elapsed_time(ev[i + 1]) * 1e-3 for i in range(nwin)]
-    refresh_s = ev[nwin].elapsed_time(ev[-1]) * 1e-3
     graph = None
     if not args.no_graph:
-        s_ = torch.cuda.Stream()
-        s_.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s_):
-            period()
-        torch.cuda.current_stream().wait_stream(s_)
-        torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            period()
+            batch.period()
         torch.cuda.synchronize()
-    step = graph.replay if graph is not None else period
+    step = graph.replay if graph is not None else batch.period
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -536,91 +629,121 @@ def bench_uneven(wl, args, torch):
     e1.record()
     torch.cuda.synchronize()
     T = max(time.perf_counter() - t0, e0.elapsed_time(e1) * 1e-3)
-    W = uw.walkers
+    W = batch.walkers
     value = W * P * args.steps / T
-    # algorithmic bytes of one window (all proposals applied): per walker and step
-    # read A_0^-1 (n^2) and the live b-slot rows (n kbar tau), u and C (2 n kbar),
-    # write the new slot (2 n kbar); per walker and flush the flush reads and
-    # writes A_0^-1 and reads the Kc kbar live slot columns of a and b.
-    kbar = float(np.mean(wl.ranks))
-    es = 4
-    wbytes = 0.0
-    for p in uw.parts:      # each class with its own (autotuned) delay Kc, flushed K / Kc times per window
-        n, Kc = p.st.n, p.st.delay
-        per_step = n * n + n * kbar * (Kc - 1) / 2.0 + 4 * n * kbar
-        wbytes += p.st.walkers * es * (K * per_step + (K / Kc) * (2 * n * n + 2 * n * Kc * kbar))
-    win = float(np.mean(win_s))
-    log(f"  [uneven f32] {value:.4g} walker-steps/s, {T / args.steps * 1e3:.2f} ms per period; window "
-        f"{win * 1e3:.3f} ms ({wbytes / win / 1e9:.0f} GB/s algorithmic); refresh {refresh_s * 1e3:.1f} ms")
-    return {"metric": METRIC, "value": value, "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+    # error profiles: one eager period each with Metropolis decisions (device generator)
+    # and with forced accept; at every point where a class or sub-batch has an empty
+    # delay window and a multiple of 32 steps since its refresh, 4 sampled walkers
+    # against the same-GPU FP64 recompute
+    def profile(mode, what):
+        rows = []
+
+        def probe(kind, part, since):
+            if since % 32:
+                return
+            parts = part.parts if kind == "window" else [part]
+            for q in parts:
+                Wq = q.st.walkers if kind == "window" else q.W
+                idx = torch.as_tensor(np.linspace(0, Wq - 1, 4).astype(int), device="cuda")
+                a_, b_ = state_error(torch, q, idx, q.table, "det", False)
+                rows.append((since, a_, b_))
+        batch.period(mode, probe)
+        torch.cuda.synchronize()
+        return summarize_errors(rows, f"FP64 full recompute on the same GPU (torch.linalg), {what}, 4 sampled "
+                                      "walkers per class or sub-batch at every 32 steps since its refresh", 4)
+    err = profile(lrx.LRX_MH_DEVICE_RNG, "Metropolis chain")
+    err["forced_accept"] = profile(lrx.LRX_MH_FORCE, "forced-accept chain")
+    dom = max((v for v in per_class.values() if v.get("schedule") == "per-step"),
+              key=lambda v: v["accept_total_ms"], default=None)
+    dom_n = [n for n, v in per_class.items() if v is dom][0] if dom is not None else None
+    log(f"  [uneven f32] {value:.4g} walker-steps/s, {T / args.steps * 1e3:.2f} ms per period; " +
+        "; ".join(f"n={n}: accept {v['accept_gbs']:.0f} GB/s" for n, v in per_class.items() if "accept_gbs" in v))
+    line = {"metric": METRIC, "value": value, "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": T / args.steps * 1e3, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": wl.name, "walkers": W, "sizes": list(wl.extra["sizes"]),
-                       "class_walkers": {int(p.st.n): int(p.st.walkers) for p in uw.parts},
-                       "ranks": list(wl.ranks), "window_steps": K, "refresh_every": P, "mode": "forced-accept",
-                       "delay_per_class": {int(p.st.n): int(p.st.delay) for p in uw.parts},
-                       "delay_and_grid": "autotuned", "graph": graph is not None, "grid": uw.grid},
-            "roofline": {"bound": "hbm", "kernel": "det_window_kernel", "achieved": wbytes / win / 1e9,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": wbytes / win / 1e9 / HBM_PEAK_GBS,
-                         "traffic": None, "avg_us": win * 1e6, "bytes_per_launch": wbytes},
-            "refresh_ms": refresh_s * 1e3}
+                       "class_walkers": {int(c["n"]): len(c["walkers"]) for c in classes},
+                       "ranks": list(wl.ranks), "refresh_every": P, "mc_steps_per_bench_step": P,
+                       "mode": "forced-accept", "bulk": "f32", "refresh": "f64",
+                       "schedule_per_class": {int(c["n"]): ("persistent window" if p["window"] else "per-step")
+                                              for c, p in zip(classes, plan)},
+                       "delay_per_class": {int(c["n"]): p["delay"] for c, p in zip(classes, plan)},
+                       "delay_schedule_and_tiles": "autotuned", "graph": graph is not None,
+                       "substreams_per_step_class": 4, "window_steps": K},
+            "per_class": per_class, "rel_error": err}
+    if dom is not None:
+        line["roofline"] = {"bound": "hbm", "kernel": f"det_accept_kernel (delayed, FP32, n={dom_n})",
+                            "achieved": dom["accept_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": dom["accept_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                            "avg_us": dom["accept_us"], "bytes_per_launch": dom["accept_bytes_per_launch"]}
+    else:
+        wc = per_class["window_classes"]
+        line["roofline"] = {"bound": "hbm", "kernel": "det_window_kernel", "achieved": wc["window_gbs"],
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": wc["window_gbs"] / HBM_PEAK_GBS,
+                            "traffic": None, "avg_us": wc["window_ms"] * 1e3, "bytes_per_launch": None}
+    return line
+
+
+def bench_delay_sweep(args, torch, kinds=("det", "pf")):
+    """Delayed against plain updates (the paper's delay-length benchmark): 16384 walkers,
+    n = 128, 128 consecutive single-hop updates of every walker (forced accept, no refresh),
+    FP64, for each delay K; one HIP graph of the 128 steps per K.  Reports the time per
+    128 updates, the speedup of each delay over the plain update, the fastest K, and the
+    K the library's byte model proposes (lrx_autotune_lookup default)."""
+    from paper_2602_05255_amd import inputs as gen
+    from paper_2602_05255_amd import lrx
+    out = {}
+    for kind in kinds:
+        base = gen.WORKLOADS[f"delay_sweep_n128_{kind}"]
+        W = args.walkers or base.walkers
+        rows = []
+        for K in (0, 2, 4, 8, 16, 32, 64):
+            wl = gen.Workload(base.name, kind, base.sites, base.n, W, base.ranks, base.k_max, K, 0, False, "f64",
+                              steps=base.steps, seed=base.seed)
+            run = Run(wl, torch.float64, W, streams=1)
+            run.capture()
+            for _ in range(2):
+                run.step()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 3
+            e0.record()
+            for _ in range(reps):
+                run.step()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rows.append({"delay": K, "ms_per_128_updates": ms, "walker_steps_per_s": W * wl.steps / (ms * 1e-3)})
+            log(f"  delay sweep {kind} K={K}: {ms:.2f} ms per 128 updates of {W} walkers")
+            del run
+            torch.cuda.empty_cache()
+        plain = rows[0]["ms_per_128_updates"]
+        for r in rows:
+            r["speedup_vs_plain"] = plain / r["ms_per_128_updates"]
+        best = min(rows[1:], key=lambda r: r["ms_per_128_updates"])
+        model = lrx.lrx_autotune_lookup(torch.float64, base.n, 1)["delay"]
+        out[kind] = {"walkers": W, "n": base.n, "updates": base.steps, "dtype": "f64", "rows": rows,
+                     "best_delay": best["delay"], "best_speedup_vs_plain": best["speedup_vs_plain"],
+                     "byte_model_delay": model,
+                     "paper_best_delay": 16 if kind == "det" else 4,
+                     "paper_note": "the paper finds T = 16 (det) and T = 4 (pf) best for 16384 matrices of n = 128 "
+                                   "and reports an additional 20-40 % speedup of delayed over plain updates "
+                                   "(NVIDIA A100-80GB, JAX)"}
+    return out
 
 
 def bench_nsweep(wl, args, torch):
     """Single-hop determinant LRU against full recompute on the same GPU, n = 64 .. 1024
-    (the shape of the paper's speedup-vs-n figure).  Per n: the delayed LRU (K near the
-    byte-model optimum, forced accept, FP64 refresh every 128 steps amortised) in FP64 and
-    FP32 bulk, and torch.linalg.slogdet of the gathered Phi[occ] (rocSOLVER LU) in FP64."""
-    from paper_2602_05255_amd import inputs as gen
+    (the shape of the paper's speedup-vs-n figure), one bench_single_hop per n."""
     sizes = [int(x) for x in args.sizes.split(",")] if args.sizes else list(wl.extra["sizes"])
-    W = args.walkers or wl.walkers
-    rows = []
-    for n in sizes:
-        wn = gen.nsweep_workload(n)
-        log(f"n-sweep n={n}: W={W} L={wn.sites} K={wn.delay} refresh={wn.refresh}")
-        run64, r64 = measure(wn, torch.float64, W, args, torch, f"f64 n={n}")
-        err64 = rel_error(run64, torch, np.linspace(0, W - 1, 4).astype(int))
-        rc = recompute(wn, run64, torch, reps=3)
-        del run64
-        torch.cuda.empty_cache()
-        row = {"n": n, "delay": wn.delay,
-               "lru_f64": r64["value"], "accept_gbs_f64": r64["accept_gbs"],
-               "accept_hbm_frac_f64": r64["accept_gbs"] / HBM_PEAK_GBS, "refresh_ms": r64["refresh_ms"],
-               "rel_error_f64": err64, "recompute": rc}
-        if not args.no_fp32:
-            run32, r32 = measure(wn, torch.float32, W, args, torch, f"f32 n={n}")
-            row["lru_f32"] = r32["value"]
-            row["accept_gbs_f32"] = r32["accept_gbs"]
-            del run32
-            torch.cuda.empty_cache()
-        # this library's own full recompute: the FP64 refresh (gather, Gauss-Jordan inverse
-        # and log|det| of every walker), timed inside the LRU run
-        own = W / (r64["refresh_ms"] * 1e-3)
-        row["recompute_own_gj"] = {"walker_steps_per_s": own, "what": "slogdet + inverse, FP64 Gauss-Jordan refresh"}
-        row["speedup_f64_vs_own_gj"] = r64["value"] / own
-        if "lru_f32" in row:
-            row["speedup_f32_bulk_vs_own_gj"] = row["lru_f32"] / own
-        rs = rc.get("slogdet", {}).get("walker_steps_per_s")
-        if rs:
-            row["speedup_f64"] = r64["value"] / rs
-            row["recompute_tflops"] = rc["slogdet"]["tflops"]
-            row["recompute_fp64_frac"] = rc["slogdet"]["tflops"] / FP64_PEAK_TFS
-            if "lru_f32" in row:
-                row["speedup_f32_bulk"] = row["lru_f32"] / rs
-        log(f"  n={n}: LRU f64 {r64['value']:.4g}/s, recompute rocSOLVER {rs if rs else float('nan'):.4g}/s "
-            f"(speedup {row.get('speedup_f64', float('nan')):.1f}x, f32 bulk {row.get('speedup_f32_bulk', float('nan')):.1f}x), "
-            f"own GJ {own:.4g}/s (speedup {row['speedup_f64_vs_own_gj']:.1f}x, "
-            f"f32 bulk {row.get('speedup_f32_bulk_vs_own_gj', float('nan')):.1f}x)")
-        rows.append(row)
+    rows = [bench_single_hop(n, args, torch, walkers=args.walkers or wl.walkers) for n in sizes]
     top = rows[-1]
-    return {"metric": METRIC, "value": top["lru_f64"], "unit": "walker-steps/s", "n_gpus": 1,
+    return {"metric": METRIC, "value": top["lru_f64"]["value"], "unit": "walker-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": wl.name, "walkers": W, "sizes": sizes, "ranks": [1],
-                       "delay_per_n": {str(r["n"]): r["delay"] for r in rows}, "refresh_every": wl.refresh,
-                       "mode": "forced-accept"},
-            "speedup_vs_recompute_at_largest_n": top.get("speedup_f64"),
-            "speedup_vs_own_gj_recompute_at_largest_n": top.get("speedup_f64_vs_own_gj"), "sweep": rows}
+            "config": {"workload": wl.name, "walkers": args.walkers or wl.walkers, "sizes": sizes, "ranks": [1],
+                       "refresh_every": wl.refresh, "mode": "forced-accept"},
+            "sweep": rows}
 
 
 def copy_calibration(torch, nbytes=1 << 30, reps=5):
@@ -638,6 +761,29 @@ def copy_calibration(torch, nbytes=1 << 30, reps=5):
     torch.cuda.synchronize()
     dt = e0.elapsed_time(e1) * 1e-3 / reps
     return {"copy_bytes": nbytes, "reps": reps + 1, "us": dt * 1e6, "gbs_read_plus_write": 2 * nbytes / dt / 1e9}
+
+
+def headline_line(res, args, extras):
+    """The JSON line: the uneven batch (the largest single-GPU configuration) as the headline,
+    the other configurations as extra keys."""
+    line = {k: res[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+                                "roofline")}
+    line.update({k: v for k, v in extras.items()})
+    return line
+
+
+def run_extra(name, fn):
+    """One secondary configuration; a failure is reported in the line instead of ending the run."""
+    t0 = time.time()
+    try:
+        out = fn()
+    except Exception as exc:       # noqa: BLE001 -- keep the headline line whatever happens here
+        import traceback
+        traceback.print_exc()
+        out = {"error": f"{type(exc).__name__}: {exc}"}
+    log(f"  [{name}] done in {time.time() - t0:.1f}s")
+    return out
 
 
 def main():
@@ -661,60 +807,47 @@ def main():
     if wl.name == "logpsi_grad_n512_c64":
         print(json.dumps(bench_adjoint(wl, args, torch)), flush=True)
         return
-    if wl.kind == "pf":
-        print(json.dumps(bench_secondary(wl, args, torch, torch.complex64)), flush=True)
-        return
-    if wl.name == "uneven_n64_1024_fp32":
-        print(json.dumps(bench_uneven(wl, args, torch)), flush=True)
-        return
     if wl.name == "nsweep_det_k1":
         print(json.dumps(bench_nsweep(wl, args, torch)), flush=True)
         return
-    assert wl.kind == "det" and wl.n > 0, "the default benchmark drives a uniform-n determinant workload"
-    W = args.walkers or wl.walkers
-    log(f"workload {wl.name}: W={W} n={wl.n} L={wl.sites} ranks={wl.ranks} K={wl.delay} refresh={wl.refresh}")
+    if wl.name.startswith("delay_sweep_n128"):
+        print(json.dumps({"workload": "delay_sweep_n128", **bench_delay_sweep(args, torch, (wl.kind,))}), flush=True)
+        return
+    if wl.name != "uneven_n64_1024_fp32":
+        # one uniform workload on its own
+        dt = {"f64": torch.float64, "f32": torch.float32, "c64": torch.complex64,
+              "c128": torch.complex128}[wl.bulk]
+        if wl.name == "slater_n32_fp64":
+            print(json.dumps({"workload": wl.name, **bench_plain_chain(wl, args, torch)}), flush=True)
+            return
+        r = bench_uniform(wl, dt, args, torch, wl.bulk, recompute_leg=not args.no_recompute)
+        print(json.dumps({"metric": METRIC, "workload": wl.name, **r}), flush=True)
+        return
 
-    run64, r64 = measure(wl, torch.float64, W, args, torch, "f64")
-    sample = np.linspace(0, W - 1, 8).astype(int)
-    err64 = rel_error(run64, torch, sample)
-    log(f"  f64 error vs full recompute: {err64}")
-    rc = None if args.no_recompute else recompute(wl, run64, torch)
-    del run64
+    # Default: the uneven batch is the headline; every other configuration rides along.
+    t_start = time.time()
+    res = bench_uneven(wl, args, torch)
     torch.cuda.empty_cache()
-    fp32 = None
-    if not args.no_fp32:
-        run32, r32 = measure(wl, torch.float32, W, args, torch, "f32")
-        err32 = rel_error(run32, torch, sample)
-        log(f"  f32 error vs full recompute: {err32}")
-        fp32 = {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "rel_error": err32,
-                "accept_gbs": r32["accept_gbs"], "refresh_ms": r32["refresh_ms"]}
-        del run32
-    cpu = None if args.no_cpu else cpu_baseline(wl, args.cpu_seconds)
-
-    achieved = r64["accept_gbs"]
-    line = {
-        "metric": METRIC, "value": r64["value"], "unit": "walker-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "walkers": W, "n": wl.n, "sites": wl.sites, "ranks": list(wl.ranks),
-                   "delay": wl.delay, "refresh_every": wl.refresh, "mc_steps_per_bench_step": wl.refresh,
-                   "mode": "forced-accept", "graph": not args.no_graph, "streams": args.streams},
-        "roofline": {"bound": "hbm", "kernel": "det_accept_kernel (delayed)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic("det_accept_kernel_slater_n256_k124_counters.md", DET_SOURCES,
-                                                W // max(1, args.streams)),
-                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "avg_us": r64["accept_avg_us"], "bytes_per_launch": r64["accept_bytes_per_launch"]},
-        "cpu_baseline": cpu,
-        "rel_error": err64,
-        "recompute": rc,
-        "speedup_vs_recompute": (r64["value"] / rc["slogdet"]["walker_steps_per_s"])
-        if rc and "walker_steps_per_s" in rc.get("slogdet", {}) else None,
-        "flush": r64["flush"], "refresh_ms": r64["refresh_ms"],
-        "fp32": fp32,
-    }
-    print(json.dumps(line), flush=True)
+    extras = {"rel_error": res["rel_error"], "per_class": res["per_class"]}
+    short = with_steps(args, max(3, args.steps // 4), max(1, min(args.warmup, 2)))
+    c2 = gen.WORKLOADS["slater_n256_k124"]
+    cfg = {}
+    cfg["slater_n256_k124"] = run_extra("slater_n256_k124", lambda: {
+        "f64": bench_uniform(c2, torch.float64, short, torch, "f64", streams=4, recompute_leg=not args.no_recompute),
+        "f32": bench_uniform(c2, torch.float32, short, torch, "f32", streams=4)})
+    c3 = gen.WORKLOADS["pfaffian_n512_c64"]
+    cfg["pfaffian_n512_c64"] = run_extra("pfaffian_n512_c64", lambda: bench_uniform(
+        c3, torch.complex64, short, torch, "c64", streams=4, recompute_leg=not args.no_recompute))
+    cfg["single_hop_n1024"] = run_extra("single_hop_n1024", lambda: bench_single_hop(1024, args, torch))
+    cfg["delay_sweep_n128"] = run_extra("delay_sweep_n128", lambda: bench_delay_sweep(short, torch))
+    cfg["slater_n32_fp64"] = run_extra("slater_n32_fp64", lambda: bench_plain_chain(
+        gen.WORKLOADS["slater_n32_fp64"], args, torch))
+    cfg["logpsi_grad_n512_c64"] = run_extra("logpsi_grad_n512_c64", lambda: bench_adjoint(
+        gen.WORKLOADS["logpsi_grad_n512_c64"], short, torch))
+    extras["configs"] = cfg
+    extras["cpu_baseline"] = None if args.no_cpu else cpu_baseline(wl, args.cpu_seconds)
+    extras["bench_wall_s"] = time.time() - t_start
+    print(json.dumps(headline_line(res, args, extras)), flush=True)
 
 
 if __name__ == "__main__":

@@ -259,6 +259,9 @@ int lrx_det_flush_delayed(lrx_state *st, void *stream);
 /* Uneven batches: one launch for a window of delayed steps                  */
 /* ------------------------------------------------------------------------ */
 
+/* Largest number of steps in one lrx_det_window call. */
+#define LRX_MAX_WINDOW_STEPS 256
+
 /* One size class of an uneven batch (all walkers of a class share n). */
 typedef struct lrx_window_class {
     lrx_state *state;       /* DET state of the class: real bulk dtype, delay K >= 1;
@@ -277,14 +280,8 @@ typedef struct lrx_window_class {
                                for LRX_MH_MASK, out otherwise)                       */
 } lrx_window_class;
 
-/*
- * Work order of a window (host only): the (class, walker) pairs of all classes,
- * heaviest first (n^2 descending, then class, then walker), written to
- * order[2*i], order[2*i+1].  Returns the number of pairs in *count.
- *   capacity: pairs that fit in order (LRX_EINVAL if fewer than the walkers).
- */
-int lrx_window_plan(const lrx_window_class *classes, int32_t n_classes,
-                    int32_t *order, int32_t capacity, int32_t *count);
+/* Device workspace bytes of lrx_det_window (host only): its work counter, 256-byte rounded. */
+int lrx_window_work_bytes(const lrx_window_class *classes, int32_t n_classes, size_t *out);
 
 /*
  * Advance every walker of every class by `steps` Markov-chain steps in one
@@ -296,52 +293,102 @@ int lrx_window_plan(const lrx_window_class *classes, int32_t n_classes,
  * whenever a class's slot reaches K the flush M0 -= sum_t b_t a_t^T
  * (Eq. delayed_Ainv) of that walker.  Results equal the sequence of per-step
  * calls (propose_hop, accept_hop, flush_delayed) up to rounding.
- *   order: device int32 [n_items][2] from lrx_window_plan (copied to the device);
- *   queue: device uint32 [1] work counter (reset by the call);
+ * Walkers are handed out heaviest first (classes by n descending) from a work
+ * counter in `work` to `grid` persistent work-groups; a work-group keeps its
+ * walker for the whole window (its flush runs as 64-column MFMA strips).
+ *   work: device workspace of lrx_window_work_bytes bytes (cleared by the call;
+ *         calls sharing a workspace must not overlap);
  *   grid: work-groups of the persistent launch (a few per compute unit);
  *   seed, counter: generator key and step-0 counter (LRX_MH_DEVICE_RNG); the
  *   key's walker index is the walker's position in the class list (class 0
  *   first), and step t uses counter + t.
- * All classes must share the bulk dtype (FP32 or FP64) and k_max.  The refresh
- * of each class stays a separate lrx_det_refresh call.
+ * All classes must share the bulk dtype (FP32 or FP64) and k_max; steps is
+ * 1..LRX_MAX_WINDOW_STEPS.  The refresh of each class stays a separate
+ * lrx_det_refresh call.
  */
 int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps,
                    int32_t mode, uint64_t seed, uint64_t counter,
-                   const int32_t *order, int32_t n_items, uint32_t *queue,
-                   int32_t grid, void *stream);
+                   void *work, size_t work_bytes, int32_t grid, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tuning table                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Launch parameters of one (bulk dtype, n, k_max) size class. */
+typedef struct lrx_tune {
+    int32_t delay;          /* delay K (window length between flushes, Sec. II.C)        */
+    int32_t rows_per_block; /* rows of M per work-group of the per-step accept kernels
+                               (0: the library's heuristic; the accept launches use a
+                               stored value >= 16)                                        */
+    int32_t wgs_per_cu;     /* persistent work-groups per compute unit (0: not stored)   */
+    int32_t window;         /* schedule: 1 = the persistent lrx_det_window launch,
+                               0 = per-step launches (propose_hop / accept_hop / flush)   */
+    int32_t tuned;          /* out: 1 = stored by lrx_autotune_store, 0 = default        */
+    int32_t reserved;
+} lrx_tune;
+
+/*
+ * Record measured launch parameters for a size class in the library's
+ * process-wide table (host only, thread-safe; a later store replaces an
+ * earlier one).  The table lives in host memory for the life of the process.
+ * Returns LRX_ESHAPE / LRX_EINVAL for a bad key or values (delay 1..LRX_MAX_DELAY
+ * with delay * k_max <= 256, rows_per_block >= 16 or 0, wgs_per_cu 0..16,
+ * window 0 or 1).  The per-step accept launches of the library read
+ * rows_per_block from this table.
+ */
+int lrx_autotune_store(int32_t dtype, int32_t n, int32_t k_max, const lrx_tune *t);
+
+/*
+ * Launch parameters for a size class (host only): the stored entry if there is
+ * one (out->tuned = 1), otherwise the byte-model default (out->tuned = 0): the
+ * delay K that minimises the bytes per step of the delayed form, the power of
+ * two nearest sqrt(2 n / kbar) with kbar = (k_max + 1) / 2 (Sec. II.C moves
+ * n^2 + n kbar tau bytes per accept and 2 n^2 per flush), the library's
+ * accept heuristic (rows_per_block 0), two work-groups per compute unit, and
+ * the persistent window below n = 512 (per-step launches from n = 512 on).
+ */
+int lrx_autotune_lookup(int32_t dtype, int32_t n, int32_t k_max, lrx_tune *out);
 
 /* ------------------------------------------------------------------------ */
 /* Low-rank log-determinant and its adjoint                                  */
 /* ------------------------------------------------------------------------ */
 
 /*
- * log det M_w for M_w = A_w + B_w C_w^T, with A_w^-T the state's inverse
- * (flushed: st->slot == 0, else LRX_ENEEDFLUSH).  By the matrix determinant
- * lemma (Sec. II.A with dense u = C, v = B):
+ * log det M_w for M_w = A_w + B_w C_w^T, with A_w^-T the state's inverse used
+ * as it stands: flushed (st->slot == 0) or in the delayed form of Sec. II.C,
+ * A^-T = M0 - sum_{t < slot} b_t a_t^T (Eq. delayed_Ainv), whose slot terms
+ * enter P and Q through O(n slot r) products without flushing (the state is
+ * the checkpoint of the forward pass; it must not change before the backward).
+ * By the matrix determinant lemma (Sec. II.A with dense u = C, v = B):
  *   log det M = log det A + log det R,  R = I_r + C^T P,  P = A^-1 B,
- * computed in one pass over A^-T per walker.
+ * computed in one pass over M0 per walker.
  *   r: rank, 1..8.  B, C: bulk [W][n][r].  P, Q (= A^-T C): bulk [W][n][r] out;
  *   Rinv: bulk [W][r][r] out; logabs: double [W] out; phase: wide [W] out
  *   (zero phase and -inf logabs when R is singular).
+ * LRX_ENEEDFLUSH when the delay window is full (st->slot == K).
  */
 int lrx_det_lowrank_fwd(const lrx_state *st, int32_t r, const void *B, const void *C,
                         void *P, void *Q, void *Rinv, double *logabs, void *phase,
                         void *stream);
 
-/* Workspace bytes of lrx_det_lowrank_bwd (host only). */
+/* Workspace bytes of lrx_det_lowrank_bwd for a shape (host only; covers any slot). */
 int lrx_det_lowrank_work_bytes(const lrx_shape *shape, int32_t r, int32_t sites, size_t *out);
 
 /*
- * Adjoint of lrx_det_lowrank_fwd.  g: wide [W], the cotangent of log det M_w in
- * torch's convention (gradients of a real loss are returned conjugate-weighted).
- * With M^-T = A^-T - Q R^-T P^T (Woodbury, Eq. det_inv):
+ * Adjoint of lrx_det_lowrank_fwd (same state, same st->slot).  g: wide [W], the
+ * cotangent of log det M_w in torch's convention (gradients of a real loss are
+ * returned conjugate-weighted).  With M^-T = A^-T - Q R^-T P^T (Woodbury,
+ * Eq. det_inv):
  *   dB   = g conj(M^-T C) = g conj(Q R^-T)          bulk [W][n][r]
  *   dC   = g conj(M^-1 B) = g conj(P R^-1)          bulk [W][n][r]
  *   dphi[s][:] = sum over (w, i) with occ[w][i] = s of g_w conj(M_w^-T[i][:])
  *                                                   bulk [sites][n] (overwritten)
  * (the gradient with respect to the orbital matrix through A_w = phi[occ_w]).
- * The first term of dphi is gathered site by site; the correction
- * sum g conj(Q R^-T P^T) is one dense GEMM on MFMA with inner dimension W r.
+ * The first term of dphi is gathered site by site from M0; the low-rank terms
+ * (Q R^-T P^T and, in the delayed form, the slot terms b_t a_t^T) form one dense
+ * product on MFMA with inner dimension W (r + slot k_max).  Every sum runs in a
+ * fixed order, so the results are bitwise reproducible.
+ *   occ: int32 [W][n] distinct sites in 0..sites-1;
  *   work: device workspace of lrx_det_lowrank_work_bytes bytes.
  */
 int lrx_det_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int32_t sites,
@@ -439,6 +486,44 @@ int lrx_pf_accept_hop(lrx_state *st, const int32_t *k, const int32_t *cols,
  * sets st->slot = 0.
  */
 int lrx_pf_flush_delayed(lrx_state *st, void *stream);
+
+/*
+ * log pf M_w for M_w = A_w - U_w J U_w^T (Sec. III.A: the general low-rank
+ * update of a skew matrix, J the 2k x 2k skew identity) with A_w^-1 the
+ * Pfaffian state's inverse as it stands (flushed or in the delayed form
+ * A^-1 = M0 + sum_t a_t R_t^-1 a_t^T, Eq. pf_delayed_Ainv):
+ *   log pf M = log pf A + log pf R - log pf J,  R = J + U^T P,  P = A^-1 U
+ * (Eqs. pf_ratio, pf_R; pf J = (-1)^(k(k-1)/2)); R is made exactly skew and its
+ * Pfaffian taken by Parlett-Reid.
+ *   r: columns of U (= 2k), even, 2..8.  U: bulk [W][n][r].  P: bulk [W][n][r]
+ *   out; Rinv: bulk [W][r][r] out; logabs: double [W]; phase: wide [W] out.
+ */
+int lrx_pf_lowrank_fwd(const lrx_state *st, int32_t r, const void *U, void *P, void *Rinv,
+                       double *logabs, void *phase, void *stream);
+
+/* Workspace bytes of lrx_pf_lowrank_bwd for a shape (host only). */
+int lrx_pf_lowrank_work_bytes(const lrx_shape *shape, int32_t r, int32_t sites, size_t *out);
+
+/*
+ * Adjoint of lrx_pf_lowrank_fwd.  With d log pf M / dM_ij = (1/2) (M^-1)_ji
+ * (Appendix A, Eq. pf_grad) and M^-1 = A^-1 + P R^-1 P^T (Eq. pf_inv):
+ *   dU = g conj(P R^-1)                              bulk [W][n][r]
+ *   dF[a][b] = -(1/2) sum over walkers w with sites a = occ[w][i], b = occ[w][j]
+ *              of g_w conj(M_w^-1[i][j])              bulk [sites][sites] (overwritten)
+ * (the gradient with respect to the pairing matrix through A_w = F[occ_w][:, occ_w]).
+ * Fixed summation order (bitwise reproducible).
+ */
+int lrx_pf_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int32_t sites,
+                       const void *P, const void *Rinv, const void *g, void *dF, void *dU,
+                       void *work, size_t work_bytes, void *stream);
+
+/*
+ * Gradient of log pf A for a flushed Pfaffian state (the standalone pf /
+ * slogpf operation: lrx_pf_init_inverse of a dense skew batch, then this):
+ *   dA[w][i][j] = g_w conj((1/2) (A_w^-1)_ji)   (Appendix A, Eq. pf_grad)
+ *   g: wide [W] cotangent of log pf; dA: bulk [W][n][n] out.
+ */
+int lrx_pf_grad(const lrx_state *st, const void *g, void *dA, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Markov-chain helpers                                                     */

@@ -262,6 +262,46 @@ def lowrank_logdet_and_grads(phi, occ, b, c):
     return la, ph, g, g @ np.asarray(c), inv @ np.asarray(b)
 
 
+def skew_eye(k):
+    """The 2k x 2k skew identity J = [[0, 1], [-1, 0]] (blocks of size k) of Sec. III.A."""
+    j = np.zeros((2 * k, 2 * k))
+    j[:k, k:] = np.eye(k)
+    j[k:, :k] = -np.eye(k)
+    return j
+
+
+def lowrank_logpf_and_grads(f, occ, u):
+    """log pf M_s for M_s = F[occ_s][:, occ_s] - U_s J U_s^T (the low-rank skew update of
+    Sec. III.A) and its holomorphic gradients.
+
+    Returns (logabs[S], phase[S], G[S][n][n], GU[S][n][2k]) with G = d log pf M / dM,
+    G_ij = (1/2) (M^-1)_ji (Appendix A, Eq. pf_grad), and GU = d log pf M / dU by the
+    chain rule through M_kl = A_kl - sum_cd U_kc J_cd U_ld:
+    GU = -(G U J^T) - (G^T U J).  Every quantity comes from a fresh Parlett-Reid
+    Pfaffian and LU inverse of M.
+    """
+    u = np.asarray(u)
+    k = u.shape[-1] // 2
+    jm = skew_eye(k)
+    m = pairing_matrices(f, occ) - u @ jm @ np.swapaxes(u, -1, -2)
+    la, ph = slogpf(m)
+    _, _, inv = slogdet(m)
+    g = 0.5 * np.swapaxes(inv, -1, -2)
+    gu = -(g @ u @ jm.T) - (np.swapaxes(g, -1, -2) @ u @ jm)
+    return la, ph, g, gu
+
+
+def scatter_pairs(g, occ, n_sites):
+    """dF[a][b] = sum over (walker, i, j with occ_i = a, occ_j = b) of G[w][i][j] (adjoint of
+    the gather A[w][i][j] = F[occ[w][i]][occ[w][j]])."""
+    g = np.asarray(g)
+    occ = np.asarray(occ)
+    out = np.zeros((n_sites, n_sites), dtype=g.dtype)
+    for w in range(occ.shape[0]):
+        out[np.ix_(occ[w], occ[w])] += g[w]
+    return out
+
+
 def scatter_rows(g, occ, n_sites):
     """dPhi[s] = sum over (walker, electron i with occ = s) of G[w][i] (adjoint of the gather)."""
     g = np.asarray(g)

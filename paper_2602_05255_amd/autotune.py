@@ -2,8 +2,11 @@
 
 Picks, per (device, bulk dtype, n, k_max), the delay K of a size class (the
 window length between flushes: longer windows move fewer bytes in the flush
-but make every accept read more slot rows, Sec. II.C), and per batch the
-number of work-groups of the persistent launch.  Candidates are timed on the
+but make every accept read more slot rows, Sec. II.C), its schedule (the
+persistent window kernel, one work-group per walker, or per-step launches that
+spread a walker over several work-groups) and, for per-step launches, the
+accept tile height (rows of M per work-group); and per batch the number of
+work-groups of the persistent launch.  Candidates are timed on the
 device with the real kernels (HIP events around whole windows, all proposals
 applied) and the winners are cached in a JSON file keyed by the device name,
 so a process tunes a shape once.
@@ -60,43 +63,96 @@ def delay_candidates(n, k_max, ranks):
 
 
 def _time_windows(uw, reps):
-    """Seconds per walker-step over `reps` windows (forced accept, refresh excluded)."""
-    uw.window(mode=lrx.LRX_MH_FORCE, counter=0)      # warm-up
+    """Seconds per walker-step over `reps` windows (forced accept, refresh excluded).  The
+    windows are launched directly (not through uw.window), so the batch's window count and
+    refresh schedule are left alone."""
+    lrx.lrx_det_window(uw.parts, uw.steps, lrx.LRX_MH_FORCE, 0, 0, uw.work, uw.grid)      # warm-up
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for r in range(reps):
-        lrx.lrx_det_window(uw.parts, uw.steps, lrx.LRX_MH_FORCE, 0, (r + 1) * uw.steps, uw.order, uw.queue,
-                           uw.grid)
+        lrx.lrx_det_window(uw.parts, uw.steps, lrx.LRX_MH_FORCE, 0, (r + 1) * uw.steps, uw.work, uw.grid)
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) * 1e-3 / (reps * uw.steps * uw.walkers)
 
 
-def tune_delay(dtype, n, k_max, ranks, walkers=512, device="cuda", cache=None, seed=7):
-    """Best delay K for one size class (cached)."""
+def rows_candidates(n):
+    """Accept work-group heights tried for the per-step schedule: the library's heuristic (0)
+    and 128, 256, 512 rows below n."""
+    return [0] + [r for r in (128, 256, 512) if r < n]
+
+
+def _time_steps(wk, draws, steps, reps):
+    """Seconds per walker-step of the per-step schedule (propose_hop, accept_hop, flush;
+    forced accept) over `reps` passes of `steps` steps."""
+    k, e, s = draws
+
+    def one_pass():
+        for t in range(steps):
+            lrx.lrx_det_propose_hop(wk.st, wk.table, wk.sites, wk.occ, wk.empty, wk.n_empty, k[t], e[t], s[t],
+                                    wk.u, wk.ratio)
+            lrx.lrx_det_accept_hop(wk.st, k[t], e[t], s[t], wk.u, lrx.LRX_MH_FORCE, None, 0, t, wk.accept, wk.occ,
+                                   wk.empty, wk.n_empty)
+            if wk.st.slot == wk.delay:
+                wk.flush()
+    one_pass()                                        # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        one_pass()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / (reps * steps * wk.W)
+
+
+def tune_class(dtype, n, k_max, ranks, walkers=512, device="cuda", cache=None, seed=7):
+    """Schedule of one size class, timed on the device: the delay K, and either the
+    persistent window kernel (one work-group per walker for the whole window) or per-step
+    launches with the accept work-group height (rows of M per work-group) that ran
+    fastest.  Cached in JSON and registered with the library's tuning table
+    (lrx_autotune_store), which the per-step accept launches read."""
     from .uneven import UnevenWalkers
+    from .walkers import Walkers
     path = cache or cache_path()
     table = _load(path)
-    key = f"{_device_key(device)}|{str(dtype).replace('torch.', '')}|n={n}|kmax={k_max}|ranks={list(ranks)}"
-    if key in table and "delay" in table[key]:
-        return int(table[key]["delay"])
+    dname = str(dtype).replace("torch.", "")
+    key = f"{_device_key(device)}|{dname}|n={n}|kmax={k_max}|ranks={list(ranks)}|v2"
+    hit = table.get(key, {})
+    if all(f in hit for f in ("delay", "rows_per_block", "window")):
+        out = {"delay": int(hit["delay"]), "rows_per_block": int(hit["rows_per_block"]), "window": bool(hit["window"])}
+        lrx.lrx_autotune_store(dtype, n, k_max, out["delay"], out["rows_per_block"], 0, out["window"])
+        return out
     g = gen.generator(gen.SEED_BASE + seed)
     phi = gen.normal(g, (2 * n, n))
     occ, emp = gen.occupancy(g, walkers, 2 * n, n)
     results = {}
     for K in delay_candidates(n, k_max, ranks):
+        kk, ee, ss = gen.hop_draws_batch(g, 2 * K, walkers, n, n, ranks, k_max)
         uw = UnevenWalkers(dtype, [{"phi": phi, "occ": occ, "empty": emp}], k_max, [K], 2 * K, device=device)
-        k, e, s = gen.hop_draws_batch(g, 2 * K, walkers, n, n, ranks, k_max)
-        uw.set_draws([(k, e, s)])
-        results[K] = _time_windows(uw, reps=3)
+        uw.set_draws([(kk, ee, ss)])
+        results[("window", K, 0)] = _time_windows(uw, reps=2)
         del uw
+        wk = Walkers(lrx.LRX_DET, dtype, phi, occ, emp, k_max, K, device=device)
+        dev = tuple(torch.as_tensor(x).to(device) for x in (kk, ee, ss))
+        for rpb in rows_candidates(n):
+            lrx.lrx_autotune_store(dtype, n, k_max, K, rpb, 0, 0)
+            results[("step", K, rpb)] = _time_steps(wk, dev, 2 * K, reps=2)
+        del wk
     best = min(results, key=results.get)
+    out = {"delay": int(best[1]), "rows_per_block": int(best[2]), "window": best[0] == "window"}
     table = _load(path)
-    table[key] = {"delay": int(best), "s_per_walker_step": {str(K): v for K, v in results.items()},
-                  "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+    table[key] = dict(out, s_per_walker_step={f"{m},K={K},rows={r}": v for (m, K, r), v in results.items()},
+                      tuned_at=time.strftime("%Y-%m-%d %H:%M:%S"))
     _store(path, table)
-    return int(best)
+    lrx.lrx_autotune_store(dtype, n, k_max, out["delay"], out["rows_per_block"], 0, out["window"])
+    return out
+
+
+def tune_delay(dtype, n, k_max, ranks, walkers=512, device="cuda", cache=None, seed=7):
+    """Best delay K for one size class (see tune_class)."""
+    return tune_class(dtype, n, k_max, ranks, walkers, device, cache, seed)["delay"]
 
 
 def tune_grid(uw, candidates=(1, 2, 3, 4), cache=None):
@@ -112,20 +168,21 @@ def tune_grid(uw, candidates=(1, 2, 3, 4), cache=None):
         return uw.grid
     # the trial windows advance the chains; keep the caller's state out of it
     snap = [(p.st.buffers["inv"].clone(), p.st.buffers["fa"].clone(), p.st.buffers["fb"].clone(),
-             p.st.buffers["stash"].clone(), p.st.logabs.clone(), p.st.phase.clone(), p.occ.clone(),
-             p.empty.clone(), p.st.c.slot) for p in uw.parts]
+             p.st.buffers["stash"].clone(), p.st.logabs.clone(), p.st.phase.clone(), p.st.flags.clone(),
+             p.occ.clone(), p.empty.clone(), p.st.c.slot) for p in uw.parts]
     results = {}
     for c in candidates:
         uw.grid = c * cus
         results[c] = _time_windows(uw, reps=2)
     best = min(results, key=results.get)
-    for p, (inv, fa, fb, st, la, ph, occ, emp, slot) in zip(uw.parts, snap):
+    for p, (inv, fa, fb, st, la, ph, fl, occ, emp, slot) in zip(uw.parts, snap):
         p.st.buffers["inv"].copy_(inv)
         p.st.buffers["fa"].copy_(fa)
         p.st.buffers["fb"].copy_(fb)
         p.st.buffers["stash"].copy_(st)
         p.st.logabs.copy_(la)
         p.st.phase.copy_(ph)
+        p.st.flags.copy_(fl)
         p.occ.copy_(occ)
         p.empty.copy_(emp)
         p.st.c.slot = slot

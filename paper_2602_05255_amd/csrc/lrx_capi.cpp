@@ -1,6 +1,9 @@
 // C ABI of liblrx: host-side validation, buffer sizing and kernel dispatch.
 // Every check here runs on the host before anything is enqueued, so the error
 // paths are testable without a GPU.
+#include <cmath>
+#include <mutex>
+#include <vector>
 #include <hip/hip_runtime.h>
 
 #include <string.h>
@@ -332,29 +335,47 @@ int lrx_det_flush_delayed(lrx_state *st, void *stream) {
     return rc;
 }
 
-static int lowrank_check(const lrx_state *st, int32_t r) {
-    int rc = check_kind(st, LRX_DET);
+static int lowrank_check(const lrx_state *st, int32_t r, int kind) {
+    int rc = check_kind(st, kind);
     if (rc) return rc;
-    if (r < 1 || r > 8 || r > st->shape.n) return LRX_ESHAPE;
-    if (st->shape.delay > 0 && st->slot != 0) return LRX_ENEEDFLUSH;
-    // forward kernel keeps C and the P accumulation in LDS
-    if (2 * (size_t)8 * padded_n(st->shape.n, bulk_bytes(st->shape.dtype)) * bulk_bytes(st->shape.dtype) > 163840)
+    if (kind == LRX_DET && (r < 1 || r > 8 || r > st->shape.n)) return LRX_ESHAPE;
+    if (kind == LRX_PF && (r < 2 || r > 8 || (r & 1) || r > st->shape.n)) return LRX_ESHAPE;
+    if (st->shape.delay > 0 && st->slot == st->shape.delay) return LRX_ENEEDFLUSH;
+    const int KA = kind == LRX_PF ? 2 * st->shape.k_max : st->shape.k_max;
+    const int RR = r <= 1 ? 1 : (r <= 2 ? 2 : (r <= 4 ? 4 : 8));
+    if (lowrank_lds_bytes(kind, st->shape.dtype, st->shape.n, RR, st->shape.delay * KA) > 163840)
         return LRX_EUNSUPPORTED;
     return LRX_OK;
 }
 
-int lrx_det_lowrank_fwd(const lrx_state *st, int32_t r, const void *B, const void *C, void *P, void *Q,
-                        void *Rinv, double *logabs, void *phase, void *stream) {
-    int rc = lowrank_check(st, r);
-    if (rc) return rc;
-    if (!B || !C || !P || !Q || !Rinv || !logabs || !phase) return LRX_EINVAL;
+// Arguments shared by the forward and backward calls: the state, flushed or in
+// the delayed form (its st->slot live steps of slot columns).
+static LowRankArgs lowrank_args(const lrx_state *st, int32_t r, int kind) {
     LowRankArgs a;
     memset(&a, 0, sizeof(a));
+    a.kind = kind;
     a.dtype = st->shape.dtype;
     a.W = st->shape.walkers;
     a.n = st->shape.n;
     a.r = r;
+    a.K = st->shape.delay;
+    a.KA = (kind == LRX_PF ? 2 * st->shape.k_max : st->shape.k_max) * st->shape.delay;
+    a.KK = st->shape.k_max * st->shape.delay;
+    a.TE = st->shape.delay > 0 ? st->slot * (kind == LRX_PF ? 2 * st->shape.k_max : st->shape.k_max) : 0;
     a.inv = st->inv;
+    a.fa = st->fa;
+    a.fb = st->fb;
+    a.state_logabs = st->logabs;
+    a.state_phase = st->phase;
+    return a;
+}
+
+int lrx_det_lowrank_fwd(const lrx_state *st, int32_t r, const void *B, const void *C, void *P, void *Q,
+                        void *Rinv, double *logabs, void *phase, void *stream) {
+    int rc = lowrank_check(st, r, LRX_DET);
+    if (rc) return rc;
+    if (!B || !C || !P || !Q || !Rinv || !logabs || !phase) return LRX_EINVAL;
+    LowRankArgs a = lowrank_args(st, r, LRX_DET);
     a.B = B;
     a.C = C;
     a.P = P;
@@ -362,38 +383,38 @@ int lrx_det_lowrank_fwd(const lrx_state *st, int32_t r, const void *B, const voi
     a.Rinv = Rinv;
     a.logabs = logabs;
     a.phase = phase;
-    a.state_logabs = st->logabs;
-    a.state_phase = st->phase;
     return hip_rc(lowrank_fwd(a, as_stream(stream)));
 }
 
-int lrx_det_lowrank_work_bytes(const lrx_shape *shape, int32_t r, int32_t sites, size_t *out) {
+static int lowrank_work(const lrx_shape *shape, int32_t r, int32_t sites, size_t *out, int kind) {
     int rc = check_shape(shape);
     if (rc) return rc;
+    if (shape->kind != kind) return LRX_EKIND;
     if (!out) return LRX_EINVAL;
-    if (shape->kind != LRX_DET) return LRX_EKIND;
     if (r < 1 || r > 8 || sites < shape->n) return LRX_ESHAPE;
-    *out = lowrank_work_bytes(shape->dtype, shape->walkers, shape->n, r, sites);
+    const int KA = kind == LRX_PF ? 2 * shape->k_max : shape->k_max;
+    *out = lowrank_work_bytes(kind, shape->dtype, shape->walkers, shape->n, r, shape->delay * KA, sites);
     return LRX_OK;
+}
+
+int lrx_det_lowrank_work_bytes(const lrx_shape *shape, int32_t r, int32_t sites, size_t *out) {
+    return lowrank_work(shape, r, sites, out, LRX_DET);
+}
+
+int lrx_pf_lowrank_work_bytes(const lrx_shape *shape, int32_t r, int32_t sites, size_t *out) {
+    return lowrank_work(shape, r, sites, out, LRX_PF);
 }
 
 int lrx_det_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int32_t sites, const void *P,
                         const void *Q, const void *Rinv, const void *g, void *dphi, void *dB, void *dC,
                         void *work, size_t work_bytes, void *stream) {
-    int rc = lowrank_check(st, r);
+    int rc = lowrank_check(st, r, LRX_DET);
     if (rc) return rc;
     if (!occ || !P || !Q || !Rinv || !g || !dphi || !dB || !dC || !work) return LRX_EINVAL;
     if (sites < st->shape.n) return LRX_ESHAPE;
-    if (work_bytes < lowrank_work_bytes(st->shape.dtype, st->shape.walkers, st->shape.n, r, sites))
-        return LRX_EINVAL;
-    LowRankArgs a;
-    memset(&a, 0, sizeof(a));
-    a.dtype = st->shape.dtype;
-    a.W = st->shape.walkers;
-    a.n = st->shape.n;
-    a.r = r;
+    LowRankArgs a = lowrank_args(st, r, LRX_DET);
+    if (work_bytes < lowrank_work_bytes(LRX_DET, a.dtype, a.W, a.n, r, a.TE, sites)) return LRX_EINVAL;
     a.sites = sites;
-    a.inv = st->inv;
     a.P = const_cast<void *>(P);
     a.Q = const_cast<void *>(Q);
     a.Rinv = const_cast<void *>(Rinv);
@@ -404,6 +425,48 @@ int lrx_det_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int3
     a.dC = dC;
     lowrank_bind_work(a, work);
     return hip_rc(lowrank_bwd(a, as_stream(stream)));
+}
+
+int lrx_pf_lowrank_fwd(const lrx_state *st, int32_t r, const void *U, void *P, void *Rinv, double *logabs,
+                       void *phase, void *stream) {
+    int rc = lowrank_check(st, r, LRX_PF);
+    if (rc) return rc;
+    if (!U || !P || !Rinv || !logabs || !phase) return LRX_EINVAL;
+    LowRankArgs a = lowrank_args(st, r, LRX_PF);
+    a.B = U;
+    a.P = P;
+    a.Rinv = Rinv;
+    a.logabs = logabs;
+    a.phase = phase;
+    return hip_rc(lowrank_fwd(a, as_stream(stream)));
+}
+
+int lrx_pf_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int32_t sites, const void *P,
+                       const void *Rinv, const void *g, void *dF, void *dU, void *work, size_t work_bytes,
+                       void *stream) {
+    int rc = lowrank_check(st, r, LRX_PF);
+    if (rc) return rc;
+    if (!occ || !P || !Rinv || !g || !dF || !dU || !work) return LRX_EINVAL;
+    if (sites < st->shape.n) return LRX_ESHAPE;
+    LowRankArgs a = lowrank_args(st, r, LRX_PF);
+    if (work_bytes < lowrank_work_bytes(LRX_PF, a.dtype, a.W, a.n, r, a.TE, sites)) return LRX_EINVAL;
+    a.sites = sites;
+    a.P = const_cast<void *>(P);
+    a.Rinv = const_cast<void *>(Rinv);
+    a.g = g;
+    a.occ = occ;
+    a.dphi = dF;
+    a.dB = dU;
+    lowrank_bind_work(a, work);
+    return hip_rc(lowrank_bwd(a, as_stream(stream)));
+}
+
+int lrx_pf_grad(const lrx_state *st, const void *g, void *dA, void *stream) {
+    int rc = check_kind(st, LRX_PF);
+    if (rc) return rc;
+    if (st->shape.delay > 0 && st->slot != 0) return LRX_ENEEDFLUSH;
+    if (!g || !dA) return LRX_EINVAL;
+    return hip_rc(pf_grad(st->shape.dtype, st->inv, g, dA, st->shape.walkers, st->shape.n, as_stream(stream)));
 }
 
 int lrx_pf_propose_ratio(lrx_state *st, const int32_t *k, const int32_t *cols, const void *x, void *ratio,
@@ -532,54 +595,51 @@ static int window_check(const lrx_window_class *classes, int32_t n_classes, int6
     return LRX_OK;
 }
 
-int lrx_window_plan(const lrx_window_class *classes, int32_t n_classes, int32_t *order, int32_t capacity,
-                    int32_t *count) {
+int lrx_window_work_bytes(const lrx_window_class *classes, int32_t n_classes, size_t *out) {
     int64_t total = 0;
     int rc = window_check(classes, n_classes, &total);
     if (rc) return rc;
-    if (!order || !count || capacity < total) return LRX_EINVAL;
-    // classes by n descending (stable in the class index), walkers in order within a class
-    int idx[LRX_MAX_CLASSES];
-    for (int c = 0; c < n_classes; ++c) idx[c] = c;
-    for (int i = 1; i < n_classes; ++i)
-        for (int j = i; j > 0 && classes[idx[j]].state->shape.n > classes[idx[j - 1]].state->shape.n; --j) {
-            int t = idx[j];
-            idx[j] = idx[j - 1];
-            idx[j - 1] = t;
-        }
-    int64_t p = 0;
-    for (int ci = 0; ci < n_classes; ++ci) {
-        const int c = idx[ci];
-        for (int w = 0; w < classes[c].state->shape.walkers; ++w) {
-            order[2 * p] = c;
-            order[2 * p + 1] = w;
-            ++p;
-        }
-    }
-    *count = (int32_t)p;
+    if (!out) return LRX_EINVAL;
+    *out = 256;
     return LRX_OK;
 }
 
 int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps, int32_t mode, uint64_t seed,
-                   uint64_t counter, const int32_t *order, int32_t n_items, uint32_t *queue, int32_t grid,
-                   void *stream) {
+                   uint64_t counter, void *work, size_t work_bytes, int32_t grid, void *stream) {
     int64_t total = 0;
     int rc = window_check(classes, n_classes, &total);
     if (rc) return rc;
-    if (steps < 1 || grid < 1 || !order || !queue || n_items != total) return LRX_EINVAL;
+    if (steps < 1 || steps > LRX_MAX_WINDOW_STEPS || grid < 1 || !work) return LRX_EINVAL;
+    if (work_bytes < sizeof(uint32_t)) return LRX_EINVAL;
     if (mode != LRX_MH_UNIFORMS && mode != LRX_MH_DEVICE_RNG && mode != LRX_MH_FORCE && mode != LRX_MH_MASK)
         return LRX_EINVAL;
+    for (int c = 0; c < n_classes; ++c)
+        if (mode == LRX_MH_UNIFORMS && !classes[c].u01) return LRX_EINVAL;
     WindowArgs wa;
     memset(&wa, 0, sizeof(wa));
     const int dtype = classes[0].state->shape.dtype;
     const size_t es = bulk_bytes(dtype);
     const int per = (int)(16 / es) * 64;     // elements of one 16-byte chunk per lane across a wave
-    size_t lds = 0;
-    uint32_t rng_base = 0;
+    // processing order: n descending (stable in the caller's class index)
+    int idx[LRX_MAX_CLASSES];
+    uint32_t rng_base[LRX_MAX_CLASSES];
+    uint32_t rb = 0;
     for (int c = 0; c < n_classes; ++c) {
-        const lrx_window_class &wc = classes[c];
-        if (mode == LRX_MH_UNIFORMS && !wc.u01) return LRX_EINVAL;
-        WindowClass &d = wa.cls[c];
+        idx[c] = c;
+        rng_base[c] = rb;                        // generator key: position in the caller's class list
+        rb += (uint32_t)classes[c].state->shape.walkers;
+    }
+    for (int i = 1; i < n_classes; ++i)
+        for (int j = i; j > 0 && classes[idx[j]].state->shape.n > classes[idx[j - 1]].state->shape.n; --j) {
+            const int t = idx[j];
+            idx[j] = idx[j - 1];
+            idx[j - 1] = t;
+        }
+    size_t lds = 0;
+    for (int ci = 0; ci < n_classes; ++ci) {
+        const lrx_window_class &wc = classes[idx[ci]];
+        const int n = wc.state->shape.n;
+        WindowClass &d = wa.cls[ci];
         d.a = step_args(wc.state);
         d.a.u = wc.u;
         d.a.hop_table = wc.table;
@@ -590,9 +650,9 @@ int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps, 
         d.a.mh_mode = mode == LRX_MH_MASK ? -1 : mode;
         d.a.seed = seed;
         d.a.counter = counter;
-        d.a.rng_base = rng_base;
+        d.a.rng_base = rng_base[idx[ci]];
         int nch = 1;
-        while (nch * per < wc.state->shape.n) nch <<= 1;
+        while (nch * per < n) nch <<= 1;
         d.nch = nch;
         d.k = wc.k;
         d.elec = wc.elec;
@@ -600,21 +660,82 @@ int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps, 
         d.u01 = wc.u01;
         d.ratio = wc.ratio;
         d.accept = wc.accept;
-        rng_base += (uint32_t)wc.state->shape.walkers;
         const size_t l = window_lds_bytes(dtype, wc.state->shape.k_max, wc.state->shape.delay, nch);
         lds = l > lds ? l : lds;
     }
     if (lds == 0 || lds > 160 * 1024) return LRX_EUNSUPPORTED;
     wa.n_classes = n_classes;
     wa.steps = steps;
-    wa.n_items = n_items;
-    wa.order = order;
-    wa.queue = queue;
-    rc = hip_rc(det_window(dtype, wa, grid, as_stream(stream)));
+    wa.walkers = (int)total;
+    wa.queue = static_cast<uint32_t *>(work);
+    rc = hip_rc(det_window(dtype, wa, grid, lds, as_stream(stream)));
     if (rc == LRX_OK)
         for (int c = 0; c < n_classes; ++c)
             classes[c].state->slot = (classes[c].state->slot + steps) % classes[c].state->shape.delay;
     return rc;
+}
+
+// ------------------------------------------------------------------ tuning table
+namespace {
+struct TuneEntry {
+    int32_t dtype, n, k_max;
+    lrx_tune t;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int tune_key_ok(int32_t dtype, int32_t n, int32_t k_max) {
+    if (dtype < LRX_F32 || dtype > LRX_C128) return LRX_EUNSUPPORTED;
+    if (n < 1 || n > LRX_MAX_N || k_max < 1 || k_max > LRX_MAX_KMAX_DET) return LRX_ESHAPE;
+    return LRX_OK;
+}
+}  // namespace
+
+int lrx_autotune_store(int32_t dtype, int32_t n, int32_t k_max, const lrx_tune *t) {
+    int rc = tune_key_ok(dtype, n, k_max);
+    if (rc) return rc;
+    if (!t) return LRX_EINVAL;
+    if (t->delay < 1 || t->delay > LRX_MAX_DELAY || t->delay * k_max > 256) return LRX_EINVAL;
+    if (t->rows_per_block != 0 && t->rows_per_block < 16) return LRX_EINVAL;
+    if (t->wgs_per_cu < 0 || t->wgs_per_cu > 16) return LRX_EINVAL;
+    if (t->window != 0 && t->window != 1) return LRX_EINVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    lrx_tune v = *t;
+    v.tuned = 1;
+    for (TuneEntry &e : g_tune)
+        if (e.dtype == dtype && e.n == n && e.k_max == k_max) {
+            e.t = v;
+            return LRX_OK;
+        }
+    g_tune.push_back({dtype, n, k_max, v});
+    return LRX_OK;
+}
+
+int lrx_autotune_lookup(int32_t dtype, int32_t n, int32_t k_max, lrx_tune *out) {
+    int rc = tune_key_ok(dtype, n, k_max);
+    if (rc) return rc;
+    if (!out) return LRX_EINVAL;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const TuneEntry &e : g_tune)
+            if (e.dtype == dtype && e.n == n && e.k_max == k_max) {
+                *out = e.t;
+                return LRX_OK;
+            }
+    }
+    const double kbar = 0.5 * (k_max + 1);
+    const double kstar = std::sqrt(2.0 * n / kbar);
+    int K = 1;
+    while (K * 2 <= LRX_MAX_DELAY && K * 2 * k_max <= 256 && std::fabs(std::log2(K * 2.0) - std::log2(kstar)) <
+                                                                  std::fabs(std::log2((double)K) - std::log2(kstar)))
+        K *= 2;
+    out->delay = K;
+    out->rows_per_block = 0;
+    out->wgs_per_cu = 2;
+    out->window = n < 512 ? 1 : 0;
+    out->tuned = 0;
+    out->reserved = 0;
+    return LRX_OK;
 }
 
 int lrx_hop_commit(int32_t walkers, int32_t n, int32_t n_empty, int32_t k_max, const int32_t *k,

@@ -18,6 +18,12 @@ using namespace lrxdet;
 using lrx::StepArgs;
 using lrx::HopArgs;
 
+template <class T> constexpr int dtype_code();
+template <> constexpr int dtype_code<float>() { return LRX_F32; }
+template <> constexpr int dtype_code<double>() { return LRX_F64; }
+template <> constexpr int dtype_code<cf32>() { return LRX_C64; }
+template <> constexpr int dtype_code<cf64>() { return LRX_C128; }
+
 // ------------------------------------------------------------------ launchers
 template <class T> hipError_t build_hop_t(const HopArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(det_build_hop_kernel<T>, dim3(a.W), dim3(kThreads), 0, s, a);
@@ -59,8 +65,9 @@ template <class T, int KM, int NEL, bool D> hipError_t accept_t(const StepArgs &
         return hipErrorInvalidValue;
     } else {
     constexpr int RB = rows_per_batch<T, NEL, KM>();
-    // Rows per block: long-lived blocks (set-up amortised over at least 128 rows)
-    // with still about eight blocks per compute unit.
+    // Rows per block: a height stored in the tuning table for this size class, else
+    // long-lived blocks (set-up amortised over at least 128 rows) with still about
+    // eight blocks per compute unit.
     const int n = a.n;
     int rpb = kWaves * RB;
     long long blocks = (long long)a.W * ((n + rpb - 1) / rpb);
@@ -68,6 +75,9 @@ template <class T, int KM, int NEL, bool D> hipError_t accept_t(const StepArgs &
         rpb *= 2;
         blocks = (long long)a.W * ((n + rpb - 1) / rpb);
     }
+    lrx_tune tuned;
+    if (lrx_autotune_lookup(dtype_code<T>(), n, KM, &tuned) == LRX_OK && tuned.tuned && tuned.rows_per_block >= 16)
+        rpb = tuned.rows_per_block < n ? tuned.rows_per_block : n;
     const int bpw = (n + rpb - 1) / rpb;
     const size_t lds = accept_lds_bytes<T, KM, NEL, D, RB>(a.K);
     const dim3 grid((unsigned)(a.W * bpw)), block(kThreads);

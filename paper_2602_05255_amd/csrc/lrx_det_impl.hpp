@@ -1,6 +1,6 @@
 // Determinant step kernels as per-walker device functions, shared by the
 // per-step launches (lrx_det.hip) and the persistent window kernel
-// (lrx_persistent.hip).  See lrx_det.hip for the method notes.
+// (lrx_window.hip).  See lrx_det.hip for the method notes.
 #pragma once
 
 #include "lrx_common.hpp"

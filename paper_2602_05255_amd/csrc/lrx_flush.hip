@@ -46,119 +46,16 @@ __global__ __launch_bounds__(256) void det_flush_kernel(StepArgs a, int tiles_pe
                       s_a);
 }
 
-// Real data: a work-group owns a 64-column strip of one walker and walks its
-// 64-row tiles.  The strip's a panel (live columns x 64) is staged in LDS once
-// and serves every row tile; the b values are read straight into the MFMA
-// operand registers.  The next tile's M block is in flight while the current
-// tile is on the matrix cores, and its b values while the current tile is
-// stored.  Live columns are taken in
-// chunks of 64 (one chunk unless tau * k_max exceeds 64).
+// Real data: one 64-column strip per work-group (det_flush_strip).
 template <class T>
 __global__ __launch_bounds__(256, 2) void det_flush_strip_kernel(StepArgs a, int tpd) {
-    using R = typename Real<T>::type;
-    using A4 = typename Acc<R>::type;
-    constexpr int KCH = 64;                  // live columns per chunk
-    constexpr int SA = 64 + 1;               // padded LDS row stride of the a panel
-    constexpr int NS = KCH / 4;              // 4-deep MFMA steps per chunk
-    constexpr int V = vec16<T>();
-    __shared__ __align__(16) T s_a[KCH * SA];
+    __shared__ __align__(16) T s_a[FlushStripLds<T>::kA];
     __shared__ int s_live[LRX_MAX_DELAY * LRX_MAX_KMAX_DET];
     __shared__ int s_nl;
-    const int n = a.n, KK = a.K * a.KM;
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int w = lb / tpd;
     if (w >= a.W) return;
-    const int j0 = (lb - w * tpd) * 64;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, kq = lane >> 4, lc = lane & 15;
-    T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
-    const T *fa = static_cast<const T *>(a.fa) + (size_t)w * KK * n;
-    const T *fb = static_cast<const T *>(a.fb) + (size_t)w * n * KK;
-    int col[4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) col[jb] = min(j0 + jb * 16 + lc, n - 1);
-    struct Buf { T m[4][4]; };
-    // M block of row tile rt (clamped to the last one, so that the load
-    // counts stay exact), from 32-bit element offsets off the walker's base
-    auto issue_m = [&](int rt, Buf &B) {
-        const int rbase = min(rt, tpd - 1) * 64 + wv * 16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t ro = (uint32_t)min(rbase + acc_row<R>(lane, r), n - 1) * (uint32_t)n;
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) B.m[jb][r] = M[ro + (uint32_t)col[jb]];
-        }
-    };
-    Buf b0, b1;
-    issue_m(0, b0);                          // in flight while the live list and a panel are built
-    const int *kslot = reinterpret_cast<const int *>(a.stash + (size_t)w * a.L.stride + a.L.kslot);
-    const int nl = det_live_columns(kslot, a.tau, a.KM, s_live, &s_nl);
-    if (nl == 0) return;                     // nothing accepted since the last flush
-    const bool vec_a = (n % V) == 0;
-    for (int c0 = 0; c0 < nl; c0 += KCH) {
-        const int cw = min(KCH, nl - c0);
-        const int ns = (cw + 3) / 4;
-        if (c0 > 0) __syncthreads();
-        for (int idx = tid; idx < KCH * (64 / V); idx += 256) {
-            const int t = idx / (64 / V), jv = (idx - t * (64 / V)) * V;
-            const int j = j0 + jv;
-            const T *src = fa + (size_t)s_live[c0 + min(t, cw - 1)] * n;
-            T tmp[V];
-            if (vec_a && j + V <= n) {
-                ld16<T>(src + j, tmp);
-            } else {
-#pragma unroll
-                for (int v = 0; v < V; ++v) tmp[v] = src[min(j + v, n - 1)];
-            }
-#pragma unroll
-            for (int v = 0; v < V; ++v) s_a[t * SA + jv + v] = (t < cw && j + v < n) ? tmp[v] : zero<T>();
-        }
-        __syncthreads();
-        // Loads from clamped addresses, nothing selected until the values are used.
-        auto load_b = [&](int rt, T (&bb)[NS]) {
-            const int rbase = min(rt, tpd - 1) * 64 + wv * 16;
-            const uint32_t bo = (uint32_t)min(rbase + lc, n - 1) * (uint32_t)KK;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) bb[s] = fb[bo + (uint32_t)s_live[c0 + min(4 * s + kq, cw - 1)]];
-        };
-        // MFMAs of tile rt, then the b values of tile rt + 1 (issued before the
-        // stores), then the stores.
-        T bcur[NS];
-        auto consume = [&](int rt, Buf &B) {
-            const int rbase = rt * 64 + wv * 16;
-            A4 acc[4];
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[jb][r] = B.m[jb][r];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                if (s >= ns) break;
-                const int k = 4 * s + kq;
-                const T bv = k < cw ? -bcur[s] : zero<T>();      // acc += (-b) a^T: M0 - B A^T
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) acc[jb] = mfma(bv, s_a[k * SA + jb * 16 + lc], acc[jb]);
-            }
-            load_b(rt + 1, bcur);
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) {
-                const int j = j0 + jb * 16 + lc;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int q = rbase + acc_row<R>(lane, r);
-                    if (q < n && j < n) M[(uint32_t)q * (uint32_t)n + (uint32_t)j] = acc[jb][r];
-                }
-            }
-        };
-        if (c0 > 0) issue_m(0, b0);          // a later chunk re-reads the updated M
-        load_b(0, bcur);
-        for (int rt = 0; rt < tpd; rt += 2) {
-            issue_m(rt + 1, b1);
-            consume(rt, b0);
-            if (rt + 1 >= tpd) break;
-            issue_m(rt + 2, b0);
-            consume(rt + 1, b1);
-        }
-    }
+    det_flush_strip<T>(a, w, (int)(lb - w * tpd), tpd, s_a, s_live, &s_nl);
 }
 
 // ------------------------------------------------------------------ PF

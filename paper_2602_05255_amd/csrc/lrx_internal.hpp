@@ -118,13 +118,12 @@ struct WindowClass {
     uint8_t *accept;         // [steps][W]
 };
 struct WindowArgs {
-    WindowClass cls[kMaxClasses];
-    int n_classes, steps, n_items;
-    const int32_t *order;    // [n_items][2] = (class, walker), heaviest first
-    uint32_t *queue;         // work counter, reset by the launch
+    WindowClass cls[kMaxClasses];   // in processing order: n descending
+    int n_classes, steps, walkers;
+    uint32_t *queue;         // work counter (cleared by the launch)
 };
 size_t window_lds_bytes(int dtype, int KM, int K, int nch_max);
-hipError_t det_window(int dtype, const WindowArgs &a, int grid, hipStream_t s);
+hipError_t det_window(int dtype, const WindowArgs &a, int grid, size_t lds, hipStream_t s);
 
 // Init / refresh (lrx_factor.hip).
 struct FactorArgs {
@@ -142,25 +141,31 @@ struct FactorArgs {
 size_t factor_work_bytes(int kind, int dtype, int W, int n);
 hipError_t factor(const FactorArgs &a, hipStream_t s);
 
-// Low-rank log-determinant and adjoint (lrx_adjoint.hip).
+// Low-rank log-determinant / log-Pfaffian and adjoints (lrx_adjoint.hip).
 struct LowRankArgs {
-    int dtype, W, n, r, sites;
-    const void *inv;                 // A^-T (bulk [W][n][n])
-    const void *B, *C;               // bulk [W][n][r]
-    void *P, *Q, *Rinv;              // bulk [W][n][r], [W][n][r], [W][r][r]
-    double *logabs;                  // out: log|det M|
+    int kind, dtype, W, n, r, sites; // r: rank of B C^T (DET) or columns of U (PF, even)
+    int TE, KK, KA, K;               // live slot columns of the delayed form (0: flushed), fb row
+                                     // stride (DET), fa columns per walker, delay K
+    const void *inv, *fa, *fb;       // state: M0 (DET A^-T, PF A^-1), slot panels
+    const void *B, *C;               // DET: bulk [W][n][r]; PF: B = U [W][n][r]
+    void *P, *Q, *Rinv;              // bulk [W][n][r], [W][n][r] (DET), [W][r][r]
+    double *logabs;                  // out: log|det M| / log|pf M|
     void *phase;                     // out: wide
-    const double *state_logabs;      // log|det A|
+    const double *state_logabs;      // log|det A| / log|pf A|
     const void *state_phase;         // wide
     const void *g;                   // wide [W] cotangent
     const int32_t *occ;              // [W][n]
-    void *dphi, *dB, *dC;            // bulk outputs
-    void *E, *F;                     // workspace
-    int *csr_start, *csr_cursor, *csr_list;
+    void *dphi, *dB, *dC;            // DET: dPhi [sites][n], dB, dC; PF: dF [sites][sites], dU (dB)
+    // workspace
+    int *pos;                        // [W][sites] electron on each site (-1: empty)
+    void *E, *F, *part, *Y;
+    int ksplit;
 };
-size_t lowrank_work_bytes(int dtype, int W, int n, int r, int sites);
+size_t lowrank_lds_bytes(int kind, int dtype, int n, int RR, int TE);
+size_t lowrank_work_bytes(int kind, int dtype, int W, int n, int r, int TE, int sites);
 void lowrank_bind_work(LowRankArgs &a, void *work);
 hipError_t lowrank_fwd(const LowRankArgs &a, hipStream_t s);
 hipError_t lowrank_bwd(const LowRankArgs &a, hipStream_t s);
+hipError_t pf_grad(int dtype, const void *M, const void *g, void *dA, int W, int n, hipStream_t s);
 
 }  // namespace lrx

@@ -3,14 +3,16 @@
 // steps (Sec. II.C), flushing each walker's slots into M0 whenever its window
 // fills (Eq. delayed_Ainv).
 //
-// Work items are whole walkers, handed out heaviest first (n^2 descending, a
-// longest-processing-time order) from a device counter, so the large classes
-// start early and the small ones fill the tail.  A work-group of four waves
-// keeps one walker for the whole window: propose -> decision -> delayed
-// accept -> commit, step after step, with only work-group barriers between
-// the phases (the slot data written by one step is read by the next inside
-// the same work-group).  The size class picks the row-chunk specialisation of
-// the step functions shared with the per-step kernels.
+// Work items are whole walkers, handed out heaviest first (classes by n
+// descending, a longest-processing-time order) from a device counter, so the
+// large classes start early and the small ones fill the tail.  A work-group of
+// four waves keeps one walker for the whole window: propose -> decision ->
+// delayed accept -> commit, step after step, with only work-group barriers
+// between the phases (the slot data written by one step is read by the next
+// inside the same work-group, so no data crosses compute units), and the
+// walker's flush runs as 64-column strips in the same work-group.  The size
+// class picks the row-chunk specialisation of the step functions shared with
+// the per-step kernels.
 #include "lrx_det_impl.hpp"
 #include "lrx_flush_impl.hpp"
 
@@ -24,22 +26,17 @@ using lrx::WindowClass;
 
 constexpr int kWindowThreads = 256;   // det_propose_walker with NW = 4 and the accept rows share it
 
+// The walker's flush M0 -= B A^T (Eq. delayed_Ainv), strip after strip.
 template <class T>
 __device__ __forceinline__ void window_flush(const StepArgs &a, int w, int tau, unsigned char *smem) {
-    const int n = a.n, KK = a.K * a.KM;
-    int *s_live = reinterpret_cast<int *>(smem + FlushLds<T>::bytes);
-    int *s_nl = s_live + KK;
-    const int *kslot = reinterpret_cast<const int *>(a.stash + (size_t)w * a.L.stride + a.L.kslot);
-    const int nl = det_live_columns(kslot, tau, a.KM, s_live, s_nl);
-    T *s_b = reinterpret_cast<T *>(smem);
-    T *s_a = s_b + 64 * FlushLds<T>::SB;
-    T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
-    const T *fa = static_cast<const T *>(a.fa) + (size_t)w * KK * n;
-    const T *fb = static_cast<const T *>(a.fb) + (size_t)w * n * KK;
-    const int tpd = (n + 63) / 64;
-    for (int tile = 0; tile < tpd * tpd; ++tile) {
-        const int ti = tile / tpd, tj = tile - ti * tpd;
-        det_flush_tile<T>(M, fa, fb, n, KK, s_live, nl, ti * 64, tj * 64, s_b, s_a);
+    StepArgs f = a;
+    f.tau = tau;
+    T *s_a = reinterpret_cast<T *>(smem);
+    int *s_live = reinterpret_cast<int *>(s_a + FlushStripLds<T>::kA);
+    const int tpd = (a.n + 63) / 64;
+    for (int strip = 0; strip < tpd; ++strip) {
+        __syncthreads();
+        det_flush_strip<T>(f, w, strip, tpd, s_a, s_live, s_live + a.K * a.KM);
     }
     __syncthreads();
 }
@@ -92,9 +89,12 @@ __global__ __launch_bounds__(kWindowThreads, 2) void det_window_kernel(WindowArg
         __syncthreads();
         // The item is block-uniform: keep it (and everything addressed through it) in scalar registers.
         const int item = __builtin_amdgcn_readfirstlane(s_item);
-        if (item >= wa.n_items) break;     // every work-group leaves once the list is drained
-        const int c = __builtin_amdgcn_readfirstlane(wa.order[2 * item]);
-        const int w = __builtin_amdgcn_readfirstlane(wa.order[2 * item + 1]);
+        if (item >= wa.walkers) break;     // every work-group leaves once the list is drained
+        // classes are in processing order (n descending): walker = position within its class
+        int c = 0, w = item;
+        while (w >= wa.cls[c].a.W) { w -= wa.cls[c].a.W; ++c; }
+        c = __builtin_amdgcn_readfirstlane(c);
+        w = __builtin_amdgcn_readfirstlane(w);
         const WindowClass &wc = wa.cls[c];
         switch (wc.nch) {
             case 1: window_walker<T, KM, 1>(wc, wa.steps, w, smem); break;
@@ -115,35 +115,27 @@ template <class T, int KM> size_t window_lds_t(int K, int nch_max) {
     const size_t npad = (size_t)nch_max * V * LRX_WAVE;
     const size_t acc = sizeof(T) * (KM * npad + KM * KM + (size_t)K * KM * KM + (size_t)kWaves * kZB * 8 * KM);
     const size_t prop = propose_lds_bytes<T, KM, 4>(K);
-    const size_t fl = FlushLds<T>::bytes + sizeof(int) * ((size_t)K * KM + 1);
+    const size_t fl = sizeof(T) * FlushStripLds<T>::kA + sizeof(int) * ((size_t)K * KM + 1);
     return acc > prop ? (acc > fl ? acc : fl) : (prop > fl ? prop : fl);
 }
 
-template <class T, int KM> hipError_t window_t(const WindowArgs &a, int grid, hipStream_t s) {
-    int nch_max = 1;
-    for (int c = 0; c < a.n_classes; ++c) nch_max = a.cls[c].nch > nch_max ? a.cls[c].nch : nch_max;
-    const size_t lds = window_lds_t<T, KM>(a.cls[0].a.K > 0 ? a.cls[0].a.K : 1, nch_max);
-    size_t need = lds;
-    for (int c = 1; c < a.n_classes; ++c) {
-        const size_t l = window_lds_t<T, KM>(a.cls[c].a.K, nch_max);
-        need = l > need ? l : need;
-    }
-    if (need > 65536) {
+template <class T, int KM> hipError_t window_t(const WindowArgs &a, int grid, size_t lds, hipStream_t s) {
+    if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&det_window_kernel<T, KM>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(window_reset_kernel, dim3(1), dim3(64), 0, s, a.queue);
-    hipLaunchKernelGGL((det_window_kernel<T, KM>), dim3((unsigned)grid), dim3(kWindowThreads), need, s, a);
+    hipLaunchKernelGGL((det_window_kernel<T, KM>), dim3((unsigned)grid), dim3(kWindowThreads), lds, s, a);
     return hipGetLastError();
 }
 
-template <class T> hipError_t window_k(const WindowArgs &a, int grid, hipStream_t s) {
+template <class T> hipError_t window_k(const WindowArgs &a, int grid, size_t lds, hipStream_t s) {
     switch (a.cls[0].a.KM) {
-        case 1: return window_t<T, 1>(a, grid, s);
-        case 2: return window_t<T, 2>(a, grid, s);
-        case 4: return window_t<T, 4>(a, grid, s);
-        case 8: return window_t<T, 8>(a, grid, s);
+        case 1: return window_t<T, 1>(a, grid, lds, s);
+        case 2: return window_t<T, 2>(a, grid, lds, s);
+        case 4: return window_t<T, 4>(a, grid, lds, s);
+        case 8: return window_t<T, 8>(a, grid, lds, s);
     }
     return hipErrorInvalidValue;
 }
@@ -170,10 +162,10 @@ size_t window_lds_bytes(int dtype, int KM, int K, int nch_max) {
     return 0;
 }
 
-hipError_t det_window(int dtype, const WindowArgs &a, int grid, hipStream_t s) {
+hipError_t det_window(int dtype, const WindowArgs &a, int grid, size_t lds, hipStream_t s) {
     switch (dtype) {
-        case LRX_F32: return window_k<float>(a, grid, s);
-        case LRX_F64: return window_k<double>(a, grid, s);
+        case LRX_F32: return window_k<float>(a, grid, lds, s);
+        case LRX_F64: return window_k<double>(a, grid, lds, s);
     }
     return hipErrorInvalidValue;
 }

@@ -78,18 +78,39 @@ def hop_draws(rng: np.random.Generator, walkers: int, n: int, n_empty: int,
     return k, elec, slot
 
 
+def _first_distinct(rng: np.random.Generator, lead, m: int, k: int):
+    """For every index of the leading shape, k distinct values of range(m) drawn uniformly
+    without replacement, in draw order: the first k distinct entries of an iid uniform
+    sequence (sequential sampling without replacement).  Rows whose candidate sequence holds
+    fewer than k distinct values are redrawn from a random permutation."""
+    c = min(m, 2 * k + 8) if m > 2 * k + 8 else m
+    if c == m:                                     # small ranges: a random permutation per row
+        return np.argsort(rng.random(tuple(lead) + (m,)), axis=-1)[..., :k]
+    cand = rng.integers(0, m, size=tuple(lead) + (c,))
+    eq = cand[..., :, None] == cand[..., None, :]
+    new = ~np.any(np.tril(eq, -1), axis=-1)        # not equal to any earlier candidate of the row
+    pos = np.argsort(~new, axis=-1, kind="stable")[..., :k]
+    out = np.take_along_axis(cand, pos, axis=-1)
+    short = new.sum(axis=-1) < k
+    if short.any():
+        idx = np.nonzero(short)
+        out[idx] = np.argsort(rng.random((len(idx[0]), m)), axis=-1)[:, :k]
+    return out
+
+
 def hop_draws_batch(rng: np.random.Generator, steps: int, walkers: int, n: int, n_empty: int,
                     ranks, k_max: int):
     """``steps`` steps of proposal draws at once (same distribution as hop_draws).
 
-    Distinct electrons / empty-list slots come from the first k entries of a
-    random permutation (argsort of iid uniforms).  Returns int32 arrays
-    k [steps][W], elec [steps][W][k_max], slot [steps][W][k_max].
+    k[t][w] is drawn uniformly from ``ranks``; the k_max electrons and empty-list slots
+    of a walker-step are distinct uniform draws without replacement, of which the first
+    k are used.  Returns int32 arrays k [steps][W], elec [steps][W][k_max],
+    slot [steps][W][k_max]; entries c >= k repeat entry 0 (padding).
     """
     ranks = np.asarray(ranks, dtype=np.int32)
     k = ranks[rng.integers(0, len(ranks), size=(steps, walkers))].astype(np.int32)
-    elec = np.argsort(rng.random((steps, walkers, n)), axis=2)[:, :, :k_max].astype(np.int32)
-    slot = np.argsort(rng.random((steps, walkers, n_empty)), axis=2)[:, :, :k_max].astype(np.int32)
+    elec = _first_distinct(rng, (steps, walkers), n, k_max).astype(np.int32)
+    slot = _first_distinct(rng, (steps, walkers), n_empty, k_max).astype(np.int32)
     pad = np.arange(k_max)[None, None, :] >= k[:, :, None]
     elec = np.where(pad, elec[:, :, :1], elec)
     slot = np.where(pad, slot[:, :, :1], slot)
@@ -138,6 +159,12 @@ WORKLOADS = {
     "nsweep_det_k1": Workload("nsweep_det_k1", "det", 0, 0, 1024, (1,), 1, 0, 128,
                               False, "f64", steps=128, seed=SEED_BASE + 6,
                               extra={"sizes": (64, 128, 256, 512, 1024)}),
+    # Delayed vs plain updates (the paper's delay-length benchmark): 16384 walkers, n = 128,
+    # L = 256, single hops, 128 consecutive updates with no refresh; delay K swept.
+    "delay_sweep_n128_det": Workload("delay_sweep_n128_det", "det", 256, 128, 16384, (1,), 1, 16, 0,
+                                     False, "f64", steps=128, seed=SEED_BASE + 7),
+    "delay_sweep_n128_pf": Workload("delay_sweep_n128_pf", "pf", 256, 128, 16384, (1,), 1, 4, 0,
+                                    False, "f64", steps=128, seed=SEED_BASE + 8),
     # Differentiated log-psi: c64 Phi 1024x512 + rank-8 B C^T per sample, 512 samples.
     "logpsi_grad_n512_c64": Workload("logpsi_grad_n512_c64", "det", 1024, 512, 512, (8,), 8, 0, 0,
                                      True, "c64", seed=SEED_BASE + 5, extra={"rank": 8, "bc_var": 0.1}),

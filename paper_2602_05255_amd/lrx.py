@@ -31,6 +31,7 @@ LRX_FLAG_SINGULAR_R, LRX_FLAG_NONFINITE, LRX_FLAG_SINGULAR_A, LRX_FLAG_BADINDEX 
 LRX_MH_UNIFORMS, LRX_MH_DEVICE_RNG, LRX_MH_FORCE, LRX_MH_MASK = 0, 1, 2, 3
 LRX_MAX_N, LRX_MAX_KMAX_DET, LRX_MAX_KMAX_PF, LRX_MAX_DELAY = 1024, 8, 1, 64
 LRX_MAX_CLASSES = 8
+LRX_MAX_WINDOW_STEPS = 256
 
 DTYPE_CODE = {torch.float32: LRX_F32, torch.float64: LRX_F64,
               torch.complex64: LRX_C64, torch.complex128: LRX_C128}
@@ -54,6 +55,11 @@ class lrx_state(ctypes.Structure):
                 ("inv", ctypes.c_void_p), ("fa", ctypes.c_void_p), ("fb", ctypes.c_void_p),
                 ("stash", ctypes.c_void_p), ("logabs", ctypes.c_void_p), ("phase", ctypes.c_void_p),
                 ("flags", ctypes.c_void_p), ("work", ctypes.c_void_p)]
+
+
+class lrx_tune(ctypes.Structure):
+    _fields_ = [("delay", ctypes.c_int32), ("rows_per_block", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("tuned", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lrx_window_class(ctypes.Structure):
@@ -85,6 +91,12 @@ _SIGS = {
                                    ctypes.c_int),
     "lrx_det_lowrank_bwd": ([ctypes.POINTER(lrx_state), _I, _P, _I, _P, _P, _P, _P, _P, _P, _P, _P,
                              ctypes.c_size_t, _P], ctypes.c_int),
+    "lrx_pf_lowrank_fwd": ([ctypes.POINTER(lrx_state), _I, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_pf_lowrank_work_bytes": ([ctypes.POINTER(lrx_shape), _I, _I, ctypes.POINTER(ctypes.c_size_t)],
+                                  ctypes.c_int),
+    "lrx_pf_lowrank_bwd": ([ctypes.POINTER(lrx_state), _I, _P, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
+                           ctypes.c_int),
+    "lrx_pf_grad": ([ctypes.POINTER(lrx_state), _P, _P, _P], ctypes.c_int),
     "lrx_pf_init_inverse": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P], ctypes.c_int),
     "lrx_pf_refresh": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _P], ctypes.c_int),
     "lrx_pf_build_hop": ([ctypes.POINTER(lrx_state), _P, _I, _P, _P, _I, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -97,10 +109,12 @@ _SIGS = {
     "lrx_metropolis": ([ctypes.POINTER(lrx_state), _P, _P, ctypes.c_uint64, ctypes.c_uint64, _I, _P, _P],
                        ctypes.c_int),
     "lrx_hop_commit": ([_I, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
-    "lrx_window_plan": ([ctypes.POINTER(lrx_window_class), _I, _P, _I, ctypes.POINTER(ctypes.c_int32)],
-                        ctypes.c_int),
-    "lrx_det_window": ([ctypes.POINTER(lrx_window_class), _I, _I, _I, ctypes.c_uint64, ctypes.c_uint64, _P, _I,
-                        _P, _I, _P], ctypes.c_int),
+    "lrx_autotune_store": ([_I, _I, _I, ctypes.POINTER(lrx_tune)], ctypes.c_int),
+    "lrx_autotune_lookup": ([_I, _I, _I, ctypes.POINTER(lrx_tune)], ctypes.c_int),
+    "lrx_window_work_bytes": ([ctypes.POINTER(lrx_window_class), _I, ctypes.POINTER(ctypes.c_size_t)],
+                              ctypes.c_int),
+    "lrx_det_window": ([ctypes.POINTER(lrx_window_class), _I, _I, _I, ctypes.c_uint64, ctypes.c_uint64, _P,
+                        ctypes.c_size_t, _I, _P], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -321,6 +335,45 @@ def lrx_det_lowrank_bwd(st: State, r, occ, sites, P, Q, Rinv, g, dphi, dB, dC, w
                                     _stream(stream)), "lrx_det_lowrank_bwd")
 
 
+def lrx_pf_lowrank_fwd(st: State, r, U, P, Rinv, logabs, phase, stream=None):
+    shp = (st.walkers, st.n, r)
+    _dev(U, "U", st.dtype, shp)
+    _dev(P, "P", st.dtype, shp)
+    _dev(Rinv, "Rinv", st.dtype, (st.walkers, r, r))
+    _dev(logabs, "logabs", torch.float64, (st.walkers,))
+    _dev(phase, "phase", st.wide, (st.walkers,))
+    _check(_lib.lrx_pf_lowrank_fwd(st.ptr(), int(r), _dev(U, "U"), _dev(P, "P"), _dev(Rinv, "Rinv"),
+                                   _dev(logabs, "logabs"), _dev(phase, "phase"), _stream(stream)),
+           "lrx_pf_lowrank_fwd")
+
+
+def lrx_pf_lowrank_work_bytes(st: State, r, sites) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.lrx_pf_lowrank_work_bytes(ctypes.byref(st.c.shape), int(r), int(sites), ctypes.byref(out)),
+           "lrx_pf_lowrank_work_bytes")
+    return int(out.value)
+
+
+def lrx_pf_lowrank_bwd(st: State, r, occ, sites, P, Rinv, g, dF, dU, work, stream=None):
+    shp = (st.walkers, st.n, r)
+    _dev(occ, "occ", torch.int32, (st.walkers, st.n))
+    _dev(P, "P", st.dtype, shp)
+    _dev(dU, "dU", st.dtype, shp)
+    _dev(Rinv, "Rinv", st.dtype, (st.walkers, r, r))
+    _dev(g, "g", st.wide, (st.walkers,))
+    _dev(dF, "dF", st.dtype, (sites, sites))
+    _dev(work, "work", torch.uint8)
+    _check(_lib.lrx_pf_lowrank_bwd(st.ptr(), int(r), _dev(occ, "occ"), int(sites), _dev(P, "P"), _dev(Rinv, "Rinv"),
+                                   _dev(g, "g"), _dev(dF, "dF"), _dev(dU, "dU"), _dev(work, "work"),
+                                   ctypes.c_size_t(work.numel()), _stream(stream)), "lrx_pf_lowrank_bwd")
+
+
+def lrx_pf_grad(st: State, g, dA, stream=None):
+    _dev(g, "g", st.wide, (st.walkers,))
+    _dev(dA, "dA", st.dtype, (st.walkers, st.n, st.n))
+    _check(_lib.lrx_pf_grad(st.ptr(), _dev(g, "g"), _dev(dA, "dA"), _stream(stream)), "lrx_pf_grad")
+
+
 # ------------------------------------------------------------------ PF
 def lrx_pf_init_inverse(st: State, f, sites, occ, stream=None):
     pocc = _dev(occ, "occ", torch.int32, (st.walkers, st.n), allow_none=True)
@@ -457,21 +510,33 @@ def _class_array(classes, steps):
     return arr
 
 
-def lrx_window_plan(classes, steps=1):
-    """Host int32 [n_items][2] work order (class, walker), heaviest first."""
+def lrx_window_work_bytes(classes, steps=1) -> int:
     arr = _class_array(classes, steps)
-    total = sum(int(arr[i].state.contents.shape.walkers) for i in range(len(classes)))
-    order = torch.empty(max(total, 1), 2, dtype=torch.int32)
-    count = ctypes.c_int32()
-    _check(_lib.lrx_window_plan(arr, len(classes), ctypes.c_void_p(order.data_ptr()), int(total),
-                                ctypes.byref(count)), "lrx_window_plan")
-    return order[: count.value]
+    out = ctypes.c_size_t()
+    _check(_lib.lrx_window_work_bytes(arr, len(classes), ctypes.byref(out)), "lrx_window_work_bytes")
+    return int(out.value)
 
 
-def lrx_det_window(classes, steps, mode, seed, counter, order, queue, grid, stream=None):
+def lrx_det_window(classes, steps, mode, seed, counter, work, grid, stream=None):
     arr = _class_array(classes, steps)
-    _dev(order, "order", torch.int32)
-    _dev(queue, "queue", torch.int32)
+    _dev(work, "work", torch.uint8)
     _check(_lib.lrx_det_window(arr, len(classes), int(steps), int(mode), ctypes.c_uint64(seed),
-                               ctypes.c_uint64(counter), _dev(order, "order"), int(order.shape[0]),
-                               _dev(queue, "queue"), int(grid), _stream(stream)), "lrx_det_window")
+                               ctypes.c_uint64(counter), _dev(work, "work"), int(work.numel()), int(grid),
+                               _stream(stream)), "lrx_det_window")
+
+
+# ------------------------------------------------------------------ tuning table
+def lrx_autotune_store(dtype, n, k_max, delay, rows_per_block=0, wgs_per_cu=0, window=1):
+    """Register tuned launch parameters of a size class with the library (host only)."""
+    code = DTYPE_CODE[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    t = lrx_tune(int(delay), int(rows_per_block), int(wgs_per_cu), int(bool(window)), 0, 0)
+    _check(_lib.lrx_autotune_store(code, int(n), int(k_max), ctypes.byref(t)), "lrx_autotune_store")
+
+
+def lrx_autotune_lookup(dtype, n, k_max):
+    """Launch parameters of a size class: the stored entry or the library's byte-model default."""
+    code = DTYPE_CODE[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    t = lrx_tune()
+    _check(_lib.lrx_autotune_lookup(code, int(n), int(k_max), ctypes.byref(t)), "lrx_autotune_lookup")
+    return {"delay": t.delay, "rows_per_block": t.rows_per_block, "wgs_per_cu": t.wgs_per_cu,
+            "window": bool(t.window), "tuned": bool(t.tuned)}

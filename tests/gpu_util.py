@@ -5,7 +5,8 @@ import sys
 
 import numpy as np
 
-EPS64 = np.finfo(np.float64).eps
+EPS64 = float(np.finfo(np.float64).eps)
+EPS32 = float(np.finfo(np.float32).eps)
 
 
 def say(*a):
@@ -22,9 +23,52 @@ def rel_err(a, b, axis=None):
 
 
 def ratio_err(r, r_ref):
+    """Relative error |r - r_o| / |r_o| of ratios (a zero oracle ratio compares absolutely)."""
     r = np.asarray(r)
     r_ref = np.asarray(r_ref)
-    return np.abs(r - r_ref) / np.maximum(np.abs(r_ref), 1.0)
+    return np.abs(r - r_ref) / np.where(r_ref == 0, 1.0, np.abs(r_ref))
+
+
+class RatioTally:
+    """Ratio checks of a test: relative error |r - r_o| / |r_o| against a flat tolerance;
+    a walker-step above it is held instead to 8 eps growth times its first-order error
+    bound (an ill-conditioned or strongly suppressed move), and counted."""
+
+    def __init__(self, name=""):
+        self.name, self.checked, self.widened, self.worst = name, 0, 0, 0.0
+
+    def check(self, r, r_o, flat, bound=None, eps=EPS64, growth=1.0, where=""):
+        er = np.atleast_1d(ratio_err(r, r_o))
+        self.checked += er.size
+        self.worst = max(self.worst, float(er.max()) if er.size else 0.0)
+        over = er > flat
+        if over.any():
+            assert bound is not None, f"{where}: ratio error {er.max():.3e} > {flat:.1e}"
+            b = np.atleast_1d(bound() if callable(bound) else np.asarray(bound))
+            tol = np.where(over, np.maximum(flat, 8.0 * eps * np.asarray(growth) * b), flat)
+            bad = er > tol
+            assert not bad.any(), (f"{where}: ratio error {er[bad].max():.3e} above its widened bound "
+                                   f"{tol[bad].min():.1e}")
+            self.widened += int(over.sum())
+        return er
+
+    def report(self):
+        say(f"  {self.name} ratio checks: {self.checked} walker-steps, {self.widened} above the flat "
+            f"tolerance (held to their first-order bound), max rel err {self.worst:.2e}")
+
+
+def assert_entries_close(got, ref, tol, what=""):
+    """Element-by-element comparison: |got - ref| <= tol * max(|ref|, rms(ref)) for every
+    entry (relative per entry, with the array's RMS as the floor for entries near zero)."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2))) if ref.size else 0.0
+    scale = np.maximum(np.abs(ref), rms)
+    err = np.abs(got - ref)
+    bad = err > tol * scale
+    assert not bad.any(), (f"{what}: {int(bad.sum())} of {ref.size} entries off, worst "
+                           f"{float(np.max(err / np.where(scale > 0, scale, 1.0))):.3e} > {tol:.1e}")
+    return float(np.max(err / np.where(scale > 0, scale, 1.0))) if ref.size else 0.0
 
 
 def det_ratio_bound(phi, occ_before, occ_after, inv_before, k, elec):
@@ -61,14 +105,20 @@ def fp64_tol(cond, steps):
 
 
 def run_chain(walkers, chain, draws, u01s, check_every=1, check_inverse=True, tol_ratio=None, tol_inv=None,
-              stats=None, check_walkers=None, bound_fn=None):
+              stats=None, check_walkers=None, bound_fn=None, eps=EPS64, growth=None):
     """Drive GPU walkers and the oracle chain through the same proposals.
 
     The oracle's Metropolis decision (from its own ratios) is fed to the GPU as
-    the accept mask so both follow one trajectory.  Returns max errors.
+    the accept mask so both follow one trajectory.  Ratios are checked with a
+    RatioTally: relative error against ``tol_ratio``, a walker-step above it held
+    to 8 eps growth(t) times the first-order bound from ``bound_fn`` (growth(t) is
+    the number of updates the stored inverse has taken since it was last
+    recomputed) and counted.  Returns max errors; ``stats`` (a list) receives
+    per-step records and the final ("widened_total", n_widened, n_checked).
     """
     import oracle as orc
-    worst_r, worst_m = 0.0, 0.0
+    tally = RatioTally(type(chain).__name__)
+    worst_m = 0.0
     cw = np.arange(walkers.W) if check_walkers is None else np.asarray(check_walkers)
     for t, ((k, elec, slot), u01) in enumerate(zip(draws, u01s)):
         walkers.set_draws(k, elec, slot)
@@ -77,19 +127,17 @@ def run_chain(walkers, chain, draws, u01s, check_every=1, check_inverse=True, to
             chain.inv_before, chain.occ_before = chain.inv.copy(), chain.book.occ.copy()
         r_orc = chain.propose(k, elec, slot)
         mask = orc.metropolis(r_orc, u01)
-        # The ratio is det(I + u^T C): its rounding error is relative to the identity
-        # term, so the error is measured on the scale max(1, |r|) (pure relative
-        # error for |r| >= 1, absolute for the strongly suppressed moves |r| < 1).
-        er = ratio_err(r_gpu[cw], r_orc[cw])
-        worst_r = max(worst_r, float(er.max()))
         if tol_ratio is not None:
-            tol = tol_ratio(t) if callable(tol_ratio) else tol_ratio
-            if np.any(er > tol) and bound_fn is not None:
-                # widen to the computed first-order bound for ill-conditioned steps (counted)
-                tol = np.maximum(tol, 8 * EPS64 * bound_fn(t, chain, k, elec, slot, cw))
-                if stats is not None:
-                    stats.append(("widened", t, int(np.sum(er > tol_ratio))))
-            assert np.all(er <= tol), f"step {t}: ratio error {er.max():.3e} > {np.min(tol):.1e}"
+            flat = tol_ratio(t) if callable(tol_ratio) else tol_ratio
+            before = tally.widened
+            er = tally.check(r_gpu[cw], r_orc[cw], flat,
+                             (lambda: bound_fn(t, chain, k, elec, slot, cw)) if bound_fn is not None else None,
+                             eps, growth(t) if growth is not None else 1.0, where=f"step {t}")
+            if stats is not None and tally.widened > before:
+                stats.append(("widened", t, tally.widened - before))
+        else:
+            er = ratio_err(r_gpu[cw], r_orc[cw])
+            tally.worst = max(tally.worst, float(er.max()))
         walkers.decide(mask=mask)
         walkers.apply()
         chain.accept(k, elec, slot, mask)
@@ -102,13 +150,16 @@ def run_chain(walkers, chain, draws, u01s, check_every=1, check_inverse=True, to
                 assert np.all(em <= tol), f"step {t}: inverse error {em.max():.3e}"
         if stats is not None:
             stats.append((t, float(er.max()), int(mask.sum())))
+    tally.report()
+    if stats is not None:
+        stats.append(("widened_total", tally.widened, tally.checked))
     # occupancy bookkeeping agrees exactly
     np.testing.assert_array_equal(walkers.occ.cpu().numpy(), chain.book.occ)
     np.testing.assert_array_equal(walkers.empty.cpu().numpy(), chain.book.empty)
     # log|det| / phase tracked through the ratios agree with the recomputation
     la = walkers.st.logabs.cpu().numpy()
     ph = walkers.st.phase.cpu().numpy()
-    return worst_r, worst_m, la, ph
+    return tally.worst, worst_m, la, ph
 
 
 def det_bound_fn(phi):
@@ -116,4 +167,29 @@ def det_bound_fn(phi):
     def fn(t, chain, k, elec, slot, cw):
         after = chain.book.proposed(k, elec, slot)
         return det_ratio_bound(phi, chain.occ_before[cw], after[cw], chain.inv_before[cw], k[cw], elec[cw])
+    return fn
+
+
+def pf_hop_bound(f, occ_before, occ_after, inv_before, elec):
+    """First-order relative error bound of the Pfaffian hop ratio r = 1 + x . col per unit
+    relative error of the stored column col = A^-1[:, i]: (1 + sum |x| |col|) / |r|
+    times cond_1(A), per walker (x_j = F[s', occ_j] - F[s, occ_j], x_i = 0)."""
+    out = np.empty(len(elec))
+    for w in range(len(elec)):
+        i = int(elec[w, 0])
+        o = occ_before[w]
+        x = f[occ_after[w][i], o] - f[o[i], o]
+        x[i] = 0.0
+        col = inv_before[w][:, i]
+        a = f[np.ix_(o, o)]
+        cond = np.linalg.norm(a, 1) * np.linalg.norm(inv_before[w], 1)
+        out[w] = pf_ratio_bound(x, col, 1.0 + x @ col) * cond
+    return out
+
+
+def pf_bound_fn(f):
+    """bound_fn for run_chain on Pfaffian chains."""
+    def fn(t, chain, k, elec, slot, cw):
+        after = chain.book.proposed(k, elec, slot)
+        return pf_hop_bound(f, chain.occ_before[cw], after[cw], chain.inv_before[cw], elec[cw])
     return fn

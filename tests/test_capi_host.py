@@ -196,38 +196,34 @@ def classes_of(*cls):
     return arr
 
 
-def test_window_plan_is_heaviest_first():
+def test_window_work_bytes():
     lib = lrx._lib
     sts = [fake_state(W=3, n=64, k_max=4, delay=4, dtype=lrx.LRX_F32),
-           fake_state(W=2, n=256, k_max=4, delay=8, dtype=lrx.LRX_F32),
-           fake_state(W=4, n=128, k_max=4, delay=4, dtype=lrx.LRX_F32),
-           fake_state(W=1, n=256, k_max=4, delay=2, dtype=lrx.LRX_F32)]
+           fake_state(W=200, n=256, k_max=4, delay=8, dtype=lrx.LRX_F32)]
     arr = classes_of(*[fake_class(s) for s in sts])
-    order = (ctypes.c_int32 * 20)()
-    count = ctypes.c_int32()
-    assert lib.lrx_window_plan(arr, 4, order, 20, ctypes.byref(count)) == lrx.LRX_OK
-    pairs = [(order[2 * i], order[2 * i + 1]) for i in range(count.value)]
-    assert pairs == [(1, 0), (1, 1), (3, 0), (2, 0), (2, 1), (2, 2), (2, 3), (0, 0), (0, 1), (0, 2)]
-    assert lib.lrx_window_plan(arr, 4, order, 9, ctypes.byref(count)) == lrx.LRX_EINVAL
+    out = ctypes.c_size_t()
+    assert lib.lrx_window_work_bytes(arr, 2, ctypes.byref(out)) == lrx.LRX_OK
+    assert out.value == 256           # one work counter, rounded up to 256 bytes
+    assert lib.lrx_window_work_bytes(arr, 2, None) == lrx.LRX_EINVAL
 
 
 def test_window_validation():
     lib = lrx._lib
     P2 = ctypes.c_void_p(0x40000)
 
-    def call(arr, n_cls, steps=4, mode=lrx.LRX_MH_FORCE, n_items=None, grid=8):
-        if n_items is None:
-            n_items = sum(arr[i].state.contents.shape.walkers for i in range(n_cls))
-        return lib.lrx_det_window(arr, n_cls, steps, mode, 1, 0, P2, n_items, P2, grid, None)
+    def call(arr, n_cls, steps=4, mode=lrx.LRX_MH_FORCE, work_bytes=4096, grid=8, work=P2):
+        return lib.lrx_det_window(arr, n_cls, steps, mode, 1, 0, work, work_bytes, grid, None)
 
     ok = fake_state(W=4, n=64, k_max=4, delay=4, dtype=lrx.LRX_F32)
     base = fake_class(ok)
-    assert lib.lrx_det_window(None, 1, 4, lrx.LRX_MH_FORCE, 1, 0, P2, 4, P2, 8, None) == lrx.LRX_EINVAL
+    assert lib.lrx_det_window(None, 1, 4, lrx.LRX_MH_FORCE, 1, 0, P2, 4096, 8, None) == lrx.LRX_EINVAL
     assert call(classes_of(base), 0) == lrx.LRX_EINVAL
     assert call(classes_of(*[base] * 9), 9) == lrx.LRX_EINVAL
     assert call(classes_of(base), 1, steps=0) == lrx.LRX_EINVAL
+    assert call(classes_of(base), 1, steps=lrx.LRX_MAX_WINDOW_STEPS + 1) == lrx.LRX_EINVAL
     assert call(classes_of(base), 1, grid=0) == lrx.LRX_EINVAL
-    assert call(classes_of(base), 1, n_items=3) == lrx.LRX_EINVAL
+    assert call(classes_of(base), 1, work_bytes=2) == lrx.LRX_EINVAL        # the counter needs 4 bytes
+    assert call(classes_of(base), 1, work=None) == lrx.LRX_EINVAL
     assert call(classes_of(base), 1, mode=7) == lrx.LRX_EINVAL
     assert call(classes_of(fake_class(ok, null=("u01",))), 1, mode=lrx.LRX_MH_UNIFORMS) == lrx.LRX_EINVAL
     for f in ("table", "occ", "empty", "k", "elec", "slot", "u", "ratio", "accept"):
@@ -244,3 +240,23 @@ def test_window_validation():
     assert call(classes_of(fake_class(pf)), 1) == lrx.LRX_EKIND
     full = fake_state(W=4, n=64, k_max=4, delay=4, slot=4, dtype=lrx.LRX_F32)
     assert call(classes_of(fake_class(full)), 1) == lrx.LRX_ENEEDFLUSH
+
+
+def test_autotune_table():
+    """Byte-model defaults for an unknown size class; a stored entry replaces them."""
+    d = lrx.lrx_autotune_lookup(lrx.LRX_F32, 1000, 1)
+    assert d == {"delay": 32, "rows_per_block": 0, "wgs_per_cu": 2, "window": False,
+                 "tuned": False}                                       # sqrt(2000) = 44.7 -> 32
+    assert lrx.lrx_autotune_lookup(lrx.LRX_F64, 128, 1)["delay"] == 16   # the paper's det optimum T = 16
+    assert lrx.lrx_autotune_lookup(lrx.LRX_F32, 64, 8)["window"] is True
+    lrx.lrx_autotune_store(lrx.LRX_F32, 1000, 1, 8, 256, 3, 0)
+    assert lrx.lrx_autotune_lookup(lrx.LRX_F32, 1000, 1) == {"delay": 8, "rows_per_block": 256, "wgs_per_cu": 3,
+                                                            "window": False, "tuned": True}
+    lrx.lrx_autotune_store(lrx.LRX_F32, 1000, 1, 16, 0, 0, 1)
+    assert lrx.lrx_autotune_lookup(lrx.LRX_F32, 1000, 1)["delay"] == 16
+    with pytest.raises(lrx.LrxError):
+        lrx.lrx_autotune_store(lrx.LRX_F32, 1000, 8, 64, 0, 0)     # K k_max > 256
+    with pytest.raises(lrx.LrxError):
+        lrx.lrx_autotune_lookup(lrx.LRX_F32, 0, 1)
+    with pytest.raises(lrx.LrxError):
+        lrx.lrx_autotune_store(lrx.LRX_F32, 64, 1, 4, 8, 0)        # rows per block below 16

@@ -4,7 +4,7 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-from gpu_util import ratio_err, rel_err, run_chain, say
+from gpu_util import EPS32, EPS64, RatioTally, pf_ratio_bound, ratio_err, rel_err, run_chain, pf_bound_fn, say
 
 pytestmark = pytest.mark.gpu
 
@@ -66,7 +66,8 @@ def test_pf_chain(dt, n, K, W, steps):
     u01 = [gen.uniforms(g, W) for _ in range(steps)]
     wk = Walkers(lrx.LRX_PF, DT[dt], f, occ, emp, 1, K)
     chain = orc.PfChain(f, occ, emp)
-    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=4, tol_ratio=1e-10, tol_inv=1e-10)
+    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=4, tol_ratio=1e-10, tol_inv=1e-10,
+                                         bound_fn=pf_bound_fn(f), growth=lambda t: 1.0 + t)
     say(f"  max rel err ratio {worst_r:.2e} inverse {worst_m:.2e}")
     np.testing.assert_allclose(la, chain.logabs, atol=1e-8)
     np.testing.assert_allclose(ph, chain.phase, atol=1e-8)
@@ -85,6 +86,8 @@ def test_pf_fused_hop_step_matches_oracle(K):
     wk = Walkers(lrx.LRX_PF, torch.complex128, f, occ, emp, 1, K)
     chain = orc.PfChain(f, occ, emp)
     u01 = torch.zeros(5, dtype=torch.float64, device="cuda")
+    tally = RatioTally("pf fused hop")
+    bound = pf_bound_fn(f)
     for t in range(steps):
         k, elec, slot = gen.hop_draws(g, 5, 48, 48, (1,), 1)
         u = gen.uniforms(g, 5)
@@ -95,11 +98,14 @@ def test_pf_fused_hop_step_matches_oracle(K):
                              wk._slot, x_sep)
         wk.step_device(mode=lrx.LRX_MH_UNIFORMS, u01=u01)
         assert torch.equal(wk.u, x_sep), t
+        chain.inv_before, chain.occ_before = chain.inv.copy(), chain.book.occ.copy()
         r_orc = chain.propose(k, elec, slot)
-        assert ratio_err(wk.ratio.cpu().numpy(), r_orc).max() <= 1e-10, t
+        tally.check(wk.ratio.cpu().numpy(), r_orc, 1e-10, lambda: bound(t, chain, k, elec, slot, np.arange(5)),
+                    EPS64, 1.0 + t, where=f"step {t}")
         mask = orc.metropolis(r_orc, u)
         np.testing.assert_array_equal(wk.accept.cpu().numpy().astype(bool), mask)
         chain.accept(k, elec, slot, mask)
+    tally.report()
     np.testing.assert_array_equal(wk.occ.cpu().numpy(), chain.book.occ)
     np.testing.assert_array_equal(wk.empty.cpu().numpy(), chain.book.empty)
     assert rel_err(wk.inverse().cpu().numpy(), chain.inv, axis=(1, 2)).max() <= 1e-10
@@ -114,7 +120,8 @@ def test_pf_c64_bulk_error_is_bounded():
     u01 = [gen.uniforms(g, 4) for _ in range(steps)]
     wk = Walkers(lrx.LRX_PF, torch.complex64, f, occ, emp, 1, 8, refresh_period=20)
     chain = orc.PfChain(f, occ, emp)
-    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=10, tol_ratio=5e-3, tol_inv=5e-3)
+    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=10, tol_ratio=1e-4, tol_inv=5e-3,
+                                         bound_fn=pf_bound_fn(f), eps=EPS32, growth=lambda t: 1.0 + t % 20)
     say(f"  c64: max rel err ratio {worst_r:.2e} inverse {worst_m:.2e}")
 
 
@@ -131,31 +138,65 @@ def test_pf_refresh_report():
 
 def test_pfaffian_workload_full_size_sampled():
     """F = (G - G^T)/2 with G 1024x1024 CN(0,1), n = 512, 256 walkers, complex64 bulk,
-    K = 32, at full size; sampled walkers recomputed by the complex128 oracle."""
+    K = 32, over one whole refresh period (64 steps: two delay windows, then the
+    complex128 Parlett-Reid refresh) and a few steps past it.  Sampled walkers are
+    recomputed by the complex128 oracle: every ratio within 1e-4 relative or, where
+    above, within 8 eps32 (1 + steps since refresh) times its first-order bound
+    (counted); the inverses before the refresh within 8 eps32 (1 + 64) sqrt(n) cond."""
     wl = gen.WORKLOADS["pfaffian_n512_c64"]
     say(f"full-size {wl.name}")
     f, occ, emp, g = gen.pairing_inputs(wl)
     wk = Walkers(lrx.LRX_PF, torch.complex64, f, occ, emp, 1, wl.delay)
     book = orc.Occupancy(occ, emp)
     sample = np.array([0, 77, 255])
-    steps = wl.delay + 3
-    worst = 0.0
+    steps = wl.refresh + 4
+    check = set(range(0, wl.refresh, 8)) | {wl.delay - 1, wl.refresh - 1, wl.refresh, steps - 1}
+    tally = RatioTally("pfaffian full-size c64")
+    errs = []
     for t in range(steps):
         k, elec, slot = gen.hop_draws(g, wl.walkers, wl.n, wl.sites - wl.n, (1,), 1)
         wk.set_draws(k, elec, slot)
         r = wk.propose().cpu().numpy()
-        if t in (0, wl.delay - 1, steps - 1):
+        if t in check:
             prop = book.proposed(k, elec, slot)
-            la0, ph0 = orc.slogpf(orc.pairing_matrices(f, book.occ[sample]))
+            a0 = orc.pairing_matrices(f, book.occ[sample])
+            la0, ph0 = orc.slogpf(a0)
             la1, ph1 = orc.slogpf(orc.pairing_matrices(f, prop[sample]))
             ref = orc.ratio(la1, ph1, la0, ph0)
-            worst = max(worst, float(ratio_err(r[sample], ref).max()))
+            inv0 = orc.skew_inverse(a0)
+
+            def bound():
+                out = []
+                for j, w in enumerate(sample):
+                    i = int(elec[w, 0])
+                    o = book.occ[w]
+                    x = f[prop[w, i], o] - f[o[i], o]
+                    x[i] = 0.0
+                    col = inv0[j][:, i]
+                    cond = np.linalg.norm(a0[j], 1) * np.linalg.norm(inv0[j], 1)
+                    out.append(pf_ratio_bound(x, col, 1.0 + x @ col) * cond)
+                return np.array(out)
+            since = t % wl.refresh
+            er = tally.check(r[sample], ref, 1e-4, bound, EPS32, 1.0 + since, where=f"step {t}")
+            errs.append((since, float(er.max()), float(np.median(er))))
         mask = np.ones(wl.walkers, bool)
         wk.decide(mask=mask)
         wk.apply()
         book.commit(k, elec, slot, mask)
-    say(f"  c64 sampled ratio error {worst:.2e}")
-    assert worst < 1e-2
+        if t == wl.refresh - 1:
+            # the state just before the refresh, with every update of the period applied
+            inv = wk.inverse().cpu().numpy()[sample]
+            a_end = orc.pairing_matrices(f, book.occ[sample])
+            oinv = orc.skew_inverse(a_end)
+            cond = np.linalg.norm(a_end, 1, axis=(1, 2)) * np.linalg.norm(oinv, 1, axis=(1, 2))
+            e_inv = rel_err(inv, oinv, axis=(1, 2))
+            say(f"  inverse after {wl.refresh} steps (before the refresh): max {e_inv.max():.2e} "
+                f"median {np.median(e_inv):.2e}")
+            assert np.all(e_inv <= 8 * EPS32 * (1.0 + wl.refresh) * np.sqrt(wl.n) * cond), (e_inv, cond)
+            wk.refresh(report=False)
+    tally.report()
+    for since, emax, emed in errs:
+        say(f"  steps since refresh {since:3d}: ratio rel err max {emax:.2e} median {emed:.2e}")
     np.testing.assert_array_equal(wk.occ.cpu().numpy(), book.occ)
     m = wk.st.inv.cpu().numpy()
     assert np.array_equal(m, -np.swapaxes(m, 1, 2))

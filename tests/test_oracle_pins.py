@@ -481,6 +481,49 @@ def test_pf_gradient_formula_fd(oracle, cplx):
         assert abs(fd - 0.5 * p0 * inv[j, i]) <= 1e-7 * max(1, abs(p0))
 
 
+@pytest.mark.parametrize("cplx", [False, True])
+def test_lowrank_logpf_gradients_fd(oracle, cplx):
+    """log pf(F[occ][:, occ] - U J U^T) and its gradients with respect to U and to the
+    pairing matrix F (through the gather, skew directions), by central differences of the
+    Pfaffian itself, and the Pfaffian low-rank identity for the value (App. A, Eq.
+    pf_low_rank: pf(A - U J U^T) = pf(A) pf(J + U^T A^-1 U) / pf(J), with J^-1 = -J)."""
+    g = np.random.default_rng(51)
+    L, n, k, S = 12, 6, 2, 2
+    z = (lambda sh: g.standard_normal(sh) + 1j * g.standard_normal(sh)) if cplx else g.standard_normal
+    f = skew(z((L, L)))
+    occ = np.stack([np.sort(g.permutation(L)[:n]) for _ in range(S)])
+    u = 0.4 * z((S, n, 2 * k))
+    la, ph, gm, gu = oracle.lowrank_logpf_and_grads(f, occ, u)
+    jm = oracle.skew_eye(k)
+    a = oracle.pairing_matrices(f, occ)
+    for s in range(S):
+        # value by the low-rank identity, with brute-force perfect-matching Pfaffians
+        pa = brute.matching_pf(a[s].tolist())
+        pr = brute.matching_pf((jm + u[s].T @ np.linalg.inv(a[s]) @ u[s]).tolist())
+        pj = (-1) ** (k * (k - 1) // 2)
+        want = pa * pr / pj
+        assert abs(ph[s] * np.exp(la[s]) - want) <= 1e-10 * abs(want)
+
+    def logpf(f_, u_):
+        m = oracle.pairing_matrices(f_, occ) - u_ @ jm @ np.swapaxes(u_, -1, -2)
+        l_, p_ = oracle.slogpf(m)
+        return l_ + (np.log(p_) if cplx else 0)     # holomorphic log pf (real: log|pf|)
+
+    h = 1e-6
+    for (i, q) in [(0, 0), (3, 1), (5, 3), (2, 2)]:
+        d = np.zeros_like(u)
+        d[:, i, q] = h
+        fd = (logpf(f, u + d) - logpf(f, u - d)) / (2 * h)
+        np.testing.assert_allclose(fd, gu[:, i, q], atol=1e-7)
+    gf = np.stack([oracle.scatter_pairs(gm[s:s + 1], occ[s:s + 1], L) for s in range(S)])
+    for (p_, q_) in [(occ[0, 1], occ[0, 4]), (occ[1, 0], occ[1, 5]), (occ[0, 2], occ[1, 3])]:
+        d = np.zeros_like(f)
+        d[p_, q_] = h
+        d[q_, p_] = -h            # a skew direction keeps F skew
+        fd = (logpf(f + d, u) - logpf(f - d, u)) / (2 * h)
+        np.testing.assert_allclose(fd, gf[:, p_, q_] - gf[:, q_, p_], atol=1e-7)
+
+
 def test_metropolis_rule(oracle):
     r = np.array([2.0, 0.5, -0.5, 0.0, np.nan, 1j])
     u = np.array([0.99, 0.24, 0.26, 0.0, 0.0, 0.5])
@@ -498,3 +541,49 @@ def test_occupancy_hop_semantics(oracle):
     book.commit(k, elec, slot, np.array([True]))
     np.testing.assert_array_equal(book.occ, [[6, 2, 3]])
     np.testing.assert_array_equal(book.empty, [[1, 5, 4, 0]])
+
+
+@pytest.mark.parametrize("kind", ["det", "pf"])
+def test_chain_partial_accept_mask(oracle, kind):
+    """A step with a mixed accept mask: every accepted walker's state is the inverse and
+    log-magnitude of the matrix gathered at its new occupancy (checked by the residual
+    A_new A^-1 = I and by LAPACK's slogdet, not by the oracle's own routines), and every
+    rejected walker's state is bitwise unchanged (Sec. II.A / III.A: a rejected proposal
+    leaves A^-1 and the tracked value alone)."""
+    from paper_2602_05255_amd import inputs as gen
+    g = gen.generator(3100 + (kind == "pf"))
+    n, L, W = 10, 24, 9
+    if kind == "det":
+        table = gen.normal(g, (L, n), True)
+        occ, emp = gen.occupancy(g, W, L, n)
+        chain = oracle.DetChain(table, occ, emp)
+    else:
+        table = gen.skew_from(gen.normal(g, (L, L), True))
+        occ, emp = gen.occupancy(g, W, L, n)
+        chain = oracle.PfChain(table, occ, emp)
+    for t in range(6):
+        k, elec, slot = gen.hop_draws(g, W, n, L - n, (1,) if kind == "pf" else (1, 2), 1 if kind == "pf" else 2)
+        mask = g.random(W) < 0.5
+        mask[t % W] = True
+        mask[(t + 1) % W] = False
+        inv0, la0, ph0 = chain.inv.copy(), chain.logabs.copy(), chain.phase.copy()
+        occ0 = chain.book.occ.copy()
+        chain.propose(k, elec, slot)
+        chain.accept(k, elec, slot, mask)
+        for w in range(W):
+            if not mask[w]:
+                assert np.array_equal(chain.inv[w], inv0[w]) and chain.logabs[w] == la0[w]
+                assert chain.phase[w] == ph0[w] and np.array_equal(chain.book.occ[w], occ0[w])
+                continue
+            o = chain.book.occ[w]
+            a = table[o] if kind == "det" else table[np.ix_(o, o)]
+            resid = np.abs(a @ chain.inv[w] - np.eye(n)).max()
+            assert resid <= 1e-10 * np.linalg.cond(a), (t, w, resid)
+            sg, lg = np.linalg.slogdet(a)
+            want = lg if kind == "det" else 0.5 * lg
+            assert abs(chain.logabs[w] - want) <= 1e-10 * max(1.0, abs(want)), (t, w)
+            if kind == "pf":
+                assert np.array_equal(chain.inv[w], -chain.inv[w].T)
+                assert abs(chain.phase[w] ** 2 - sg) <= 1e-10     # pf^2 = det (App. A)
+            else:
+                assert abs(chain.phase[w] - sg) <= 1e-10
