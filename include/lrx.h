@@ -310,6 +310,27 @@ int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps,
                    int32_t mode, uint64_t seed, uint64_t counter,
                    void *work, size_t work_bytes, int32_t grid, void *stream);
 
+/* 32-bit words of the library's own window workspace (lrx_det_window_noalloc). */
+#define LRX_NOALLOC_SCRATCH_WORDS 64
+
+/*
+ * lrx_det_window for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same launch, with its work counter held by the library in a device array of
+ * its own (LRX_NOALLOC_SCRATCH_WORDS 32-bit words, 256 bytes, on every GPU the
+ * library runs on, kept until the process ends) instead of a caller
+ * workspace; the launch needs no more than that at any batch size.  It calls
+ * no allocation routine; the array's device address is looked up once per
+ * device on the first call made with that device current.  The call clears
+ * the counter before the launch (with a fill kernel, so it can be recorded in
+ * a HIP graph), so consecutive calls need nothing in between; calls that
+ * overlap on one GPU (different streams, or threads, without ordering) share
+ * the array and race.  Arguments and errors as for lrx_det_window.
+ */
+int lrx_det_window_noalloc(lrx_window_class *classes, int32_t n_classes, int32_t steps,
+                           int32_t mode, uint64_t seed, uint64_t counter, int32_t grid,
+                           void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tuning table                                                             */
 /* ------------------------------------------------------------------------ */

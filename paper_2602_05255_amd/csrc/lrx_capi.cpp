@@ -604,13 +604,14 @@ int lrx_window_work_bytes(const lrx_window_class *classes, int32_t n_classes, si
     return LRX_OK;
 }
 
-int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps, int32_t mode, uint64_t seed,
-                   uint64_t counter, void *work, size_t work_bytes, int32_t grid, void *stream) {
+static int det_window_impl(lrx_window_class *classes, int32_t n_classes, int32_t steps, int32_t mode,
+                           uint64_t seed, uint64_t counter, void *work, size_t work_bytes, int32_t grid,
+                           void *stream, bool own_counters) {
     int64_t total = 0;
     int rc = window_check(classes, n_classes, &total);
     if (rc) return rc;
-    if (steps < 1 || steps > LRX_MAX_WINDOW_STEPS || grid < 1 || !work) return LRX_EINVAL;
-    if (work_bytes < sizeof(uint32_t)) return LRX_EINVAL;
+    if (steps < 1 || steps > LRX_MAX_WINDOW_STEPS || grid < 1 || (!own_counters && !work)) return LRX_EINVAL;
+    if (!own_counters && work_bytes < sizeof(uint32_t)) return LRX_EINVAL;
     if (mode != LRX_MH_UNIFORMS && mode != LRX_MH_DEVICE_RNG && mode != LRX_MH_FORCE && mode != LRX_MH_MASK)
         return LRX_EINVAL;
     for (int c = 0; c < n_classes; ++c)
@@ -667,12 +668,27 @@ int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps, 
     wa.n_classes = n_classes;
     wa.steps = steps;
     wa.walkers = (int)total;
-    wa.queue = static_cast<uint32_t *>(work);
+    if (own_counters) {
+        rc = hip_rc(window_scratch(&wa.queue));
+        if (rc) return rc;
+    } else {
+        wa.queue = static_cast<uint32_t *>(work);
+    }
     rc = hip_rc(det_window(dtype, wa, grid, lds, as_stream(stream)));
     if (rc == LRX_OK)
         for (int c = 0; c < n_classes; ++c)
             classes[c].state->slot = (classes[c].state->slot + steps) % classes[c].state->shape.delay;
     return rc;
+}
+
+int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps, int32_t mode, uint64_t seed,
+                   uint64_t counter, void *work, size_t work_bytes, int32_t grid, void *stream) {
+    return det_window_impl(classes, n_classes, steps, mode, seed, counter, work, work_bytes, grid, stream, false);
+}
+
+int lrx_det_window_noalloc(lrx_window_class *classes, int32_t n_classes, int32_t steps, int32_t mode,
+                           uint64_t seed, uint64_t counter, int32_t grid, void *stream) {
+    return det_window_impl(classes, n_classes, steps, mode, seed, counter, nullptr, 0, grid, stream, true);
 }
 
 // ------------------------------------------------------------------ tuning table

@@ -123,6 +123,9 @@ struct WindowArgs {
     uint32_t *queue;         // work counter (cleared by the launch)
 };
 size_t window_lds_bytes(int dtype, int KM, int K, int nch_max);
+// Device address, on the current device, of the library's own window work
+// counter (LRX_NOALLOC_SCRATCH_WORDS words), looked up once per device.
+hipError_t window_scratch(uint32_t **out);
 hipError_t det_window(int dtype, const WindowArgs &a, int grid, size_t lds, hipStream_t s);
 
 // Init / refresh (lrx_factor.hip).

@@ -13,6 +13,8 @@
 // walker's flush runs as 64-column strips in the same work-group.  The size
 // class picks the row-chunk specialisation of the step functions shared with
 // the per-step kernels.
+#include <mutex>
+
 #include "lrx_det_impl.hpp"
 #include "lrx_flush_impl.hpp"
 
@@ -150,9 +152,36 @@ template <class T> size_t window_lds_k(int KM, int K, int nch_max) {
     return 0;
 }
 
+// The work counter of lrx_det_window_noalloc, held by the library on every
+// device it runs on (until the process ends).  Host code never passes
+// `scratch` itself: its device address comes from hipGetSymbolAddress, once per
+// device.
+static __device__ __align__(256) uint32_t scratch[LRX_NOALLOC_SCRATCH_WORDS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kMaxDevices];
+
 }  // namespace
 
 namespace lrx {
+
+hipError_t window_scratch(uint32_t **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<uint32_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 size_t window_lds_bytes(int dtype, int KM, int K, int nch_max) {
     switch (dtype) {

@@ -32,6 +32,7 @@ LRX_MH_UNIFORMS, LRX_MH_DEVICE_RNG, LRX_MH_FORCE, LRX_MH_MASK = 0, 1, 2, 3
 LRX_MAX_N, LRX_MAX_KMAX_DET, LRX_MAX_KMAX_PF, LRX_MAX_DELAY = 1024, 8, 1, 64
 LRX_MAX_CLASSES = 8
 LRX_MAX_WINDOW_STEPS = 256
+LRX_NOALLOC_SCRATCH_WORDS = 64
 
 DTYPE_CODE = {torch.float32: LRX_F32, torch.float64: LRX_F64,
               torch.complex64: LRX_C64, torch.complex128: LRX_C128}
@@ -111,6 +112,8 @@ _SIGS = {
     "lrx_hop_commit": ([_I, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "lrx_autotune_store": ([_I, _I, _I, ctypes.POINTER(lrx_tune)], ctypes.c_int),
     "lrx_autotune_lookup": ([_I, _I, _I, ctypes.POINTER(lrx_tune)], ctypes.c_int),
+    "lrx_det_window_noalloc": ([ctypes.POINTER(lrx_window_class), _I, _I, _I, ctypes.c_uint64, ctypes.c_uint64,
+                                _I, _P], ctypes.c_int),
     "lrx_window_work_bytes": ([ctypes.POINTER(lrx_window_class), _I, ctypes.POINTER(ctypes.c_size_t)],
                               ctypes.c_int),
     "lrx_det_window": ([ctypes.POINTER(lrx_window_class), _I, _I, _I, ctypes.c_uint64, ctypes.c_uint64, _P,
@@ -523,6 +526,14 @@ def lrx_det_window(classes, steps, mode, seed, counter, work, grid, stream=None)
     _check(_lib.lrx_det_window(arr, len(classes), int(steps), int(mode), ctypes.c_uint64(seed),
                                ctypes.c_uint64(counter), _dev(work, "work"), int(work.numel()), int(grid),
                                _stream(stream)), "lrx_det_window")
+
+
+def lrx_det_window_noalloc(classes, steps, mode, seed, counter, grid, stream=None):
+    """lrx_det_window with the library's own counters (no workspace argument)."""
+    arr = _class_array(classes, steps)
+    _check(_lib.lrx_det_window_noalloc(arr, len(classes), int(steps), int(mode), ctypes.c_uint64(seed),
+                                       ctypes.c_uint64(counter), int(grid), _stream(stream)),
+           "lrx_det_window_noalloc")
 
 
 # ------------------------------------------------------------------ tuning table
