@@ -36,10 +36,12 @@ FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
 
-def counter_traffic(profile, sources, walkers_per_launch):
-    """HBM bytes per launch measured by the FETCH_SIZE / WRITE_SIZE counter passes
-    recorded in profiles/<profile>, or None when the kernel sources changed since or the
-    launch size differs."""
+def counter_traffic(profile, sources, walkers_per_launch, key=None):
+    """HBM bytes measured by the FETCH_SIZE / WRITE_SIZE counter passes recorded in
+    profiles/<profile>, or None when the kernel sources changed since.  With
+    walkers_per_launch: bytes per launch of that many walkers (None when the recorded
+    launch size differs); with key (walkers_per_launch None): bytes per walker of the
+    recorded launch configuration `key`."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -53,9 +55,13 @@ def counter_traffic(profile, sources, walkers_per_launch):
         part = line.strip().split(":", 1)
         if len(part) == 2:
             keys[part[0].strip()] = part[1].strip()
-    if keys.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in keys:
+    if keys.get("source_sha256") != h.hexdigest():
         return None
-    if keys.get("walkers_per_launch") != str(int(walkers_per_launch)):
+    if key is not None:
+        if keys.get("launch_config") != key or "traffic_bytes_per_walker" not in keys:
+            return None
+        return float(keys["traffic_bytes_per_walker"])
+    if "traffic_bytes_per_launch" not in keys or keys.get("walkers_per_launch") != str(int(walkers_per_launch)):
         return None
     return float(keys["traffic_bytes_per_launch"])
 
@@ -86,6 +92,10 @@ def parse():
     ap.add_argument("--sizes", default=None, help="n-sweep sizes, comma separated (default 64,...,1024)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload: the uneven batch only, without the other configurations")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="uneven batch: set-up and the event-timed roofline pass only (for kernel traces)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -187,6 +197,27 @@ def queue_filler(torch, ms=150.0):
         a = a @ a
 
 
+def filled_pass(torch, fn, ms=100.0, tries=4):
+    """fn() enqueues a pass whose launches carry HIP event pairs.  The pass is queued
+    behind a GEMM filler so that the GPU is still busy when the host has finished
+    enqueueing it: then no event pair brackets host launch time.  If the filler had
+    drained by then (its end event complete), the pass is repeated behind a filler
+    twice as long.  Returns (fn's result, filler ms, True if the last try stayed
+    covered)."""
+    out = None
+    for _ in range(tries):
+        queue_filler(torch, ms)
+        mark = torch.cuda.Event()
+        mark.record()
+        out = fn()
+        drained = mark.query()
+        torch.cuda.synchronize()
+        if not drained:
+            return out, ms, True
+        ms *= 2.0
+    return out, ms / 2.0, False
+
+
 def measure(wl, dtype, walkers, args, torch, label):
     run = Run(wl, dtype, walkers, streams=args.streams)
     elem = torch.empty((), dtype=dtype).element_size()
@@ -196,9 +227,13 @@ def measure(wl, dtype, walkers, args, torch, label):
     # pair brackets host launch time.
     run.period()
     torch.cuda.synchronize()
-    queue_filler(torch)
-    timer = EventTimer(torch)
-    run.period(timer)
+
+    def timed_period():
+        timer = EventTimer(torch)
+        run.period(timer)
+        return timer
+
+    timer, _, covered = filled_pass(torch, timed_period)
     res = timer.results()
     acc = res["accept"]
     bytes_tot = sum(accept_bytes(wl, elem, wp, tau) for tau, _, wp in acc)
@@ -494,38 +529,57 @@ def bench_single_hop(n, args, torch, walkers=1024):
 
 
 def bench_adjoint(wl, args, torch):
-    """Forward + hand-written backward of log det(Phi[occ] + B C^T) for all samples."""
+    """Forward + hand-written backward of log det(Phi[occ] + B C^T) for all 512 samples
+    (complex64 bulk), from the samples' walker state (the checkpoint: factorised once, as a
+    sampler holds it) and, for comparison, with a fresh complex128 factorisation of every
+    A_s = Phi[occ_s] inside each step."""
     from paper_2602_05255_amd import inputs as gen
-    from paper_2602_05255_amd.adjoint import lowrank_logdet
+    from paper_2602_05255_amd import lrx
+    from paper_2602_05255_amd.adjoint import lowrank_logdet, walker_lowrank_logdet
+    from paper_2602_05255_amd.walkers import Walkers
     phi, occ, b, c, w = gen.lowrank_inputs(wl)
     dev = "cuda"
+    L = phi.shape[0]
+    emp = np.stack([np.setdiff1d(np.arange(L), o) for o in occ]).astype(np.int32)
+    wk = Walkers(lrx.LRX_DET, torch.complex64, phi, occ, emp)
     P = torch.tensor(phi, dtype=torch.complex128, device=dev, requires_grad=True)
     B = torch.tensor(b, dtype=torch.complex64, device=dev, requires_grad=True)
     C = torch.tensor(c, dtype=torch.complex64, device=dev, requires_grad=True)
     occ_t = torch.as_tensor(occ, dtype=torch.int32, device=dev)
     wt = torch.as_tensor(w, dtype=torch.complex128, device=dev)
 
-    def one():
-        ld, _ = lowrank_logdet(P, B, C, occ_t, torch.complex64)
-        loss = (wt * ld).real.sum()
-        loss.backward()
-        return loss
+    def from_state():
+        ld, _ = walker_lowrank_logdet(wk, B, C, P)
+        (wt * ld).real.sum().backward()
 
-    for _ in range(args.warmup):
-        one()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    def with_init():
+        ld, _ = lowrank_logdet(P, B, C, occ_t, torch.complex64)
+        (wt * ld).real.sum().backward()
+
+    out = {}
+    for name, fn in (("from_state", from_state), ("with_factorisation", with_init)):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out[name] = {"ms_per_step": ms, "samples_per_s": occ.shape[0] / (ms * 1e-3)}
     S, n = occ.shape
-    return {"metric": "samples/s (log det + hand-written backward)", "value": S / dt, "unit": "samples/s",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
-            "data": "synthetic", "config": {"workload": wl.name, "samples": S, "n": n, "sites": phi.shape[0],
-                                            "rank": b.shape[-1]},
-            "note": "includes the complex128 factorisation of every A_s = Phi[occ_s] (init) in each step"}
+    log(f"  [adjoint] fwd+bwd from the walker state {out['from_state']['ms_per_step']:.2f} ms; with the "
+        f"factorisation {out['with_factorisation']['ms_per_step']:.2f} ms (512 samples)")
+    return {"metric": "samples/s (log det + hand-written backward)", "value": out["from_state"]["samples_per_s"],
+            "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": out["from_state"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+            "config": {"workload": wl.name, "samples": S, "n": n, "sites": L, "rank": b.shape[-1]},
+            "modes": out,
+            "note": "from_state: the forward reads A^-1 from the samples' walker state (the checkpoint); "
+                    "with_factorisation: a complex128 Gauss-Jordan factorisation of every A_s in each step"}
 
 
 def bench_uneven(wl, args, torch):
@@ -569,9 +623,12 @@ def bench_uneven(wl, args, torch):
         n = classes[i]["n"]
         wn = gen.Workload(f"uneven_n{n}", "det", 2 * n, n, d.W, wl.ranks, wl.k_max, plan[i]["delay"], P,
                           False, "f32")
-        queue_filler(torch, 60.0)
-        timer = EventTimer(torch)
-        d.period(timer)
+        def timed_period():
+            timer = EventTimer(torch)
+            d.period(timer)
+            return timer
+
+        timer, _, covered = filled_pass(torch, timed_period)
         res = timer.results()
         acc = res["accept"]
         byt = sum(accept_bytes(wn, es, wp, tau) for tau, _, wp in acc)
@@ -580,19 +637,23 @@ def bench_uneven(wl, args, torch):
         per_class[n] = {"schedule": "per-step", "delay": plan[i]["delay"], "rows_per_block": plan[i]["rows_per_block"],
                         "accept_us": tt / len(acc) * 1e6, "accept_gbs": byt / tt / 1e9,
                         "accept_bytes_per_launch": byt / len(acc), "accept_total_ms": tt * 1e3,
+                        "accept_launches": len(acc), "walkers_per_launch": d.W / len(d.parts),
+                        "events_covered": covered,
                         "propose_total_ms": sum(dt for _, dt, _ in res["propose"]) * 1e3,
                         "flush_total_ms": sum(dt for _, dt, _ in fl) * 1e3,
                         "refresh_total_ms": sum(dt for _, dt, _ in res.get("refresh", [])) * 1e3}
     if batch.uw is not None:
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(P // K + 2)]
-        queue_filler(torch, 60.0)
-        ev[0].record()
-        for i in range(P // K):
-            batch._window(i, lrx.LRX_MH_FORCE)
-            ev[i + 1].record()
-        batch.uw.refresh(report=False)
-        ev[-1].record()
-        torch.cuda.synchronize()
+        def timed_windows():
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(P // K + 2)]
+            ev[0].record()
+            for i in range(P // K):
+                batch._window(i, lrx.LRX_MH_FORCE)
+                ev[i + 1].record()
+            batch.uw.refresh(report=False)
+            ev[-1].record()
+            return ev
+
+        ev, _, _ = filled_pass(torch, timed_windows)
         win = [ev[i].elapsed_time(ev[i + 1]) * 1e-3 for i in range(P // K)]
         wbytes = 0.0
         for p in batch.uw.parts:
@@ -604,6 +665,8 @@ def bench_uneven(wl, args, torch):
             "delays": [int(p.st.delay) for p in batch.uw.parts], "grid": batch.uw.grid,
             "window_ms": float(np.mean(win)) * 1e3, "window_gbs": wbytes / float(np.mean(win)) / 1e9,
             "refresh_ms": ev[P // K].elapsed_time(ev[-1])}
+    if args.roofline_only:
+        return {"roofline_pass": per_class}
     # the whole period in one HIP graph
     s_ = torch.cuda.Stream()
     s_.wait_stream(torch.cuda.current_stream())
@@ -672,10 +735,15 @@ def bench_uneven(wl, args, torch):
                        "substreams_per_step_class": 4, "window_steps": K},
             "per_class": per_class, "rel_error": err}
     if dom is not None:
+        wpl = dom["walkers_per_launch"]
+        tw = counter_traffic(f"det_accept_kernel_{wl.name}_counters.md", DET_SOURCES, None,
+                             key=f"n{dom_n}_K{dom['delay']}_rows{dom['rows_per_block']}")
         line["roofline"] = {"bound": "hbm", "kernel": f"det_accept_kernel (delayed, FP32, n={dom_n})",
                             "achieved": dom["accept_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": dom["accept_gbs"] / HBM_PEAK_GBS, "traffic": None,
-                            "avg_us": dom["accept_us"], "bytes_per_launch": dom["accept_bytes_per_launch"]}
+                            "frac": dom["accept_gbs"] / HBM_PEAK_GBS,
+                            "traffic": tw * wpl if tw is not None else None,
+                            "avg_us": dom["accept_us"], "bytes_per_launch": dom["accept_bytes_per_launch"],
+                            "walkers_per_launch": wpl, "events_covered": dom["events_covered"]}
     else:
         wc = per_class["window_classes"]
         line["roofline"] = {"bound": "hbm", "kernel": "det_window_kernel", "achieved": wc["window_gbs"],
@@ -827,11 +895,17 @@ def main():
     # Default: the uneven batch is the headline; every other configuration rides along.
     t_start = time.time()
     res = bench_uneven(wl, args, torch)
+    if args.roofline_only:
+        print(json.dumps({"workload": wl.name, **res}), flush=True)
+        return
     torch.cuda.empty_cache()
     extras = {"rel_error": res["rel_error"], "per_class": res["per_class"]}
     short = with_steps(args, max(3, args.steps // 4), max(1, min(args.warmup, 2)))
     c2 = gen.WORKLOADS["slater_n256_k124"]
     cfg = {}
+    if args.headline_only:
+        print(json.dumps(headline_line(res, args, extras)), flush=True)
+        return
     cfg["slater_n256_k124"] = run_extra("slater_n256_k124", lambda: {
         "f64": bench_uniform(c2, torch.float64, short, torch, "f64", streams=4, recompute_leg=not args.no_recompute),
         "f32": bench_uniform(c2, torch.float32, short, torch, "f32", streams=4)})

@@ -85,7 +85,7 @@ enum {
 /* Limits. */
 #define LRX_MAX_N 1024
 #define LRX_MAX_KMAX_DET 8
-#define LRX_MAX_KMAX_PF 1
+#define LRX_MAX_KMAX_PF 4      /* k_max > 1: plain states (delay 0) for the general updates */
 #define LRX_MAX_DELAY 64
 
 /* Metropolis modes for lrx_metropolis. */
@@ -104,7 +104,7 @@ typedef struct lrx_shape {
     int32_t dtype;    /* bulk dtype of inv/fa/fb and of the update vectors   */
     int32_t walkers;  /* W >= 1                                               */
     int32_t n;        /* matrix dimension, 1..LRX_MAX_N (PF: even)            */
-    int32_t k_max;    /* largest rank per step (DET 1..8, PF 1)               */
+    int32_t k_max;    /* largest rank per step (DET 1, 2, 4, 8; PF 1, 2, 4)    */
     int32_t delay;    /* K: 0 = plain update every step, else 1..LRX_MAX_DELAY */
 } lrx_shape;
 
@@ -545,6 +545,60 @@ int lrx_pf_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int32
  *   g: wide [W] cotangent of log pf; dA: bulk [W][n][n] out.
  */
 int lrx_pf_grad(const lrx_state *st, const void *g, void *dA, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* General low-rank updates (plain form: states with delay 0)               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Ratio of a general determinant update A_1 = A_0 + v u^T given as the mixed
+ * dense / one-hot tuples of Sec. II.B ("Matrix updates"):
+ *   u = [xu_0 .. xu_{kr-1} | e_{eu_0} .. e_{eu_{kc-1}}],
+ *   v = [e_{ev_0} .. e_{ev_{kr-1}} | xv_0 .. xv_{kc-1}],
+ * so row ev_c of A gains xu_c (c < kr) and column eu_e gains xv_e (e < kc): rank-kr
+ * row updates (kc = 0), rank-kc column updates (kr = 0), or both at once
+ * (simultaneous row + column update; a row and column that cross add both at the
+ * crossing).  r = det(I_k + u^T A^-1 v), k = kr + kc <= k_max (Eqs. det_ratio,
+ * det_R).  A dense v column costs one pass over the inverse (A^-1 xv); one-hot
+ * entries cost O(n).  Stashes A^-1 v and R^-1 for the accept.
+ *   ev: int32 [W][kr]; xu: bulk [W][kr][n]; eu: int32 [W][kc]; xv: bulk [W][kc][n];
+ *   ratio: wide [W] out.  The same kr and kc for every walker.
+ * States with delay > 0: LRX_EUNSUPPORTED.  An index out of range sets
+ * LRX_FLAG_BADINDEX and a zero ratio.
+ */
+int lrx_det_propose_general(lrx_state *st, int32_t kr, const int32_t *ev, const void *xu,
+                            int32_t kc, const int32_t *eu, const void *xv, void *ratio,
+                            void *stream);
+
+/*
+ * Apply a general determinant update to the walkers with accept[w] != 0 (Woodbury,
+ * Eq. det_inv): A_1^-T = A^-T - (A^-T u) R^-T (A^-1 v)^T in one pass over the rows
+ * of the stored A^-T; logabs += log|r|, phase *= r/|r|.  Same arguments as the
+ * propose; accept in/out as for lrx_det_accept_update.
+ */
+int lrx_det_accept_general(lrx_state *st, int32_t kr, const int32_t *ev, const void *xu,
+                           int32_t kc, const int32_t *eu, const void *xv, uint8_t *accept,
+                           void *stream);
+
+/*
+ * Ratio of a general Pfaffian update of k rows and k columns (Sec. III.B,
+ * "update of 2 rows and 2 columns" and its k-fold form): A_1 = A_0 - u J u^T with
+ *   u = [x_0 .. x_{k-1} | e_{cols_0} .. e_{cols_{k-1}}],  J the 2k x 2k skew identity,
+ * r = pf(R) / pf(J), R = J + u^T A^-1 u (Eqs. pf_ratio, pf_R), 1 <= k <= k_max <= 4.
+ * The dense-dense entries x_c^T A^-1 x_d need one pass over the inverse
+ * (A^-1 x); R is made exactly skew and its Pfaffian taken by Parlett-Reid.
+ *   cols: int32 [W][k]; x: bulk [W][k][n]; ratio: wide [W] out.
+ */
+int lrx_pf_propose_general(lrx_state *st, int32_t k, const int32_t *cols, const void *x,
+                           void *ratio, void *stream);
+
+/*
+ * Apply a general Pfaffian update (Eq. pf_inv): A_1^-1 = A^-1 + Z R^-1 Z^T with
+ * Z = A^-1 u, computed entry by entry from the ordered index pair so the inverse
+ * stays exactly skew.  Same arguments as the propose.
+ */
+int lrx_pf_accept_general(lrx_state *st, int32_t k, const int32_t *cols, const void *x,
+                          uint8_t *accept, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Markov-chain helpers                                                     */

@@ -262,6 +262,48 @@ def lowrank_logdet_and_grads(phi, occ, b, c):
     return la, ph, g, g @ np.asarray(c), inv @ np.asarray(b)
 
 
+def det_general_matrix(a, ev, xu, eu, xv):
+    """A_1 = A_0 + v u^T for the mixed dense / one-hot tuples of Sec. II.B ("Matrix
+    updates"): u = [xu | e_eu], v = [e_ev | xv], assembled as dense n x k matrices
+    and multiplied out.  a [W][n][n]; ev [W][kr], xu [W][kr][n]; eu [W][kc], xv [W][kc][n]
+    (kr or kc may be 0)."""
+    a = np.asarray(a)
+    W, n, _ = a.shape
+    kr = 0 if ev is None else np.asarray(ev).shape[1]
+    kc = 0 if eu is None else np.asarray(eu).shape[1]
+    cplx = np.iscomplexobj(a) or (kr and np.iscomplexobj(np.asarray(xu))) or (kc and np.iscomplexobj(np.asarray(xv)))
+    out = a.astype(np.complex128 if cplx else np.float64)
+    for w in range(W):
+        u = np.zeros((n, kr + kc), dtype=out.dtype)
+        v = np.zeros_like(u)
+        for c in range(kr):
+            u[:, c] = xu[w][c]
+            v[ev[w][c], c] = 1.0
+        for e in range(kc):
+            u[eu[w][e], kr + e] = 1.0
+            v[:, kr + e] = xv[w][e]
+        out[w] = out[w] + v @ u.T
+    return out
+
+
+def pf_general_matrix(a, cols, x):
+    """A_1 = A_0 - u J u^T with u = [x | e_cols] (Sec. III.B, update of k rows and k
+    columns), assembled as a dense n x 2k matrix and multiplied out."""
+    a = np.asarray(a)
+    x = np.asarray(x)
+    W, n, _ = a.shape
+    k = np.asarray(cols).shape[1]
+    jm = skew_eye(k)
+    out = a.copy()
+    for w in range(W):
+        u = np.zeros((n, 2 * k), dtype=np.result_type(a, x))
+        for c in range(k):
+            u[:, c] = x[w][c]
+            u[cols[w][c], k + c] = 1.0
+        out[w] = a[w] - u @ jm @ u.T
+    return out
+
+
 def skew_eye(k):
     """The 2k x 2k skew identity J = [[0, 1], [-1, 0]] (blocks of size k) of Sec. III.A."""
     j = np.zeros((2 * k, 2 * k))

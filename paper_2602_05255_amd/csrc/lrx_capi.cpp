@@ -22,8 +22,12 @@ Layout stash_layout(const lrx_shape &s) {
     const int KA = pf ? 2 * KM : KM;
     Layout L;
     size_t off = 0;
-    L.c = (uint32_t)off; off += al256((size_t)(pf ? 1 : KM) * n * es);
-    L.rinv = (uint32_t)off; off += al256((size_t)KM * KM * es);
+    // C: the gathered columns (DET) or A^-1 u (PF, 2 k_max of them, the general updates)
+    L.c = (uint32_t)off; off += al256((size_t)(pf ? 2 * KM : KM) * n * es);
+    // R^-1 held square at the next power of two of its size (the general updates' tiles)
+    int p2 = 1;
+    while (p2 < (pf ? 2 * KM : KM)) p2 <<= 1;
+    L.rinv = (uint32_t)off; off += al256((size_t)p2 * p2 * es);
     L.g = (uint32_t)off; off += al256((size_t)(K > 0 ? K : 1) * KA * (pf ? 1 : KM) * es);
     L.ratio = (uint32_t)off; off += al256(16);
     L.kslot = (uint32_t)off; off += al256((size_t)(K > 0 ? K : 1) * 4);
@@ -68,8 +72,10 @@ static int check_shape(const lrx_shape *s) {
         if ((size_t)s->k_max * s->delay * s->k_max * es > 49152) return LRX_EUNSUPPORTED;
     } else {
         if (s->n & 1) return LRX_EODD;
-        if (s->k_max != 1) return LRX_EUNSUPPORTED;
-        if (s->n < 2) return LRX_ESHAPE;
+        // k_max > 1 serves the general k-row/k-column updates, which have no delayed form
+        if (s->k_max != 1 && s->k_max != 2 && s->k_max != 4) return LRX_EUNSUPPORTED;
+        if (s->k_max > 1 && s->delay > 0) return LRX_EUNSUPPORTED;
+        if (s->n < 2 * s->k_max) return LRX_ESHAPE;
     }
     return LRX_OK;
 }
@@ -689,6 +695,91 @@ int lrx_det_window(lrx_window_class *classes, int32_t n_classes, int32_t steps, 
 int lrx_det_window_noalloc(lrx_window_class *classes, int32_t n_classes, int32_t steps, int32_t mode,
                            uint64_t seed, uint64_t counter, int32_t grid, void *stream) {
     return det_window_impl(classes, n_classes, steps, mode, seed, counter, nullptr, 0, grid, stream, true);
+}
+
+// ------------------------------------------------------------------ general updates
+static GeneralArgs general_args(lrx_state *st) {
+    GeneralArgs a;
+    memset(&a, 0, sizeof(a));
+    const Layout L = stash_layout(st->shape);
+    a.W = st->shape.walkers;
+    a.n = st->shape.n;
+    a.inv = st->inv;
+    a.stash = static_cast<uint8_t *>(st->stash);
+    a.stride = L.stride;
+    a.off_c = L.c;
+    a.off_rinv = L.rinv;
+    a.off_ratio = L.ratio;
+    a.flags = st->flags;
+    a.logabs = st->logabs;
+    a.phase = st->phase;
+    return a;
+}
+
+static int general_check(const lrx_state *st, int kind, int32_t k1, int32_t k2) {
+    int rc = check_kind(st, kind);
+    if (rc) return rc;
+    if (st->shape.delay != 0) return LRX_EUNSUPPORTED;        // plain form only
+    if (k1 < 0 || k2 < 0 || k1 + k2 < 1 || k1 + k2 > st->shape.k_max) return LRX_ESHAPE;
+    return LRX_OK;
+}
+
+int lrx_det_propose_general(lrx_state *st, int32_t kr, const int32_t *ev, const void *xu, int32_t kc,
+                            const int32_t *eu, const void *xv, void *ratio, void *stream) {
+    int rc = general_check(st, LRX_DET, kr, kc);
+    if (rc) return rc;
+    if (!ratio || (kr && (!ev || !xu)) || (kc && (!eu || !xv))) return LRX_EINVAL;
+    GeneralArgs a = general_args(st);
+    a.kr = kr;
+    a.kc = kc;
+    a.ev = ev;
+    a.xu = xu;
+    a.eu = eu;
+    a.xv = xv;
+    a.ratio = ratio;
+    return hip_rc(general_update(LRX_DET, st->shape.dtype, a, true, as_stream(stream)));
+}
+
+int lrx_det_accept_general(lrx_state *st, int32_t kr, const int32_t *ev, const void *xu, int32_t kc,
+                           const int32_t *eu, const void *xv, uint8_t *accept, void *stream) {
+    int rc = general_check(st, LRX_DET, kr, kc);
+    if (rc) return rc;
+    if (!accept || (kr && (!ev || !xu)) || (kc && (!eu || !xv))) return LRX_EINVAL;
+    GeneralArgs a = general_args(st);
+    a.kr = kr;
+    a.kc = kc;
+    a.ev = ev;
+    a.xu = xu;
+    a.eu = eu;
+    a.xv = xv;
+    a.accept = accept;
+    return hip_rc(general_update(LRX_DET, st->shape.dtype, a, false, as_stream(stream)));
+}
+
+int lrx_pf_propose_general(lrx_state *st, int32_t k, const int32_t *cols, const void *x, void *ratio,
+                           void *stream) {
+    int rc = general_check(st, LRX_PF, k, 0);
+    if (rc) return rc;
+    if (!cols || !x || !ratio) return LRX_EINVAL;
+    GeneralArgs a = general_args(st);
+    a.kr = k;
+    a.ev = cols;
+    a.xu = x;
+    a.ratio = ratio;
+    return hip_rc(general_update(LRX_PF, st->shape.dtype, a, true, as_stream(stream)));
+}
+
+int lrx_pf_accept_general(lrx_state *st, int32_t k, const int32_t *cols, const void *x, uint8_t *accept,
+                          void *stream) {
+    int rc = general_check(st, LRX_PF, k, 0);
+    if (rc) return rc;
+    if (!cols || !x || !accept) return LRX_EINVAL;
+    GeneralArgs a = general_args(st);
+    a.kr = k;
+    a.ev = cols;
+    a.xu = x;
+    a.accept = accept;
+    return hip_rc(general_update(LRX_PF, st->shape.dtype, a, false, as_stream(stream)));
 }
 
 // ------------------------------------------------------------------ tuning table

@@ -283,6 +283,41 @@ __device__ void small_lu_det_inv(T (&r)[KM * KM], int k, T (&inv)[KM * KM],
     }
 }
 
+// Pfaffian of a small skew matrix held by one thread (m x m, stride N, m even),
+// by Parlett-Reid elimination in pairs (Appendix A): for columns j = 0, 2, ...
+// bring the largest |a[i][j]|, i > j, to row and column j + 1 (a swap flips the
+// sign), multiply by the pivot a[j][j+1], and remove the pair with the rank-2
+// skew update a[p][q] += w_p c_q - c_p w_q (c = a[j][q] / pivot, w = a[j+1][q]).
+template <class T, int N>
+__device__ void small_pf(T (&a)[N * N], int m, typename Wide<T>::type &pf) {
+    using W = typename Wide<T>::type;
+    W acc = one<W>();
+    for (int j = 0; j + 1 < m; j += 2) {
+        int p = j + 1;
+        double best = absv(a[(j + 1) * N + j]);
+        for (int i = j + 2; i < m; ++i) {
+            const double v = absv(a[i * N + j]);
+            if (v > best) { best = v; p = i; }
+        }
+        if (p != j + 1) {
+            for (int c = 0; c < m; ++c) { T t = a[(j + 1) * N + c]; a[(j + 1) * N + c] = a[p * N + c]; a[p * N + c] = t; }
+            for (int r = 0; r < m; ++r) { T t = a[r * N + j + 1]; a[r * N + j + 1] = a[r * N + p]; a[r * N + p] = t; }
+            acc = -acc;
+        }
+        const T piv = a[j * N + j + 1];
+        if (is_zero(piv)) { pf = zero<W>(); return; }
+        acc = acc * conv<W>(piv);
+        for (int q = j + 2; q < m; ++q) {
+            const T cq = divv(a[j * N + q], piv), wq = a[(j + 1) * N + q];
+            for (int pp = j + 2; pp < m; ++pp) {
+                const T cp = divv(a[j * N + pp], piv), wp = a[(j + 1) * N + pp];
+                a[pp * N + q] = fmsc(cp, wq, fmac(wp, cq, a[pp * N + q]));
+            }
+        }
+    }
+    pf = acc;
+}
+
 // ---------------------------------------------------------------- log|r|, phase
 __device__ __forceinline__ void accum_logphase(double r, double *logabs, double *phase) {
     *logabs += log(fabs(r));

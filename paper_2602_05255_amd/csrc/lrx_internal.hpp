@@ -128,6 +128,22 @@ size_t window_lds_bytes(int dtype, int KM, int K, int nch_max);
 hipError_t window_scratch(uint32_t **out);
 hipError_t det_window(int dtype, const WindowArgs &a, int grid, size_t lds, hipStream_t s);
 
+// General low-rank updates in the plain form (lrx_general.hip).
+struct GeneralArgs {
+    int W, n, kr, kc;               // DET: kr dense-row / kc dense-column tuples; PF: kr = k
+    void *inv;
+    uint8_t *stash;
+    uint32_t stride, off_c, off_rinv, off_ratio;
+    const int32_t *ev, *eu;         // DET: ev [W][kr] rows, eu [W][kc] columns; PF: ev [W][k]
+    const void *xu, *xv;            // DET: xu [W][kr][n], xv [W][kc][n]; PF: xu = x [W][k][n]
+    void *ratio;                    // wide [W]
+    uint8_t *accept;
+    uint32_t *flags;
+    double *logabs;
+    void *phase;
+};
+hipError_t general_update(int kind, int dtype, const GeneralArgs &a, bool propose, hipStream_t s);
+
 // Init / refresh (lrx_factor.hip).
 struct FactorArgs {
     int kind, dtype, W, n, sites;

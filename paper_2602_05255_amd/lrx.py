@@ -29,7 +29,7 @@ LRX_DET, LRX_PF = 0, 1
 LRX_F32, LRX_F64, LRX_C64, LRX_C128 = 0, 1, 2, 3
 LRX_FLAG_SINGULAR_R, LRX_FLAG_NONFINITE, LRX_FLAG_SINGULAR_A, LRX_FLAG_BADINDEX = 1, 2, 4, 8
 LRX_MH_UNIFORMS, LRX_MH_DEVICE_RNG, LRX_MH_FORCE, LRX_MH_MASK = 0, 1, 2, 3
-LRX_MAX_N, LRX_MAX_KMAX_DET, LRX_MAX_KMAX_PF, LRX_MAX_DELAY = 1024, 8, 1, 64
+LRX_MAX_N, LRX_MAX_KMAX_DET, LRX_MAX_KMAX_PF, LRX_MAX_DELAY = 1024, 8, 4, 64
 LRX_MAX_CLASSES = 8
 LRX_MAX_WINDOW_STEPS = 256
 LRX_NOALLOC_SCRATCH_WORDS = 64
@@ -107,6 +107,10 @@ _SIGS = {
     "lrx_pf_accept_hop": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _I, _P, ctypes.c_uint64, ctypes.c_uint64,
                            _P, _P, _P, _I, _P], ctypes.c_int),
     "lrx_pf_flush_delayed": ([ctypes.POINTER(lrx_state), _P], ctypes.c_int),
+    "lrx_det_propose_general": ([ctypes.POINTER(lrx_state), _I, _P, _P, _I, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_det_accept_general": ([ctypes.POINTER(lrx_state), _I, _P, _P, _I, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_pf_propose_general": ([ctypes.POINTER(lrx_state), _I, _P, _P, _P, _P], ctypes.c_int),
+    "lrx_pf_accept_general": ([ctypes.POINTER(lrx_state), _I, _P, _P, _P, _P], ctypes.c_int),
     "lrx_metropolis": ([ctypes.POINTER(lrx_state), _P, _P, ctypes.c_uint64, ctypes.c_uint64, _I, _P, _P],
                        ctypes.c_int),
     "lrx_hop_commit": ([_I, _I, _I, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -451,6 +455,51 @@ def lrx_pf_flush_delayed(st: State, stream=None):
 
 
 # ------------------------------------------------------------------ chain helpers
+def _general_det_args(st, ev, xu, eu, xv):
+    kr = 0 if ev is None else int(ev.shape[1])
+    kc = 0 if eu is None else int(eu.shape[1])
+    pev = _dev(ev, "ev", torch.int32, (st.walkers, kr), allow_none=True) if kr else None
+    pxu = _dev(xu, "xu", st.dtype, (st.walkers, kr, st.n), allow_none=True) if kr else None
+    peu = _dev(eu, "eu", torch.int32, (st.walkers, kc), allow_none=True) if kc else None
+    pxv = _dev(xv, "xv", st.dtype, (st.walkers, kc, st.n), allow_none=True) if kc else None
+    return kr, pev, pxu, kc, peu, pxv
+
+
+def lrx_det_propose_general(st: State, ev, xu, eu, xv, ratio, stream=None):
+    """ev: int32 [W][kr] rows, xu [W][kr][n] (or both None); eu: int32 [W][kc] columns,
+    xv [W][kc][n] (or both None)."""
+    kr, pev, pxu, kc, peu, pxv = _general_det_args(st, ev, xu, eu, xv)
+    _dev(ratio, "ratio", st.wide, (st.walkers,))
+    _check(_lib.lrx_det_propose_general(st.ptr(), kr, pev, pxu, kc, peu, pxv, _dev(ratio, "ratio"),
+                                        _stream(stream)), "lrx_det_propose_general")
+
+
+def lrx_det_accept_general(st: State, ev, xu, eu, xv, accept, stream=None):
+    kr, pev, pxu, kc, peu, pxv = _general_det_args(st, ev, xu, eu, xv)
+    _dev(accept, "accept", torch.uint8, (st.walkers,))
+    _check(_lib.lrx_det_accept_general(st.ptr(), kr, pev, pxu, kc, peu, pxv, _dev(accept, "accept"),
+                                       _stream(stream)), "lrx_det_accept_general")
+
+
+def lrx_pf_propose_general(st: State, cols, x, ratio, stream=None):
+    """cols: int32 [W][k]; x: [W][k][n]."""
+    k = int(cols.shape[1])
+    _dev(cols, "cols", torch.int32, (st.walkers, k))
+    _dev(x, "x", st.dtype, (st.walkers, k, st.n))
+    _dev(ratio, "ratio", st.wide, (st.walkers,))
+    _check(_lib.lrx_pf_propose_general(st.ptr(), k, _dev(cols, "cols"), _dev(x, "x"), _dev(ratio, "ratio"),
+                                       _stream(stream)), "lrx_pf_propose_general")
+
+
+def lrx_pf_accept_general(st: State, cols, x, accept, stream=None):
+    k = int(cols.shape[1])
+    _dev(cols, "cols", torch.int32, (st.walkers, k))
+    _dev(x, "x", st.dtype, (st.walkers, k, st.n))
+    _dev(accept, "accept", torch.uint8, (st.walkers,))
+    _check(_lib.lrx_pf_accept_general(st.ptr(), k, _dev(cols, "cols"), _dev(x, "x"), _dev(accept, "accept"),
+                                      _stream(stream)), "lrx_pf_accept_general")
+
+
 def lrx_metropolis(st: State, ratio, u01, seed, counter, mode, accept, stream=None):
     _dev(ratio, "ratio", st.wide, (st.walkers,))
     pu = _dev(u01, "u01", torch.float64, (st.walkers,), allow_none=True)

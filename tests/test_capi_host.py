@@ -64,6 +64,8 @@ def test_state_sizes_pf():
     assert s["fa"] == 256 * 32 * 2 * 512 * 8
     assert s["fb"] == 256 * 32 * 4 * 8
     assert s["work"] >= 256 * 512 * 512 * 16
+    g = lrx.lrx_state_sizes(lrx.LRX_PF, lrx.LRX_C128, 4, 64, 4, 0)     # general k-row/k-column updates
+    assert g["stash_stride"] >= 8 * 64 * 16 + 8 * 8 * 16
 
 
 @pytest.mark.parametrize("args,code", [
@@ -79,7 +81,9 @@ def test_state_sizes_pf():
     ((5, lrx.LRX_F64, 4, 8, 1, 0), lrx.LRX_EUNSUPPORTED),
     ((lrx.LRX_DET, lrx.LRX_C128, 4, 1024, 8, 0), lrx.LRX_EUNSUPPORTED),  # LDS panel limit
     ((lrx.LRX_PF, lrx.LRX_C64, 4, 7, 1, 0), lrx.LRX_EODD),
-    ((lrx.LRX_PF, lrx.LRX_C64, 4, 8, 2, 0), lrx.LRX_EUNSUPPORTED),
+    ((lrx.LRX_PF, lrx.LRX_C64, 4, 8, 3, 0), lrx.LRX_EUNSUPPORTED),    # k_max 1, 2 or 4
+    ((lrx.LRX_PF, lrx.LRX_C64, 4, 8, 2, 4), lrx.LRX_EUNSUPPORTED),    # general Pfaffian states are plain
+    ((lrx.LRX_PF, lrx.LRX_C64, 4, 6, 4, 0), lrx.LRX_ESHAPE),          # 2 k_max > n
 ])
 def test_state_sizes_rejects(args, code):
     with pytest.raises(lrx.LrxError) as e:

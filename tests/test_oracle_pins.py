@@ -524,6 +524,56 @@ def test_lowrank_logpf_gradients_fd(oracle, cplx):
         np.testing.assert_allclose(fd, gf[:, p_, q_] - gf[:, q_, p_], atol=1e-7)
 
 
+# ----------------------------------------------------------------------------
+# General update forms (Sec. II.B and III.B, "Matrix updates")
+# ----------------------------------------------------------------------------
+def test_det_general_update_forms_match_the_displayed_matrices(oracle):
+    """The oracle's A_1 - A_0 for the displayed examples of Sec. II.B: rank-1 row, rank-1
+    column, rank-2 row and the simultaneous row + column update (row 1 gains u, column 2
+    gains v, the crossing gets u_2 + v_1)."""
+    z = np.zeros((1, 4, 4))
+    u = np.array([2.0, 3.0, 5.0, 7.0])
+    v = np.array([11.0, 13.0, 17.0, 19.0])
+    d = oracle.det_general_matrix(z, [[1]], [[u]], None, None)[0]
+    want = np.zeros((4, 4))
+    want[1] = u
+    np.testing.assert_array_equal(d, want)
+    d = oracle.det_general_matrix(z, None, None, [[2]], [[v]])[0]
+    want = np.zeros((4, 4))
+    want[:, 2] = v
+    np.testing.assert_array_equal(d, want)
+    u2 = np.array([[2.0, 3.0, 5.0, 7.0], [23.0, 29.0, 31.0, 37.0]])
+    d = oracle.det_general_matrix(z, [[1, 3]], [u2], None, None)[0]
+    want = np.zeros((4, 4))
+    want[1], want[3] = u2[0], u2[1]
+    np.testing.assert_array_equal(d, want)
+    d = oracle.det_general_matrix(z, [[1]], [[u]], [[2]], [[v]])[0]
+    want = np.array([[0, 0, 11, 0], [2, 3, 5 + 13, 7], [0, 0, 17, 0], [0, 0, 19, 0]], dtype=float)
+    np.testing.assert_array_equal(d, want)
+
+
+def test_pf_general_update_forms_match_the_displayed_matrices(oracle):
+    """The oracle's A_1 - A_0 = -u J u^T for the displayed examples of Sec. III.B: 1 row
+    and 1 column (u = (x, e_1)) and 2 rows and 2 columns (u = (x_0, x_1, e_1, e_3))."""
+    z = np.zeros((1, 4, 4))
+    x = np.array([2.0, 3.0, 5.0, 7.0])
+    d = oracle.pf_general_matrix(z, [[1]], [[x]])[0]
+    want = np.array([[0, -2, 0, 0], [2, 0, 5, 7], [0, -5, 0, 0], [0, -7, 0, 0]], dtype=float)
+    np.testing.assert_array_equal(d, want)
+    z6 = np.zeros((1, 6, 6))
+    u0 = np.array([2.0, 3.0, 5.0, 7.0, 11.0, 13.0])
+    u1 = np.array([17.0, 19.0, 23.0, 29.0, 31.0, 37.0])
+    d = oracle.pf_general_matrix(z6, [[1, 3]], [[u0, u1]])[0]
+    want = np.array([
+        [0, -u0[0], 0, -u1[0], 0, 0],
+        [u0[0], 0, u0[2], u0[3] - u1[1], u0[4], u0[5]],
+        [0, -u0[2], 0, -u1[2], 0, 0],
+        [u1[0], u1[1] - u0[3], u1[2], 0, u1[4], u1[5]],
+        [0, -u0[4], 0, -u1[4], 0, 0],
+        [0, -u0[5], 0, -u1[5], 0, 0]])
+    np.testing.assert_array_equal(d, want)
+
+
 def test_metropolis_rule(oracle):
     r = np.array([2.0, 0.5, -0.5, 0.0, np.nan, 1j])
     u = np.array([0.99, 0.24, 0.26, 0.0, 0.0, 0.5])
