@@ -33,9 +33,11 @@
  *         (the one a row-i update needs) is the contiguous row i of M.
  *         PF : M = A^-1 row-major, kept exactly skew-symmetric.
  *         Bulk dtype, [W][n][n].  With delay K > 0 it holds A_0^-1 of the
- *         current delay window (Sec. II.C / III.C).
+ *         current delay window (Sec. II.C / III.C).  LRX_LAYOUT_PACKED: the
+ *         upper tiles only (see LRX_LAYOUT_* below).
  * fa    : delayed factors a_t (DET Eq. det_a, PF Eq. pf_a), stored as columns:
- *         [W][K*KA][n] with KA = k_max (DET) or 2*k_max (PF).
+ *         [W][K*KA][n] with KA = k_max (DET) or 2*k_max (PF); K is the slot
+ *         capacity: the delay, or 2 (FUSED) / 1 (PACKED).
  * fb    : DET: b_t (Eq. det_b) as rows, [W][n][K*k_max];
  *         PF : R_t^-1 (2k x 2k), [W][K][2k_max][2k_max].
  * stash : per-walker scratch written by propose and read by accept
@@ -56,7 +58,7 @@
 extern "C" {
 #endif
 
-#define LRX_VERSION 1
+#define LRX_VERSION 2
 
 /* Return codes. */
 enum {
@@ -96,6 +98,39 @@ enum {
     LRX_MH_MASK = 3       /* lrx_det_window only: accept[] holds the caller's decision */
 };
 
+/*
+ * Storage layouts and update schemes (lrx_shape.layout).
+ *
+ * LRX_LAYOUT_FULL  : inv holds the whole n x n matrix; plain (delay 0) or
+ *                    delayed (delay K) updates as described above.
+ * LRX_LAYOUT_FUSED : PF, delay 0, k_max 1.  The plain update of Eq. pf_inv
+ *                    (k = 1) with a delay of one accepted step fused into the
+ *                    next pass: the state holds M0 and at most one pending
+ *                    rank-2 update (a, R^-1) per walker (the delayed form of
+ *                    Eq. pf_delayed_Ainv with one slot), and an accepted step
+ *                    makes ONE pass over M0 that adds the pending update to
+ *                    every row (exactly skew, from the ordered index pair),
+ *                    writes the row back and takes its dot with the new x in
+ *                    the same pass.  HBM per accepted step: 2 n^2 elements
+ *                    instead of 3 n^2.
+ * LRX_LAYOUT_PACKED: as LRX_LAYOUT_FUSED, with inv holding only the tiles on
+ *                    and above the diagonal (skewness of A^-1, Sec. III.A):
+ *                    64 x 64 row-major tiles (I <= J) of the n x n matrix,
+ *                    tile (I, J) at tile index I*nt - I*(I-1)/2 + (J - I),
+ *                    nt = ceil(n / 64), element (r, c) of the tile at
+ *                    r * 64 + c; entries past n are zero; diagonal tiles hold
+ *                    the whole (exactly skew) 64 x 64 block.  HBM per accepted
+ *                    step: about n^2 elements (read and write of one triangle).
+ * For FUSED / PACKED states st->slot is 0 (nothing pending) or 1 (slot 0 may
+ * hold each walker's pending update; a walker that rejected keeps its own);
+ * accept sets it to 1, flush_delayed applies the pending updates and sets it to
+ * 0.  Refresh needs st->slot == 0 (LRX_ENEEDFLUSH otherwise).  The low-rank,
+ * gradient and general-update entry points take LRX_LAYOUT_FULL states only
+ * (LRX_EUNSUPPORTED).  lrx_pf_read_inverse returns A^-1 for every layout.
+ */
+enum { LRX_LAYOUT_FULL = 0, LRX_LAYOUT_FUSED = 1, LRX_LAYOUT_PACKED = 2 };
+#define LRX_PACK_TILE 64
+
 /* Largest number of size classes in one lrx_det_window call. */
 #define LRX_MAX_CLASSES 8
 
@@ -106,6 +141,8 @@ typedef struct lrx_shape {
     int32_t n;        /* matrix dimension, 1..LRX_MAX_N (PF: even)            */
     int32_t k_max;    /* largest rank per step (DET 1, 2, 4, 8; PF 1, 2, 4)    */
     int32_t delay;    /* K: 0 = plain update every step, else 1..LRX_MAX_DELAY */
+    int32_t layout;   /* LRX_LAYOUT_*: storage and update scheme (PF only for
+                         anything but LRX_LAYOUT_FULL)                        */
 } lrx_shape;
 
 typedef struct lrx_sizes {     /* bytes; every buffer 256-byte aligned by the caller */
@@ -507,6 +544,17 @@ int lrx_pf_accept_hop(lrx_state *st, const int32_t *k, const int32_t *cols,
  * sets st->slot = 0.
  */
 int lrx_pf_flush_delayed(lrx_state *st, void *stream);
+
+/*
+ * A^-1 of every walker of a Pfaffian state in any layout, as the state stands:
+ * M0 (unpacked for LRX_LAYOUT_PACKED) plus the live delayed or pending slots,
+ * sum_t a_t R_t^-1 a_t^T (Eq. pf_delayed_Ainv), without changing the state.
+ * Entry (q, j) is computed on the ordered pair and negated below the diagonal,
+ * so the output is exactly skew.
+ *   out: device, bulk dtype [W][n][n] row-major (caller-owned, written whole).
+ * Errors: LRX_EINVAL (null out), LRX_EKIND (DET state).
+ */
+int lrx_pf_read_inverse(const lrx_state *st, void *out, void *stream);
 
 /*
  * log pf M_w for M_w = A_w - U_w J U_w^T (Sec. III.A: the general low-rank

@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "liblrx.so")
 # (source, object name, extra flags); the determinant kernels build once per bulk dtype.
 SOURCES = [("lrx_capi.cpp", "lrx_capi", []), ("lrx_pf.hip", "lrx_pf", []), ("lrx_flush.hip", "lrx_flush", []),
            ("lrx_factor.hip", "lrx_factor", []), ("lrx_adjoint.hip", "lrx_adjoint", []),
-           ("lrx_window.hip", "lrx_window", []), ("lrx_general.hip", "lrx_general", [])] + \
+           ("lrx_window.hip", "lrx_window", []), ("lrx_general.hip", "lrx_general", []),
+           ("lrx_pf_fused.hip", "lrx_pf_fused", [])] + \
           [("lrx_det.hip", f"lrx_det_{i}", [f"-DLRX_DT={i}"]) for i in range(4)]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

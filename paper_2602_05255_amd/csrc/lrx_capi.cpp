@@ -1,6 +1,7 @@
 // C ABI of liblrx: host-side validation, buffer sizing and kernel dispatch.
 // Every check here runs on the host before anything is enqueued, so the error
 // paths are testable without a GPU.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -17,7 +18,7 @@ static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 Layout stash_layout(const lrx_shape &s) {
     const size_t es = bulk_bytes(s.dtype);
-    const int n = s.n, KM = s.k_max, K = s.delay;
+    const int n = s.n, KM = s.k_max, K = slot_capacity(s);
     const bool pf = s.kind == LRX_PF;
     const int KA = pf ? 2 * KM : KM;
     Layout L;
@@ -51,6 +52,10 @@ static int check_shape(const lrx_shape *s) {
     if (s->dtype < LRX_F32 || s->dtype > LRX_C128) return LRX_EUNSUPPORTED;
     if (s->walkers < 1 || s->n < 1 || s->n > LRX_MAX_N) return LRX_ESHAPE;
     if (s->delay < 0 || s->delay > LRX_MAX_DELAY) return LRX_ESHAPE;
+    if (s->layout < LRX_LAYOUT_FULL || s->layout > LRX_LAYOUT_PACKED) return LRX_EUNSUPPORTED;
+    // the fused and packed layouts: single-hop plain Pfaffian updates
+    if (s->layout != LRX_LAYOUT_FULL && (s->kind != LRX_PF || s->delay != 0 || s->k_max != 1))
+        return LRX_EUNSUPPORTED;
     const size_t es = bulk_bytes(s->dtype);
     if (s->kind == LRX_DET) {
         if (s->k_max != 1 && s->k_max != 2 && s->k_max != 4 && s->k_max != 8) return LRX_ESHAPE;
@@ -90,8 +95,10 @@ static StepArgs step_args(const lrx_state *st) {
     a.W = st->shape.walkers;
     a.n = st->shape.n;
     a.KM = st->shape.k_max;
-    a.K = st->shape.delay;
+    a.K = slot_capacity(st->shape);
     a.tau = st->slot;
+    a.layout = st->shape.layout;
+    a.part = st->work;
     a.aligned = ((size_t)st->shape.n * bulk_bytes(st->shape.dtype)) % 16 == 0 ? 1 : 0;
     a.inv = st->inv;
     a.fa = st->fa;
@@ -131,12 +138,13 @@ int lrx_state_sizes(const lrx_shape *shape, lrx_sizes *out) {
     int rc = check_shape(shape);
     if (rc) return rc;
     if (!out) return LRX_EINVAL;
-    const size_t W = shape->walkers, n = shape->n, K = shape->delay, KM = shape->k_max;
+    const size_t W = shape->walkers, n = shape->n, K = slot_capacity(*shape), KM = shape->k_max;
     const size_t es = bulk_bytes(shape->dtype);
     const bool pf = shape->kind == LRX_PF;
+    const bool packed = shape->layout == LRX_LAYOUT_PACKED;
     const size_t KA = pf ? 2 * KM : KM;
     memset(out, 0, sizeof(*out));
-    out->inv = W * n * n * es;
+    out->inv = W * (packed ? pk_elems(shape->n) : n * n) * es;
     out->fa = W * K * KA * n * es;
     out->fb = pf ? W * K * KA * KA * es : W * n * K * KM * es;
     const Layout L = stash_layout(*shape);
@@ -146,6 +154,8 @@ int lrx_state_sizes(const lrx_shape *shape, lrx_sizes *out) {
     out->phase = W * wide_bytes(shape->dtype);
     out->flags = W * 4;
     out->work = factor_work_bytes(shape->kind, shape->dtype, shape->walkers, shape->n);
+    // packed: the accept pass keeps its per-tile partial dots [W][tiles][2][64] in the workspace
+    if (packed) out->work = std::max(out->work, W * (size_t)pk_tiles(shape->n) * 2 * LRX_PACK_TILE * es);
     return LRX_OK;
 }
 
@@ -154,8 +164,9 @@ int lrx_validate(const lrx_state *st) {
     int rc = check_shape(&st->shape);
     if (rc) return rc;
     if (!st->inv || !st->stash || !st->logabs || !st->phase || !st->flags || !st->work) return LRX_EINVAL;
-    if (st->shape.delay > 0 && (!st->fa || !st->fb)) return LRX_EINVAL;
-    if (st->slot < 0 || st->slot > st->shape.delay) return LRX_EINVAL;
+    if (slot_capacity(st->shape) > 0 && (!st->fa || !st->fb)) return LRX_EINVAL;
+    const int max_slot = st->shape.layout != LRX_LAYOUT_FULL ? 1 : st->shape.delay;
+    if (st->slot < 0 || st->slot > max_slot) return LRX_EINVAL;
     return LRX_OK;
 }
 
@@ -174,7 +185,7 @@ static int factor_common(lrx_state *st, int kind, const void *src, int32_t sites
         if (kind == LRX_DET && sites < 1) return LRX_ESHAPE;
         if (kind == LRX_PF && sites < st->shape.n) return LRX_ESHAPE;
     }
-    if (refresh && st->shape.delay > 0 && st->slot != 0) return LRX_ENEEDFLUSH;
+    if (refresh && st->slot != 0) return LRX_ENEEDFLUSH;     // delayed or pending updates not flushed
     FactorArgs a;
     a.kind = kind;
     a.dtype = st->shape.dtype;
@@ -190,6 +201,7 @@ static int factor_common(lrx_state *st, int kind, const void *src, int32_t sites
     a.flags = st->flags;
     a.report = refresh ? report : nullptr;
     a.refresh = refresh;
+    a.packed = st->shape.layout == LRX_LAYOUT_PACKED ? 1 : 0;
     rc = hip_rc(factor(a, as_stream(stream)));
     if (rc == LRX_OK) st->slot = 0;
     return rc;
@@ -344,6 +356,7 @@ int lrx_det_flush_delayed(lrx_state *st, void *stream) {
 static int lowrank_check(const lrx_state *st, int32_t r, int kind) {
     int rc = check_kind(st, kind);
     if (rc) return rc;
+    if (st->shape.layout != LRX_LAYOUT_FULL) return LRX_EUNSUPPORTED;
     if (kind == LRX_DET && (r < 1 || r > 8 || r > st->shape.n)) return LRX_ESHAPE;
     if (kind == LRX_PF && (r < 2 || r > 8 || (r & 1) || r > st->shape.n)) return LRX_ESHAPE;
     if (st->shape.delay > 0 && st->slot == st->shape.delay) return LRX_ENEEDFLUSH;
@@ -470,9 +483,22 @@ int lrx_pf_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int32
 int lrx_pf_grad(const lrx_state *st, const void *g, void *dA, void *stream) {
     int rc = check_kind(st, LRX_PF);
     if (rc) return rc;
+    if (st->shape.layout != LRX_LAYOUT_FULL) return LRX_EUNSUPPORTED;
     if (st->shape.delay > 0 && st->slot != 0) return LRX_ENEEDFLUSH;
     if (!g || !dA) return LRX_EINVAL;
     return hip_rc(pf_grad(st->shape.dtype, st->inv, g, dA, st->shape.walkers, st->shape.n, as_stream(stream)));
+}
+
+// Plain / delayed accept (lrx_pf.hip) or the fused pass of the FUSED and PACKED layouts.
+static int pf_accept_common(lrx_state *st, const StepArgs &a, void *stream) {
+    if (st->shape.layout != LRX_LAYOUT_FULL) {
+        const int rc = hip_rc(pf_fused_accept(st->shape.dtype, a, as_stream(stream)));
+        if (rc == LRX_OK) st->slot = 1;
+        return rc;
+    }
+    const int rc = hip_rc(pf_accept(st->shape.dtype, a, as_stream(stream)));
+    if (rc == LRX_OK && st->shape.delay > 0) st->slot += 1;
+    return rc;
 }
 
 int lrx_pf_propose_ratio(lrx_state *st, const int32_t *k, const int32_t *cols, const void *x, void *ratio,
@@ -500,9 +526,7 @@ int lrx_pf_accept_update(lrx_state *st, const int32_t *k, const int32_t *cols, c
     a.rows = cols;
     a.u = x;
     a.accept = accept;
-    rc = hip_rc(pf_accept(st->shape.dtype, a, as_stream(stream)));
-    if (rc == LRX_OK && st->shape.delay > 0) st->slot += 1;
-    return rc;
+    return pf_accept_common(st, a, stream);
 }
 
 int lrx_pf_propose_hop(lrx_state *st, const void *f, int32_t sites, const int32_t *occ, const int32_t *empty,
@@ -550,19 +574,26 @@ int lrx_pf_accept_hop(lrx_state *st, const int32_t *k, const int32_t *cols, cons
     a.u01 = u01;
     a.seed = seed;
     a.counter = counter;
-    rc = hip_rc(pf_accept(st->shape.dtype, a, as_stream(stream)));
-    if (rc == LRX_OK && st->shape.delay > 0) st->slot += 1;
-    return rc;
+    return pf_accept_common(st, a, stream);
 }
 
 int lrx_pf_flush_delayed(lrx_state *st, void *stream) {
     int rc = check_kind(st, LRX_PF);
     if (rc) return rc;
-    if (st->shape.delay == 0 || st->slot == 0) return LRX_OK;
+    if (st->slot == 0) return LRX_OK;
     StepArgs a = step_args(st);
-    rc = hip_rc(pf_flush(st->shape.dtype, a, as_stream(stream)));
+    if (st->shape.layout != LRX_LAYOUT_FULL) rc = hip_rc(pf_fused_flush(st->shape.dtype, a, as_stream(stream)));
+    else rc = hip_rc(pf_flush(st->shape.dtype, a, as_stream(stream)));
     if (rc == LRX_OK) st->slot = 0;
     return rc;
+}
+
+int lrx_pf_read_inverse(const lrx_state *st, void *out, void *stream) {
+    int rc = check_kind(st, LRX_PF);
+    if (rc) return rc;
+    if (!out) return LRX_EINVAL;
+    StepArgs a = step_args(st);
+    return hip_rc(pf_read_inverse(st->shape.dtype, a, out, as_stream(stream)));
 }
 
 int lrx_metropolis(const lrx_state *st, const void *ratio, const double *u01, uint64_t seed, uint64_t counter,
@@ -719,7 +750,7 @@ static GeneralArgs general_args(lrx_state *st) {
 static int general_check(const lrx_state *st, int kind, int32_t k1, int32_t k2) {
     int rc = check_kind(st, kind);
     if (rc) return rc;
-    if (st->shape.delay != 0) return LRX_EUNSUPPORTED;        // plain form only
+    if (st->shape.delay != 0 || st->shape.layout != LRX_LAYOUT_FULL) return LRX_EUNSUPPORTED;   // plain form only
     if (k1 < 0 || k2 < 0 || k1 + k2 < 1 || k1 + k2 > st->shape.k_max) return LRX_ESHAPE;
     return LRX_OK;
 }

@@ -341,6 +341,19 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nblocks) {
     return (b % nx) * per + (b / nx);
 }
 
+// ---------------------------------------------------------------- packed skew storage
+// The 64 x 64 tiles on and above the diagonal (I <= J) of an n x n skew matrix,
+// tile (I, J) at index I*nt - I*(I-1)/2 + (J - I) (nt = ceil(n / 64)), each
+// row-major.  pk_offset needs r / 64 <= c / 64.
+__device__ __forceinline__ size_t pk_offset(int nt, int r, int c) {
+    const int I = r >> 6, J = c >> 6;
+    return ((size_t)(I * nt - I * (I - 1) / 2 + (J - I)) << 12) + (size_t)((r & 63) << 6) + (size_t)(c & 63);
+}
+__device__ __forceinline__ size_t lrx_pk_elems_dev(int n) {
+    const int nt = (n + 63) >> 6;
+    return (size_t)(nt * (nt + 1) / 2) << 12;
+}
+
 // ---------------------------------------------------------------- 16-byte IO
 template <class T> constexpr int vec16() { return (int)(16 / sizeof(T)); }
 

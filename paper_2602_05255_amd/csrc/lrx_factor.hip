@@ -91,6 +91,7 @@ struct FA {              // device-side argument block
     uint32_t *flags;
     double *report;
     int refresh;
+    int packed;
 };
 
 template <class Wd> __device__ __forceinline__ Wd *wX(const FA &a, int w) {
@@ -1048,7 +1049,13 @@ __global__ __launch_bounds__(kT) void final_pf_kernel(FA a, int tiles) {
     const int n = a.n;
     const Wd *X = wX<Wd>(a, w);
     const int *src = wSrc(a, w);
-    T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
+    // Full storage, or the packed upper 64 x 64 tiles (LRX_LAYOUT_PACKED): entry
+    // (i, j), i <= j by tile, at pk_offset; the lower triangle is kept only inside
+    // diagonal tiles.
+    const int nt = (n + 63) >> 6;
+    T *M = static_cast<T *>(a.inv) + (size_t)w * (a.packed ? lrx_pk_elems_dev(n) : (size_t)n * n);
+    auto at = [&](int r, int c) -> T * { return a.packed ? M + pk_offset(nt, r, c) : M + (size_t)r * n + c; };
+    const bool lower_kept = !a.packed || ti / 2 == tj / 2;      // (j, i) stored: 32-tile pair inside one 64-tile
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = ti * 32 + r, j = tj * 32 + tx;
@@ -1065,16 +1072,16 @@ __global__ __launch_bounds__(kT) void final_pf_kernel(FA a, int tiles) {
             const Wd h = half_of(t1[r][tx] - t2[tx][r]);
             const Wd nh = -h;
             if (a.report) {
-                const Wd o1 = conv<Wd>(M[(size_t)i * n + j]);
-                const Wd o2 = conv<Wd>(M[(size_t)j * n + i]);
+                const Wd o1 = conv<Wd>(*at(i, j));
+                const Wd o2 = lower_kept ? conv<Wd>(*at(j, i)) : -o1;
                 dsq += abs2(o1 - h) + abs2(o2 - nh);
                 nsq += 2.0 * abs2(h);
             }
-            M[(size_t)i * n + j] = conv<T>(h);
-            M[(size_t)j * n + i] = conv<T>(nh);
+            *at(i, j) = conv<T>(h);
+            if (lower_kept) *at(j, i) = conv<T>(nh);
         } else if (i < n && j < n && ti == tj && r == tx) {
-            if (a.report) dsq += abs2(conv<Wd>(M[(size_t)i * n + i]));
-            M[(size_t)i * n + i] = zero<T>();
+            if (a.report) dsq += abs2(conv<Wd>(*at(i, i)));
+            *at(i, i) = zero<T>();
         }
     }
     if (a.report) {
@@ -1089,6 +1096,18 @@ __global__ __launch_bounds__(kT) void final_pf_kernel(FA a, int tiles) {
             atomicAdd(&d->dsq, s0);
             atomicAdd(&d->nsq, s1);
         }
+    }
+}
+
+// Packed storage: zero the entries of the last tile row / column that lie past n
+// (the packed pass reads whole tiles; nothing else writes there).
+template <class T>
+__global__ __launch_bounds__(kT) void pk_zero_tail_kernel(FA a, int nt) {
+    const int w = blockIdx.x / nt, I = blockIdx.x - w * nt, n = a.n;
+    T *M = static_cast<T *>(a.inv) + (size_t)w * lrx_pk_elems_dev(n);
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += kT) {
+        const int r = I * 64 + (idx >> 6), c = (nt - 1) * 64 + (idx & 63);   // tile (I, nt - 1)
+        if (r >= n || c >= n) M[pk_offset(nt, r, c)] = zero<T>();
     }
 }
 
@@ -1183,7 +1202,7 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     a.work = static_cast<uint8_t *>(in.work);
     a.L = work_layout(in.n, sizeof(Wd));
     a.inv = in.inv; a.logabs = in.logabs; a.phase = in.phase; a.flags = in.flags;
-    a.report = in.report; a.refresh = in.refresh;
+    a.report = in.report; a.refresh = in.refresh; a.packed = in.packed;
     const int n = in.n, W = in.W;
     const int tiles = (n + 31) / 32;
     hipError_t e;
@@ -1218,6 +1237,10 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     } else {
         const int pairs = tiles * (tiles + 1) / 2;
         hipLaunchKernelGGL((final_pf_kernel<T, Wd>), dim3((unsigned)(W * pairs)), dim3(kT), 0, s, a, tiles);
+        if (a.packed && (n & 63)) {
+            const int nt = (n + 63) / 64;
+            hipLaunchKernelGGL(pk_zero_tail_kernel<T>, dim3((unsigned)(W * nt)), dim3(kT), 0, s, a, nt);
+        }
     }
     hipLaunchKernelGGL(finish_kernel<Wd>, dim3((W + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -55,6 +55,8 @@ struct StepArgs {
     const double *u01;
     uint64_t seed, counter;
     uint32_t rng_base;      // added to the walker index in the device generator's key
+    int layout;             // LRX_LAYOUT_* (PF): FULL, FUSED (one pending update), PACKED
+    void *part;             // PACKED: per-tile partial dots [W][tiles][2][64] (the init workspace)
 };
 
 struct HopArgs {
@@ -97,6 +99,22 @@ hipError_t pf_accept(int dtype, const StepArgs &a, hipStream_t s);
 // Flush GEMMs (lrx_flush.hip).
 hipError_t det_flush(int dtype, const StepArgs &a, hipStream_t s);
 hipError_t pf_flush(int dtype, const StepArgs &a, hipStream_t s);
+
+// Delayed-by-one fused plain Pfaffian update, full or packed storage (lrx_pf_fused.hip).
+hipError_t pf_fused_accept(int dtype, const StepArgs &a, hipStream_t s);
+hipError_t pf_fused_flush(int dtype, const StepArgs &a, hipStream_t s);
+hipError_t pf_read_inverse(int dtype, const StepArgs &a, void *out, hipStream_t s);
+
+// Packed skew storage: upper 64 x 64 tiles (I <= J) per walker.
+inline int pk_tiles(int n) {
+    const int nt = (n + LRX_PACK_TILE - 1) / LRX_PACK_TILE;
+    return nt * (nt + 1) / 2;
+}
+inline size_t pk_elems(int n) { return (size_t)pk_tiles(n) * LRX_PACK_TILE * LRX_PACK_TILE; }
+// Slots the state's fa / fb hold: the delay, or the pending slot(s) of the fused layouts.
+inline int slot_capacity(const lrx_shape &s) {
+    return s.layout == LRX_LAYOUT_FUSED ? 2 : (s.layout == LRX_LAYOUT_PACKED ? 1 : s.delay);
+}
 
 // Chain helpers (lrx_det.hip).
 hipError_t metropolis(int dtype, int W, const void *ratio, const double *u01,
@@ -156,6 +174,7 @@ struct FactorArgs {
     uint32_t *flags;
     double *report;           // refresh report [W][2] or NULL
     int refresh;              // 1 -> compare with the current state
+    int packed;               // PF: inv in packed skew storage (LRX_LAYOUT_PACKED)
 };
 size_t factor_work_bytes(int kind, int dtype, int W, int n);
 hipError_t factor(const FactorArgs &a, hipStream_t s);

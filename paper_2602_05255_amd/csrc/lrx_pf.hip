@@ -7,6 +7,8 @@
 //               r = pf R / pf J = R_12 = 1 + x . col          (Eqs. pf_ratio, pf_R)
 //   accept K=0: a_x = M x (pass 1); M += (col a_x^T - a_x col^T)/r (pass 2)   (Eq. pf_inv, k = 1)
 //   accept K>0: a_tau = [A_{tau-1}^-1 x, col], R_tau^-1 = [[0,-1/r],[1/r,0]] (Eq. pf_a, Sec. III.C)
+//   (the fused and packed layouts' accept is in lrx_pf_fused.hip; their propose is this one,
+//   with one pending slot and, packed, M0 read from the upper tiles)
 //
 // Exact skew symmetry of the plain update: entry (q, j) is computed from the
 // ordered pair (min, max) and negated when q > j, so (j, q) receives exactly
@@ -66,13 +68,15 @@ __global__ __launch_bounds__(kThreads) void pf_build_hop_kernel(HopArgs a) {
 // Slot columns per unrolled round of loads in the column pass of the propose.
 constexpr int kPfPropRound = 16;
 
-template <class T>
+// PK: M0 in packed skew storage (upper 64 x 64 tiles, LRX_LAYOUT_PACKED).
+template <class T, bool PK>
 __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
     using Wd = typename Wide<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = blockIdx.x, n = a.n, tau = a.tau, TE = tau * KA;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const T *M = static_cast<const T *>(a.inv) + (size_t)w * n * n;
+    const T *M = static_cast<const T *>(a.inv) + (size_t)w * (PK ? lrx_pk_elems_dev(n) : (size_t)n * n);
+    const int nt = (n + 63) >> 6;
     const T *x = static_cast<const T *>(a.u) + (size_t)w * n;
     const T *fa = static_cast<const T *>(a.fa) + (size_t)w * a.K * KA * n;
     const T *rinv = static_cast<const T *>(a.fb) + (size_t)w * a.K * KA * KA;
@@ -144,7 +148,10 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
     __syncthreads();
     T part = zero<T>();
     for (int q = tid; q < n; q += kThreads) {
-        T c = -M[(size_t)i * n + q];
+        // col_q = A0^-1[q][i] = -A0^-1[i][q]
+        T c;
+        if constexpr (PK) c = (i >> 6) <= (q >> 6) ? -M[pk_offset(nt, i, q)] : M[pk_offset(nt, q, i)];
+        else c = -M[(size_t)i * n + q];
         for (int t0 = 0; t0 < TE; t0 += kPfPropRound) {
             T fv[kPfPropRound];
 #pragma unroll
@@ -444,7 +451,10 @@ template <class T> hipError_t propose_t(const StepArgs &a, hipStream_t s) {
     const size_t tep = ((size_t)a.tau * KA + kPfPropRound - 1) / kPfPropRound * kPfPropRound;
     const size_t npx = ((size_t)a.n + 8 * 64 - 1) / (8 * 64) * (8 * 64);
     size_t lds = sizeof(T) * (tep + kWaves + npx);
-    hipLaunchKernelGGL(pf_propose_kernel<T>, dim3(a.W), dim3(kThreads), lds, s, a);
+    if (a.layout == LRX_LAYOUT_PACKED)
+        hipLaunchKernelGGL((pf_propose_kernel<T, true>), dim3(a.W), dim3(kThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((pf_propose_kernel<T, false>), dim3(a.W), dim3(kThreads), lds, s, a);
     return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ LRX_FLAG_SINGULAR_R, LRX_FLAG_NONFINITE, LRX_FLAG_SINGULAR_A, LRX_FLAG_BADINDEX 
 LRX_MH_UNIFORMS, LRX_MH_DEVICE_RNG, LRX_MH_FORCE, LRX_MH_MASK = 0, 1, 2, 3
 LRX_MAX_N, LRX_MAX_KMAX_DET, LRX_MAX_KMAX_PF, LRX_MAX_DELAY = 1024, 8, 4, 64
 LRX_MAX_CLASSES = 8
+LRX_LAYOUT_FULL, LRX_LAYOUT_FUSED, LRX_LAYOUT_PACKED = 0, 1, 2
+LRX_PACK_TILE = 64
 LRX_MAX_WINDOW_STEPS = 256
 LRX_NOALLOC_SCRATCH_WORDS = 64
 
@@ -43,7 +45,8 @@ WIDE = {LRX_F32: torch.float64, LRX_F64: torch.float64,
 
 class lrx_shape(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("walkers", ctypes.c_int32),
-                ("n", ctypes.c_int32), ("k_max", ctypes.c_int32), ("delay", ctypes.c_int32)]
+                ("n", ctypes.c_int32), ("k_max", ctypes.c_int32), ("delay", ctypes.c_int32),
+                ("layout", ctypes.c_int32)]
 
 
 class lrx_sizes(ctypes.Structure):
@@ -107,6 +110,7 @@ _SIGS = {
     "lrx_pf_accept_hop": ([ctypes.POINTER(lrx_state), _P, _P, _P, _P, _I, _P, ctypes.c_uint64, ctypes.c_uint64,
                            _P, _P, _P, _I, _P], ctypes.c_int),
     "lrx_pf_flush_delayed": ([ctypes.POINTER(lrx_state), _P], ctypes.c_int),
+    "lrx_pf_read_inverse": ([ctypes.POINTER(lrx_state), _P, _P], ctypes.c_int),
     "lrx_det_propose_general": ([ctypes.POINTER(lrx_state), _I, _P, _P, _I, _P, _P, _P, _P], ctypes.c_int),
     "lrx_det_accept_general": ([ctypes.POINTER(lrx_state), _I, _P, _P, _I, _P, _P, _P, _P], ctypes.c_int),
     "lrx_pf_propose_general": ([ctypes.POINTER(lrx_state), _I, _P, _P, _P, _P], ctypes.c_int),
@@ -172,9 +176,9 @@ def lrx_strerror(code: int) -> str:
     return _lib.lrx_strerror(int(code)).decode()
 
 
-def lrx_state_sizes(kind, dtype, walkers, n, k_max, delay):
+def lrx_state_sizes(kind, dtype, walkers, n, k_max, delay, layout=0):
     """Byte sizes of the state buffers (host only; raises LrxError for bad shapes)."""
-    shp = lrx_shape(kind, dtype, walkers, n, k_max, delay)
+    shp = lrx_shape(kind, dtype, walkers, n, k_max, delay, layout)
     out = lrx_sizes()
     _check(_lib.lrx_state_sizes(ctypes.byref(shp), ctypes.byref(out)), "lrx_state_sizes")
     return {f: getattr(out, f) for f, _ in lrx_sizes._fields_}
@@ -183,11 +187,11 @@ def lrx_state_sizes(kind, dtype, walkers, n, k_max, delay):
 class State:
     """Device buffers of one walker batch plus the C state (caller-owned memory)."""
 
-    def __init__(self, kind, dtype, walkers, n, k_max=1, delay=0, device="cuda"):
+    def __init__(self, kind, dtype, walkers, n, k_max=1, delay=0, device="cuda", layout=0):
         code = DTYPE_CODE[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
-        self.sizes = lrx_state_sizes(kind, code, walkers, n, k_max, delay)
+        self.sizes = lrx_state_sizes(kind, code, walkers, n, k_max, delay, layout)
         self.kind, self.code, self.dtype = kind, code, CODE_DTYPE[code]
-        self.walkers, self.n, self.k_max, self.delay = walkers, n, k_max, delay
+        self.walkers, self.n, self.k_max, self.delay, self.layout = walkers, n, k_max, delay, layout
         dev = torch.device(device)
         self.buffers = {}
         for name in ("inv", "fa", "fb", "stash", "logabs", "phase", "flags", "work"):
@@ -195,7 +199,7 @@ class State:
             self.buffers[name] = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.buffers["flags"].zero_()
         ptr = {k: ctypes.c_void_p(v.data_ptr()) for k, v in self.buffers.items()}
-        self.c = lrx_state(lrx_shape(kind, code, walkers, n, k_max, delay), 0, 0,
+        self.c = lrx_state(lrx_shape(kind, code, walkers, n, k_max, delay, layout), 0, 0,
                            ptr["inv"], ptr["fa"], ptr["fb"], ptr["stash"], ptr["logabs"], ptr["phase"],
                            ptr["flags"], ptr["work"])
         _check(_lib.lrx_validate(ctypes.byref(self.c)), "lrx_validate")
@@ -203,7 +207,11 @@ class State:
     # Typed views of the device state.
     @property
     def inv(self):
-        return self.buffers["inv"][: self.sizes["inv"]].view(self.dtype).view(self.walkers, self.n, self.n)
+        """M0 as stored: [W][n][n], or [W][tiles][64][64] for the packed layout."""
+        v = self.buffers["inv"][: self.sizes["inv"]].view(self.dtype)
+        if self.layout == LRX_LAYOUT_PACKED:
+            return v.view(self.walkers, -1, LRX_PACK_TILE, LRX_PACK_TILE)
+        return v.view(self.walkers, self.n, self.n)
 
     @property
     def logabs(self):
@@ -452,6 +460,12 @@ def lrx_pf_accept_hop(st: State, k, cols, slot, x, mode, u01, seed, counter, acc
 
 def lrx_pf_flush_delayed(st: State, stream=None):
     _check(_lib.lrx_pf_flush_delayed(st.ptr(), _stream(stream)), "lrx_pf_flush_delayed")
+
+
+def lrx_pf_read_inverse(st: State, out, stream=None):
+    """out: device bulk dtype [W][n][n] <- A^-1 of every walker (any layout, state unchanged)."""
+    po = _dev(out, "out", st.dtype, (st.walkers, st.n, st.n))
+    _check(_lib.lrx_pf_read_inverse(st.ptr(), po, _stream(stream)), "lrx_pf_read_inverse")
 
 
 # ------------------------------------------------------------------ chain helpers

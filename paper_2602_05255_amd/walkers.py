@@ -20,14 +20,14 @@ class Walkers:
     """A batch of walkers sharing one orbital (DET) or pairing (PF) matrix."""
 
     def __init__(self, kind, dtype, table, occ, empty, k_max=1, delay=0, refresh_period=0,
-                 device="cuda"):
+                 device="cuda", layout=0):
         occ = np.asarray(occ)
         empty = np.asarray(empty)
         self.kind = kind
         self.W, self.n = occ.shape
         self.n_empty = empty.shape[1]
         self.k_max, self.delay, self.refresh_period = k_max, delay, refresh_period
-        self.st = lrx.State(kind, dtype, self.W, self.n, k_max, delay, device)
+        self.st = lrx.State(kind, dtype, self.W, self.n, k_max, delay, device, layout)
         self.device = torch.device(device)
         self.table = torch.as_tensor(np.ascontiguousarray(table)).to(self.device, self.st.wide)
         self.sites = int(self.table.shape[0])
@@ -141,8 +141,13 @@ class Walkers:
 
     # ------------------------------------------------------------------ views
     def inverse(self):
-        """A^-1 of every walker in the wide dtype (flushing pending factors first)."""
+        """A^-1 of every walker in the wide dtype (flushing pending factors first; packed
+        Pfaffian states are read out through lrx_pf_read_inverse)."""
         if self.st.slot:
             self.flush()
+        if self.st.layout == lrx.LRX_LAYOUT_PACKED:
+            out = torch.empty(self.W, self.n, self.n, dtype=self.st.dtype, device=self.device)
+            lrx.lrx_pf_read_inverse(self.st, out)
+            return out.to(self.st.wide)
         m = self.st.inv.to(self.st.wide)
         return m.transpose(1, 2) if self.kind == lrx.LRX_DET else m

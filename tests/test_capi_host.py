@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_strerror():
-    assert lrx.lrx_version() == 1
+    assert lrx.lrx_version() == 2
     assert "flush" in lrx.lrx_strerror(lrx.LRX_ENEEDFLUSH)
     assert lrx.lrx_strerror(999) == "unknown error"
 
@@ -91,12 +91,12 @@ def test_state_sizes_rejects(args, code):
     assert e.value.code == code
 
 
-def fake_state(kind=lrx.LRX_DET, dtype=lrx.LRX_F64, W=4, n=8, k_max=1, delay=0, slot=0, null=()):
+def fake_state(kind=lrx.LRX_DET, dtype=lrx.LRX_F64, W=4, n=8, k_max=1, delay=0, slot=0, null=(), layout=0):
     p = {f: ctypes.c_void_p(0x10000 + 0x1000 * i) for i, f in
          enumerate(("inv", "fa", "fb", "stash", "logabs", "phase", "flags", "work"))}
     for f in null:
         p[f] = ctypes.c_void_p(0)
-    return lrx.lrx_state(lrx.lrx_shape(kind, dtype, W, n, k_max, delay), slot, 0, p["inv"], p["fa"], p["fb"],
+    return lrx.lrx_state(lrx.lrx_shape(kind, dtype, W, n, k_max, delay, layout), slot, 0, p["inv"], p["fa"], p["fb"],
                          p["stash"], p["logabs"], p["phase"], p["flags"], p["work"])
 
 
@@ -264,3 +264,42 @@ def test_autotune_table():
         lrx.lrx_autotune_lookup(lrx.LRX_F32, 0, 1)
     with pytest.raises(lrx.LrxError):
         lrx.lrx_autotune_store(lrx.LRX_F32, 64, 1, 4, 8, 0)        # rows per block below 16
+
+
+def test_layout_sizes_and_checks():
+    """Fused and packed Pfaffian layouts: sizes (upper 64 x 64 tiles, one or two pending
+    slots, partial dots in the workspace) and the shapes they refuse."""
+    W, n, es = 3, 130, 16
+    full = lrx.lrx_state_sizes(lrx.LRX_PF, lrx.LRX_C128, W, n, 1, 0)
+    fused = lrx.lrx_state_sizes(lrx.LRX_PF, lrx.LRX_C128, W, n, 1, 0, lrx.LRX_LAYOUT_FUSED)
+    packed = lrx.lrx_state_sizes(lrx.LRX_PF, lrx.LRX_C128, W, n, 1, 0, lrx.LRX_LAYOUT_PACKED)
+    nt = 3                                              # ceil(130 / 64)
+    assert fused["inv"] == full["inv"] == W * n * n * es
+    assert packed["inv"] == W * nt * (nt + 1) // 2 * 64 * 64 * es
+    assert fused["fa"] == W * 2 * 2 * n * es and fused["fb"] == W * 2 * 4 * es
+    assert packed["fa"] == W * 1 * 2 * n * es and packed["fb"] == W * 1 * 4 * es
+    assert packed["work"] >= W * 6 * 2 * 64 * es
+    # at n = 1024 the packed triangle is 136 of 256 tiles
+    big = lrx.lrx_state_sizes(lrx.LRX_PF, lrx.LRX_F32, 1, 1024, 1, 0, lrx.LRX_LAYOUT_PACKED)
+    assert big["inv"] == 136 * 4096 * 4
+    for args in [(lrx.LRX_DET, lrx.LRX_F64, 2, 8, 1, 0, lrx.LRX_LAYOUT_FUSED),      # DET
+                 (lrx.LRX_PF, lrx.LRX_C64, 2, 8, 1, 4, lrx.LRX_LAYOUT_FUSED),       # delayed
+                 (lrx.LRX_PF, lrx.LRX_C64, 2, 8, 2, 0, lrx.LRX_LAYOUT_PACKED),      # k_max 2
+                 (lrx.LRX_PF, lrx.LRX_C64, 2, 8, 1, 0, 3)]:                         # unknown layout
+        with pytest.raises(lrx.LrxError) as e:
+            lrx.lrx_state_sizes(*args)
+        assert e.value.code == lrx.LRX_EUNSUPPORTED, args
+    lib = lrx._lib
+    st = fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64, layout=lrx.LRX_LAYOUT_PACKED, slot=1)
+    assert lib.lrx_validate(ctypes.byref(st)) == lrx.LRX_OK
+    assert lib.lrx_validate(ctypes.byref(fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64,
+                                                    layout=lrx.LRX_LAYOUT_FUSED, slot=2))) == lrx.LRX_EINVAL
+    assert lib.lrx_validate(ctypes.byref(fake_state(kind=lrx.LRX_PF, dtype=lrx.LRX_C64, layout=lrx.LRX_LAYOUT_FUSED,
+                                                    null=("fa",)))) == lrx.LRX_EINVAL
+    # refresh with a pending update, and the entry points that take full storage only
+    assert lib.lrx_pf_refresh(ctypes.byref(st), P, 16, P, None, None) == lrx.LRX_ENEEDFLUSH
+    assert lib.lrx_pf_lowrank_fwd(ctypes.byref(st), 2, P, P, P, P, P, None) == lrx.LRX_EUNSUPPORTED
+    assert lib.lrx_pf_grad(ctypes.byref(st), P, P, None) == lrx.LRX_EUNSUPPORTED
+    assert lib.lrx_pf_propose_general(ctypes.byref(st), 1, P, P, P, None) == lrx.LRX_EUNSUPPORTED
+    assert lib.lrx_pf_read_inverse(ctypes.byref(st), None, None) == lrx.LRX_EINVAL
+    assert lib.lrx_pf_read_inverse(ctypes.byref(fake_state()), P, None) == lrx.LRX_EKIND
