@@ -107,7 +107,7 @@ class Run:
     staggered refreshes, one HIP graph per period).  Workloads without a refresh (the plain
     Sherman-Morrison chain) use their step count as the period and never refresh."""
 
-    def __init__(self, wl, dtype, walkers, seed_offset=0, streams=1):
+    def __init__(self, wl, dtype, walkers, seed_offset=0, streams=1, layout=0):
         import torch
         from paper_2602_05255_amd import inputs as gen
         from paper_2602_05255_amd import lrx
@@ -127,7 +127,7 @@ class Run:
         draws = tuple(torch.as_tensor(x).cuda() for x in (k, e, s))
         kind = lrx.LRX_DET if wl.kind == "det" else lrx.LRX_PF
         self.drv = PeriodDriver(kind, dtype, phi, occ, emp, wl.k_max, wl.delay, self.P, draws, streams=streams,
-                                refresh=bool(wl.refresh))
+                                refresh=bool(wl.refresh), layout=layout)
         self.parts = self.drv.parts
         self.wk = self.parts[0][0]
 
@@ -800,6 +800,54 @@ def bench_delay_sweep(args, torch, kinds=("det", "pf")):
     return out
 
 
+def bench_pf_layouts(args, torch, steps=64):
+    """The Pfaffian workload's shape (256 walkers, n = 512, L = 1024, complex64 bulk), single
+    hops, forced accept, no refresh: 64 consecutive steps (one HIP graph) on the plain
+    update (three passes over A^-1), the fused delay-one update (one read + write pass),
+    the same on packed skew storage (upper 64 x 64 tiles), and the delayed update with
+    K = 32 for reference.  Bytes per accepted step (algorithmic): plain 3 n^2, fused 2 n^2,
+    packed 2 * tiles * 64^2, delayed n^2 + 2 n^2 / K (flush) plus the slot columns."""
+    from paper_2602_05255_amd import inputs as gen
+    from paper_2602_05255_amd import lrx
+    base = gen.WORKLOADS["pfaffian_n512_c64"]
+    W, n = args.walkers or base.walkers, base.n
+    es = 8
+    nt = (n + 63) // 64
+    tiles = nt * (nt + 1) // 2
+    variants = [("plain", lrx.LRX_LAYOUT_FULL, 0, 3.0 * n * n),
+                ("fused", lrx.LRX_LAYOUT_FUSED, 0, 2.0 * n * n),
+                ("packed", lrx.LRX_LAYOUT_PACKED, 0, 2.0 * tiles * 64 * 64),
+                ("delayed_K32", lrx.LRX_LAYOUT_FULL, 32, n * n + 2.0 * n * n / 32 + 2.0 * n * 16)]
+    rows = []
+    for name, layout, K, per_step in variants:
+        wl = gen.Workload(base.name, "pf", base.sites, n, W, (1,), 1, K, 0, True, "c64", steps=steps, seed=base.seed)
+        run = Run(wl, torch.complex64, W, streams=1, layout=layout)
+        run.capture()
+        for _ in range(2):
+            run.step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            run.step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = W * steps * per_step * es / (ms * 1e-3) / 1e9
+        rows.append({"variant": name, "layout": int(layout), "delay": K, "ms_per_64_steps": ms,
+                     "walker_steps_per_s": W * steps / (ms * 1e-3), "bytes_per_step": per_step * es,
+                     "achieved_gbs_algorithmic": gbs})
+        log(f"  pf layouts {name}: {ms:.3f} ms per {steps} steps, {gbs:.0f} GB/s algorithmic")
+        del run
+        torch.cuda.empty_cache()
+    plain = rows[0]["ms_per_64_steps"]
+    for r in rows:
+        r["speedup_vs_plain"] = plain / r["ms_per_64_steps"]
+    return {"walkers": W, "n": n, "sites": base.sites, "dtype": "c64", "steps": steps, "mode": "forced-accept",
+            "rows": rows}
+
+
 def bench_nsweep(wl, args, torch):
     """Single-hop determinant LRU against full recompute on the same GPU, n = 64 .. 1024
     (the shape of the paper's speedup-vs-n figure), one bench_single_hop per n."""
@@ -869,6 +917,9 @@ def main():
     if args.copy_calibration:
         print(json.dumps(copy_calibration(torch)), flush=True)
         return
+    if args.workload == "pf_layouts_n512_c64":
+        print(json.dumps({"workload": "pf_layouts_n512_c64", **bench_pf_layouts(args, torch)}), flush=True)
+        return
     wl = gen.WORKLOADS[args.workload]
     if args.streams is None:
         args.streams = {"slater_n256_k124": 4, "pfaffian_n512_c64": 4}.get(wl.name, 1)
@@ -914,6 +965,7 @@ def main():
         c3, torch.complex64, short, torch, "c64", streams=4, recompute_leg=not args.no_recompute))
     cfg["single_hop_n1024"] = run_extra("single_hop_n1024", lambda: bench_single_hop(1024, args, torch))
     cfg["delay_sweep_n128"] = run_extra("delay_sweep_n128", lambda: bench_delay_sweep(short, torch))
+    cfg["pf_layouts_n512_c64"] = run_extra("pf_layouts_n512_c64", lambda: bench_pf_layouts(short, torch))
     cfg["slater_n32_fp64"] = run_extra("slater_n32_fp64", lambda: bench_plain_chain(
         gen.WORKLOADS["slater_n32_fp64"], args, torch))
     cfg["logpsi_grad_n512_c64"] = run_extra("logpsi_grad_n512_c64", lambda: bench_adjoint(

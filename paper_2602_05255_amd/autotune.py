@@ -79,8 +79,8 @@ def _time_windows(uw, reps):
 
 def rows_candidates(n):
     """Accept work-group heights tried for the per-step schedule: the library's heuristic (0)
-    and 128, 256, 512 rows below n."""
-    return [0] + [r for r in (128, 256, 512) if r < n]
+    and 64, 128, 256, 512 rows below n."""
+    return [0] + [r for r in (64, 128, 256, 512) if r < n]
 
 
 def _time_steps(wk, draws, steps, reps):
@@ -118,7 +118,7 @@ def tune_class(dtype, n, k_max, ranks, walkers=512, device="cuda", cache=None, s
     path = cache or cache_path()
     table = _load(path)
     dname = str(dtype).replace("torch.", "")
-    key = f"{_device_key(device)}|{dname}|n={n}|kmax={k_max}|ranks={list(ranks)}|v2"
+    key = f"{_device_key(device)}|{dname}|n={n}|kmax={k_max}|ranks={list(ranks)}|v3"
     hit = table.get(key, {})
     if all(f in hit for f in ("delay", "rows_per_block", "window")):
         out = {"delay": int(hit["delay"]), "rows_per_block": int(hit["rows_per_block"]), "window": bool(hit["window"])}

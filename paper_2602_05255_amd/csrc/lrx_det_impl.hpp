@@ -70,11 +70,9 @@ __global__ __launch_bounds__(kThreads) void det_build_hop_kernel(HopArgs a) {
 //   R        = I + u^T C,   r = det R
 // With a hop table the update vectors u = Phi[s'] - Phi[s] are built here too.
 template <class T> constexpr int prop_nv() { return sizeof(T) <= 4 ? 32 : (sizeof(T) == 8 ? 16 : 8); }
-// Groups of slot columns in flight in the propose (registers: NB GS NI values).
-template <class T, int GS, int NI> constexpr int prop_nb() {
-    constexpr int regs = (int)(sizeof(T) / 4) * GS * NI;     // 32-bit registers per group
-    return regs <= 16 ? 4 : (regs <= 32 ? 3 : 2);
-}
+// Groups of slot columns in flight in the propose: two (deeper rings of three or
+// four groups measured slower on gfx950, by 5-15 %).
+template <class T, int GS, int NI> constexpr int prop_nb() { return 2; }
 
 // NW waves per walker (one work-group); each thread owns NI entries i = t + 64 NW ii.
 // tid is the thread's index in the work-group (passed in so that a caller

@@ -30,13 +30,13 @@ from .walkers import Walkers
 
 class PeriodDriver:
     def __init__(self, kind, dtype, table, occ, empty, k_max, delay, period, draws, streams=1,
-                 mode=lrx.LRX_MH_FORCE, seed=0, ratio_log=None, refresh=True, u01=None):
+                 mode=lrx.LRX_MH_FORCE, seed=0, ratio_log=None, refresh=True, u01=None, layout=0):
         """draws: device int32 tensors (k [P][W], elec [P][W][k_max], slot [P][W][k_max]);
         period: P (steps per period); ratio_log: optional device tensor [P][W] receiving the
         ratio of every walker at each step (indexed by the step's position in the period);
         refresh: refresh every sub-batch once per period (False: never); u01: device float64
         [P][W] uniforms read at run time by mode LRX_MH_UNIFORMS (refill it between replays
-        of a captured period)."""
+        of a captured period); layout: storage / update scheme of the states (LRX_LAYOUT_*)."""
         occ = np.asarray(occ)
         empty = np.asarray(empty)
         self.kind, self.P, self.W = kind, int(period), occ.shape[0]
@@ -45,7 +45,7 @@ class PeriodDriver:
         bounds = np.linspace(0, self.W, max(1, streams) + 1).astype(int)
         self.parts = []
         for a0, a1 in zip(bounds[:-1], bounds[1:]):
-            wk = Walkers(kind, dtype, table, occ[a0:a1], empty[a0:a1], k_max, delay, refresh_period=0)
+            wk = Walkers(kind, dtype, table, occ[a0:a1], empty[a0:a1], k_max, delay, refresh_period=0, layout=layout)
             self.parts.append((wk, int(a0), int(a1), torch.cuda.Stream() if streams > 1 else None))
         K = max(1, delay)
         self.offsets = [(p * (self.P // len(self.parts))) // K * K for p in range(len(self.parts))]
