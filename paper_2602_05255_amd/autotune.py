@@ -79,8 +79,8 @@ def _time_windows(uw, reps):
 
 def rows_candidates(n):
     """Accept work-group heights tried for the per-step schedule: the library's heuristic (0)
-    and 64, 128, 256, 512 rows below n."""
-    return [0] + [r for r in (64, 128, 256, 512) if r < n]
+    and 32, 64, 128, 256, 512 rows below n."""
+    return [0] + [r for r in (32, 64, 128, 256, 512) if r < n]
 
 
 def _time_steps(wk, draws, steps, reps):

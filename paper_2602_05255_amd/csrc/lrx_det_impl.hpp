@@ -70,17 +70,13 @@ __global__ __launch_bounds__(kThreads) void det_build_hop_kernel(HopArgs a) {
 //   R        = I + u^T C,   r = det R
 // With a hop table the update vectors u = Phi[s'] - Phi[s] are built here too.
 template <class T> constexpr int prop_nv() { return sizeof(T) <= 4 ? 32 : (sizeof(T) == 8 ? 16 : 8); }
-// Groups of slot columns in flight in the propose: two (deeper rings of three or
-// four groups measured slower on gfx950, by 5-15 %).
-template <class T, int GS, int NI> constexpr int prop_nb() { return 2; }
 
 // NW waves per walker (one work-group); each thread owns NI entries i = t + 64 NW ii.
 // tid is the thread's index in the work-group (passed in so that a caller
 // looping over steps can keep the derived addresses from living across steps).
 // With NW = 1 every reduction stays inside the wave and no block barrier sits on
 // the critical path.
-// NBX: groups of slot columns in flight (0: prop_nb's default).
-template <class T, int KM, int NW, int NI, int NBX = 0>
+template <class T, int KM, int NW, int NI>
 __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, unsigned char *smem, int tid) {
     using Wd = typename Wide<T>::type;
     constexpr int NT = 64 * NW;
@@ -180,24 +176,18 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
         }
     }
     __syncthreads();
-    // Live slot columns in groups of GS, NB groups in flight: while one group is
-    // reduced the loads of the next NB - 1 are outstanding, so the chain of
-    // dependent loads per walker is about nl / (NB GS) memory latencies long.
-    // Loads are unconditional; a padded entry (past the live columns) reads one
-    // cached address (entry 0 of slot column 0) on every lane, multiplies the
-    // zero column TE of s_fbI and its G partial is dropped.  Slot column 0 is live
-    // whenever a group is processed (k >= 1 at every filled slot), so the value is
-    // finite.  Each wave reduces G over its own part of i and keeps the partial in
-    // LDS, so the loop has no block barrier.
+    // Live slot columns in groups of GS: the loads of the next group are in
+    // flight while the current one is reduced (unconditional loads from clamped
+    // addresses; a padded entry multiplies the zero column TE of s_fbI and its
+    // G partial is dropped).  Each wave reduces G over its own part of i and
+    // keeps the partial in LDS, so the loop has no block barrier.
     const int nl = s_nl;
     auto load_grp = [&](int g0, T (&av)[GS][NI]) {
 #pragma unroll
         for (int gi = 0; gi < GS; ++gi) {
-            const bool in = g0 + gi < nl;
-            const int te = in ? s_live[g0 + gi] : 0;
+            const int te = (g0 + gi < nl) ? s_live[g0 + gi] : 0;
 #pragma unroll
-            for (int ii = 0; ii < NI; ++ii)
-                av[gi][ii] = fa[(size_t)te * n + (in ? min(tid + ii * NT, n - 1) : 0)];
+            for (int ii = 0; ii < NI; ++ii) av[gi][ii] = fa[(size_t)te * n + min(tid + ii * NT, n - 1)];
         }
     };
     auto do_grp = [&](int g0, T (&av)[GS][NI]) {
@@ -223,18 +213,18 @@ __device__ __forceinline__ void det_propose_walker(const StepArgs &a, int w, uns
             else s_gpart[(size_t)wv * TE * KM + idx] = tot;
         }
     };
-    if (nl > 0) {
-        constexpr int NB = NBX > 0 ? NBX : prop_nb<T, GS, NI>();
-        T ab[NB][GS][NI];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) load_grp(b * GS, ab[b]);
-        for (int g0 = 0; g0 < nl; g0 += NB * GS) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int gb = g0 + b * GS;
-                if (gb < nl) do_grp(gb, ab[b]);          // wave-uniform
-                load_grp(gb + NB * GS, ab[b]);
-            }
+    {
+        T a0[GS][NI], a1[GS][NI];
+        int g0 = 0;
+        if (nl > 0) load_grp(0, a0);
+        while (g0 < nl) {
+            load_grp(g0 + GS, a1);
+            do_grp(g0, a0);
+            g0 += GS;
+            if (g0 >= nl) break;
+            load_grp(g0 + GS, a0);
+            do_grp(g0, a1);
+            g0 += GS;
         }
     }
     if constexpr (NW > 1) {   // G = sum of the wave partials; dead slot columns and ranks >= k are zero

@@ -67,7 +67,7 @@ __device__ __forceinline__ void window_walker(const WindowClass &wc, int steps, 
         // them all live across the whole window.
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        det_propose_walker<T, KM, 4, NI, 2>(a, w, smem, tid);   // two groups in flight: registers are tight here
+        det_propose_walker<T, KM, 4, NI>(a, w, smem, tid);
         __syncthreads();
         tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
