@@ -805,8 +805,9 @@ def bench_pf_layouts(args, torch, steps=64):
     hops, forced accept, no refresh: 64 consecutive steps (one HIP graph) on the plain
     update (three passes over A^-1), the fused delay-one update (one read + write pass),
     the same on packed skew storage (upper 64 x 64 tiles), and the delayed update with
-    K = 32 for reference.  Bytes per accepted step (algorithmic): plain 3 n^2, fused 2 n^2,
-    packed 2 * tiles * 64^2, delayed n^2 + 2 n^2 / K (flush) plus the slot columns."""
+    K = 32 on full and on packed storage.  Bytes per accepted step (algorithmic): plain 3 n^2,
+    fused 2 n^2, packed 2 * tiles * 64^2, delayed n^2 + 2 n^2 / K (flush), packed delayed
+    tiles * 64^2 (1 + 2 / K), plus the slot columns."""
     from paper_2602_05255_amd import inputs as gen
     from paper_2602_05255_amd import lrx
     base = gen.WORKLOADS["pfaffian_n512_c64"]
@@ -817,7 +818,9 @@ def bench_pf_layouts(args, torch, steps=64):
     variants = [("plain", lrx.LRX_LAYOUT_FULL, 0, 3.0 * n * n),
                 ("fused", lrx.LRX_LAYOUT_FUSED, 0, 2.0 * n * n),
                 ("packed", lrx.LRX_LAYOUT_PACKED, 0, 2.0 * tiles * 64 * 64),
-                ("delayed_K32", lrx.LRX_LAYOUT_FULL, 32, n * n + 2.0 * n * n / 32 + 2.0 * n * 16)]
+                ("delayed_K32", lrx.LRX_LAYOUT_FULL, 32, n * n + 2.0 * n * n / 32 + 2.0 * n * 16),
+                ("packed_delayed_K32", lrx.LRX_LAYOUT_PACKED, 32,
+                 tiles * 64 * 64 + 2.0 * tiles * 64 * 64 / 32 + 2.0 * n * 16)]
     rows = []
     for name, layout, K, per_step in variants:
         wl = gen.Workload(base.name, "pf", base.sites, n, W, (1,), 1, K, 0, True, "c64", steps=steps, seed=base.seed)

@@ -37,7 +37,7 @@
  *         upper tiles only (see LRX_LAYOUT_* below).
  * fa    : delayed factors a_t (DET Eq. det_a, PF Eq. pf_a), stored as columns:
  *         [W][K*KA][n] with KA = k_max (DET) or 2*k_max (PF); K is the slot
- *         capacity: the delay, or 2 (FUSED) / 1 (PACKED).
+ *         capacity: the delay, or 2 (FUSED) / 1 (PACKED with delay 0).
  * fb    : DET: b_t (Eq. det_b) as rows, [W][n][K*k_max];
  *         PF : R_t^-1 (2k x 2k), [W][K][2k_max][2k_max].
  * stash : per-walker scratch written by propose and read by accept
@@ -113,20 +113,26 @@ enum {
  *                    writes the row back and takes its dot with the new x in
  *                    the same pass.  HBM per accepted step: 2 n^2 elements
  *                    instead of 3 n^2.
- * LRX_LAYOUT_PACKED: as LRX_LAYOUT_FUSED, with inv holding only the tiles on
- *                    and above the diagonal (skewness of A^-1, Sec. III.A):
- *                    64 x 64 row-major tiles (I <= J) of the n x n matrix,
- *                    tile (I, J) at tile index I*nt - I*(I-1)/2 + (J - I),
- *                    nt = ceil(n / 64), element (r, c) of the tile at
- *                    r * 64 + c; entries past n are zero; diagonal tiles hold
- *                    the whole (exactly skew) 64 x 64 block.  HBM per accepted
- *                    step: about n^2 elements (read and write of one triangle).
- * For FUSED / PACKED states st->slot is 0 (nothing pending) or 1 (slot 0 may
- * hold each walker's pending update; a walker that rejected keeps its own);
- * accept sets it to 1, flush_delayed applies the pending updates and sets it to
- * 0.  Refresh needs st->slot == 0 (LRX_ENEEDFLUSH otherwise).  The low-rank,
- * gradient and general-update entry points take LRX_LAYOUT_FULL states only
- * (LRX_EUNSUPPORTED).  lrx_pf_read_inverse returns A^-1 for every layout.
+ * LRX_LAYOUT_PACKED: PF, k_max 1, inv holding only the tiles on and above the
+ *                    diagonal (skewness of A^-1, Sec. III.A): 64 x 64 row-major
+ *                    tiles (I <= J) of the n x n matrix, tile (I, J) at tile
+ *                    index I*nt - I*(I-1)/2 + (J - I), nt = ceil(n / 64),
+ *                    element (r, c) of the tile at r * 64 + c; entries past n
+ *                    are zero; diagonal tiles hold the whole (exactly skew)
+ *                    64 x 64 block.  Delay 0: the fused update above on the
+ *                    tiles, about n^2 elements per accepted step (read and write
+ *                    of one triangle).  Delay K > 0: the delayed update of
+ *                    Sec. III.C with A_0^-1 x formed from the tiles (n^2 / 2
+ *                    elements read per step) and a flush that reads and writes
+ *                    the stored tiles only (half the output of the full flush).
+ * For FUSED states and PACKED states with delay 0, st->slot is 0 (nothing
+ * pending) or 1 (slot 0 may hold each walker's pending update; a walker that
+ * rejected keeps its own); accept sets it to 1, flush_delayed applies the
+ * pending updates and sets it to 0.  PACKED states with a delay count slots as
+ * LRX_LAYOUT_FULL ones do.  Refresh needs st->slot == 0 (LRX_ENEEDFLUSH
+ * otherwise).  The low-rank, gradient and general-update entry points take
+ * LRX_LAYOUT_FULL states only (LRX_EUNSUPPORTED).  lrx_pf_read_inverse returns
+ * A^-1 for every layout.
  */
 enum { LRX_LAYOUT_FULL = 0, LRX_LAYOUT_FUSED = 1, LRX_LAYOUT_PACKED = 2 };
 #define LRX_PACK_TILE 64

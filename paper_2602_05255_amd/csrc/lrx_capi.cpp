@@ -53,9 +53,9 @@ static int check_shape(const lrx_shape *s) {
     if (s->walkers < 1 || s->n < 1 || s->n > LRX_MAX_N) return LRX_ESHAPE;
     if (s->delay < 0 || s->delay > LRX_MAX_DELAY) return LRX_ESHAPE;
     if (s->layout < LRX_LAYOUT_FULL || s->layout > LRX_LAYOUT_PACKED) return LRX_EUNSUPPORTED;
-    // the fused and packed layouts: single-hop plain Pfaffian updates
-    if (s->layout != LRX_LAYOUT_FULL && (s->kind != LRX_PF || s->delay != 0 || s->k_max != 1))
-        return LRX_EUNSUPPORTED;
+    // the fused and packed layouts: single-hop Pfaffian updates (fused: plain only)
+    if (s->layout != LRX_LAYOUT_FULL && (s->kind != LRX_PF || s->k_max != 1)) return LRX_EUNSUPPORTED;
+    if (s->layout == LRX_LAYOUT_FUSED && s->delay != 0) return LRX_EUNSUPPORTED;
     const size_t es = bulk_bytes(s->dtype);
     if (s->kind == LRX_DET) {
         if (s->k_max != 1 && s->k_max != 2 && s->k_max != 4 && s->k_max != 8) return LRX_ESHAPE;
@@ -98,6 +98,7 @@ static StepArgs step_args(const lrx_state *st) {
     a.K = slot_capacity(st->shape);
     a.tau = st->slot;
     a.layout = st->shape.layout;
+    a.delay = st->shape.delay;
     a.part = st->work;
     a.aligned = ((size_t)st->shape.n * bulk_bytes(st->shape.dtype)) % 16 == 0 ? 1 : 0;
     a.inv = st->inv;
@@ -165,7 +166,8 @@ int lrx_validate(const lrx_state *st) {
     if (rc) return rc;
     if (!st->inv || !st->stash || !st->logabs || !st->phase || !st->flags || !st->work) return LRX_EINVAL;
     if (slot_capacity(st->shape) > 0 && (!st->fa || !st->fb)) return LRX_EINVAL;
-    const int max_slot = st->shape.layout != LRX_LAYOUT_FULL ? 1 : st->shape.delay;
+    // FULL: the delay; FUSED and PACKED with delay 0: one pending slot; PACKED with a delay: the delay
+    const int max_slot = st->shape.delay > 0 ? st->shape.delay : (st->shape.layout != LRX_LAYOUT_FULL ? 1 : 0);
     if (st->slot < 0 || st->slot > max_slot) return LRX_EINVAL;
     return LRX_OK;
 }
@@ -493,7 +495,7 @@ int lrx_pf_grad(const lrx_state *st, const void *g, void *dA, void *stream) {
 static int pf_accept_common(lrx_state *st, const StepArgs &a, void *stream) {
     if (st->shape.layout != LRX_LAYOUT_FULL) {
         const int rc = hip_rc(pf_fused_accept(st->shape.dtype, a, as_stream(stream)));
-        if (rc == LRX_OK) st->slot = 1;
+        if (rc == LRX_OK) st->slot = st->shape.delay > 0 ? st->slot + 1 : 1;   // delayed packed: next slot
         return rc;
     }
     const int rc = hip_rc(pf_accept(st->shape.dtype, a, as_stream(stream)));

@@ -56,6 +56,7 @@ struct StepArgs {
     uint64_t seed, counter;
     uint32_t rng_base;      // added to the walker index in the device generator's key
     int layout;             // LRX_LAYOUT_* (PF): FULL, FUSED (one pending update), PACKED
+    int delay;              // the shape's delay K (K above is the slot capacity)
     void *part;             // PACKED: per-tile partial dots [W][tiles][2][64] (the init workspace)
 };
 
@@ -113,7 +114,9 @@ inline int pk_tiles(int n) {
 inline size_t pk_elems(int n) { return (size_t)pk_tiles(n) * LRX_PACK_TILE * LRX_PACK_TILE; }
 // Slots the state's fa / fb hold: the delay, or the pending slot(s) of the fused layouts.
 inline int slot_capacity(const lrx_shape &s) {
-    return s.layout == LRX_LAYOUT_FUSED ? 2 : (s.layout == LRX_LAYOUT_PACKED ? 1 : s.delay);
+    if (s.layout == LRX_LAYOUT_FUSED) return 2;
+    if (s.layout == LRX_LAYOUT_PACKED) return s.delay > 0 ? s.delay : 1;
+    return s.delay;
 }
 
 // Chain helpers (lrx_det.hip).

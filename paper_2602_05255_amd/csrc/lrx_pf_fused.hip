@@ -20,6 +20,7 @@
 // workspace and are summed in a fixed order by the commit kernel.
 #include "lrx_common.hpp"
 #include "lrx_internal.hpp"
+#include "lrx_flush_impl.hpp"
 
 namespace {
 
@@ -159,9 +160,10 @@ __global__ __launch_bounds__(kThreads) void pf_fused_rows_kernel(StepArgs a, int
 }
 
 // ------------------------------------------------------------------ packed storage pass
-// One work-group per tile (I <= J) of walker w.  MODE 0 (accept): decision,
-// pending update, write-back and the tile's partial dots; MODE 1 (flush): the
-// pending update only.  Thread t holds row t / 4 and 16 consecutive columns.
+// One work-group per tile (I <= J) of walker w.  MODE 0 (fused accept): decision,
+// pending update, write-back and the tile's partial dots of A^-1 x; MODE 2 (delayed
+// accept, Sec. III.C): decision and the partial dots of A_0^-1 x, M0 untouched.
+// Thread t holds row t / 4 and 16 consecutive columns.
 template <class T, int MODE>
 __global__ __launch_bounds__(kThreads) void pf_pk_tile_kernel(StepArgs a, int nt, int ntiles) {
     using Wd = typename Wide<T>::type;
@@ -182,11 +184,8 @@ __global__ __launch_bounds__(kThreads) void pf_pk_tile_kernel(StepArgs a, int nt
     const T *rinv = static_cast<const T *>(a.fb) + (size_t)w * a.K * KA * KA;
     const uint8_t *st = a.stash + (size_t)w * a.L.stride;
     const int *kslot = reinterpret_cast<const int *>(st + a.L.kslot);
-    if constexpr (MODE == 0) {
-        if (!pf_take<Wd>(a, w, t == 0, tid, st)) return;
-    }
-    const bool pend = a.tau > 0 && kslot[0] != 0;
-    if (MODE == 1 && !pend) return;
+    if (!pf_take<Wd>(a, w, t == 0, tid, st)) return;
+    const bool pend = MODE == 0 && a.tau > 0 && kslot[0] != 0;
     const T ir = pend ? rinv[2] : zero<T>();
     if (tid < 2 * TS) {
         const int side = tid / TS, rr = tid - side * TS;
@@ -194,7 +193,7 @@ __global__ __launch_bounds__(kThreads) void pf_pk_tile_kernel(StepArgs a, int nt
         const bool in = q < n;
         s_v[side * 3 + 0][rr] = (pend && in) ? fa[q] : zero<T>();
         s_v[side * 3 + 1][rr] = (pend && in) ? fa[n + q] : zero<T>();
-        s_v[side * 3 + 2][rr] = (MODE == 0 && in) ? static_cast<const T *>(a.u)[(size_t)w * n + q] : zero<T>();
+        s_v[side * 3 + 2][rr] = in ? static_cast<const T *>(a.u)[(size_t)w * n + q] : zero<T>();
     }
     __syncthreads();
     const int r = tid >> 2, c0 = (tid & 3) * NE;
@@ -224,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void pf_pk_tile_kernel(StepArgs a, int nt
             st16<T>(prow + e, tmp);
         }
     }
-    if constexpr (MODE == 0) {
+    {
         T *part = static_cast<T *>(a.part) + ((size_t)w * ntiles + t) * 2 * TS;
         // row dots over the tile's columns (rows I of A^-1 x)
         T rp = zero<T>();
@@ -252,25 +251,34 @@ __global__ __launch_bounds__(kThreads) void pf_pk_tile_kernel(StepArgs a, int nt
 }
 
 // ------------------------------------------------------------------ commit
-// After the pass: a taken walker's new update (ax, col, 1/r) becomes its pending
-// slot 0 and log|pf|, phase take the ratio.  A walker that was not taken keeps
-// its pending update; at st->slot == 0 its slot 0 is cleared instead.
-template <class T, bool PACKED>
+// Fused form (DELAYED = false): a taken walker's new update (ax, col, 1/r)
+// becomes its pending slot 0; a walker that was not taken keeps its pending
+// update, and at st->slot == 0 its slot 0 is cleared instead.
+// Delayed packed form (DELAYED = true, Eq. pf_a): slot tau of a taken walker
+// receives a_tau = [A_{tau-1}^-1 x, col] with A_{tau-1}^-1 x = A_0^-1 x (the
+// tiles' partial dots) + sum_te a_te h_te (h = R^-1 a^T x, from the propose),
+// and R_tau^-1; a rejected walker's slot tau is zeroed.  Either way log|pf| and
+// the phase take the ratio of a taken walker.
+template <class T, bool PACKED, bool DELAYED = false>
 __global__ __launch_bounds__(kThreads) void pf_fused_commit_kernel(StepArgs a, int nt, int ntiles) {
     using Wd = typename Wide<T>::type;
     const int w = blockIdx.x, n = a.n, tid = threadIdx.x;
     uint8_t *st = a.stash + (size_t)w * a.L.stride;
     int *kslot = reinterpret_cast<int *>(st + a.L.kslot);
     const T *col = reinterpret_cast<const T *>(st + a.L.c);
+    const T *h = reinterpret_cast<const T *>(st + a.L.g);
     const Wd ratio = *reinterpret_cast<const Wd *>(st + a.L.ratio);
     T *fa = static_cast<T *>(a.fa) + (size_t)w * a.K * KA * n;
     T *rinv = static_cast<T *>(a.fb) + (size_t)w * a.K * KA * KA;
+    const int slot = DELAYED ? a.tau : 0, TE = DELAYED ? a.tau * KA : 0;
+    T *fs = fa + (size_t)slot * KA * n;               // the slot written by this step
+    T *rs = rinv + (size_t)slot * KA * KA;
     const bool take = a.accept[w] != 0 && a.flags[w] == 0 && !is_zero(ratio);
     if (!take) {
-        if (a.tau == 0) {
-            for (int q = tid; q < KA * n; q += kThreads) fa[q] = zero<T>();
-            if (tid < KA * KA) rinv[tid] = zero<T>();
-            if (tid == 0) kslot[0] = 0;
+        if (DELAYED || a.tau == 0) {
+            for (int q = tid; q < KA * n; q += kThreads) fs[q] = zero<T>();
+            if (tid < KA * KA) rs[tid] = zero<T>();
+            if (tid == 0) kslot[slot] = 0;
         }
         return;
     }
@@ -287,17 +295,90 @@ __global__ __launch_bounds__(kThreads) void pf_fused_commit_kernel(StepArgs a, i
         } else {
             ax = fa[(size_t)KA * n + q];
         }
-        fa[q] = ax;
-        fa[n + q] = col[q];
+        for (int te = 0; te < TE; ++te) ax = fmac(fa[(size_t)te * n + q], h[te], ax);   // delayed: slot correction
+        fs[q] = ax;
+        fs[n + q] = col[q];
     }
     if (tid == 0) {
         const T irt = conv<T>(divv(one<Wd>(), ratio));
-        rinv[0] = zero<T>();
-        rinv[1] = -irt;
-        rinv[2] = irt;
-        rinv[3] = zero<T>();
-        kslot[0] = 1;
+        rs[0] = zero<T>();
+        rs[1] = -irt;
+        rs[2] = irt;
+        rs[3] = zero<T>();
+        kslot[slot] = 1;
         accum_logphase(ratio, a.logabs + w, static_cast<Wd *>(a.phase) + w);
+    }
+}
+
+// ------------------------------------------------------------------ packed flush
+// Upper tiles of M0 += sum_{t < tau} a_t R_t^-1 a_t^T (Eq. pf_delayed_Ainv) on the
+// matrix cores: one work-group per stored tile, each wave 16 rows x 64 columns,
+// Atilde[q][te] = sum_s a_t[q][s] R_t^-1[s][te mod KA] formed per 4-deep step.
+// Only the stored tiles are read and written (half the output of the full-storage
+// flush); a diagonal tile's lower half is written as the exact negative of its
+// upper half.  Dead slots hold zeros.
+template <class T>
+__global__ __launch_bounds__(kThreads) void pf_pk_flush_kernel(StepArgs a, int nt, int ntiles) {
+    using R = typename Real<T>::type;
+    using A4 = typename lrxfl::Acc<R>::type;
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int w = lb / ntiles, t = lb - w * ntiles;
+    if (w >= a.W) return;
+    int I = 0, p = t;
+    while (p >= nt - I) { p -= nt - I; ++I; }
+    const int J = I + p;
+    const int n = a.n, TE = a.tau * KA;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lc = lane & 15, kq = lane >> 4;
+    T *P = static_cast<T *>(a.inv) + ((size_t)w * ntiles + t) * TS * TS;
+    const T *fa = static_cast<const T *>(a.fa) + (size_t)w * a.K * KA * n;
+    const T *rinv = static_cast<const T *>(a.fb) + (size_t)w * a.K * KA * KA;
+    const bool diag = I == J;
+    A4 re[4], im[4];
+    const int rl0 = wv * 16;                          // local row base of this wave
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int cl = jb * 16 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rl = rl0 + lrxfl::acc_row<R>(lane, r);
+            const T v = (!diag || rl < cl) ? P[rl * TS + cl] : zero<T>();
+            re[jb][r] = lrxfl::re_(v);
+            im[jb][r] = lrxfl::im_(v);
+        }
+    }
+    const int qa = I * TS + rl0 + lc;                 // this lane's A-operand row
+    for (int te0 = 0; te0 < TE; te0 += 4) {
+        const int te = te0 + kq;
+        T at = zero<T>();
+        if (te < TE && qa < n) {
+            const int ts = te / KA, sp = te - ts * KA;
+            for (int s2 = 0; s2 < KA; ++s2)
+                at = fmac(fa[(size_t)(ts * KA + s2) * n + qa], rinv[(size_t)ts * KA * KA + s2 * KA + sp], at);
+        }
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            const int j = J * TS + jb * 16 + lc;
+            const T av = (te < TE && j < n) ? fa[(size_t)te * n + j] : zero<T>();
+            lrxfl::mac<T>(at, av, re[jb], im[jb]);
+        }
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int cl = jb * 16 + lc, j = J * TS + cl;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rl = rl0 + lrxfl::acc_row<R>(lane, r), q = I * TS + rl;
+            if (q >= n || j >= n) continue;           // entries past n stay zero
+            const T v = lrxfl::make_<T>(re[jb][r], im[jb][r]);
+            if (!diag) {
+                P[rl * TS + cl] = v;
+            } else if (rl < cl) {
+                P[rl * TS + cl] = v;
+                P[cl * TS + rl] = lrxfl::make_<T>(-re[jb][r], -im[jb][r]);
+            } else if (rl == cl) {
+                P[rl * TS + cl] = zero<T>();
+            }
+        }
     }
 }
 
@@ -366,8 +447,15 @@ template <class T> hipError_t fused_accept_t(const StepArgs &a, hipStream_t s) {
     const int nt = (a.n + TS - 1) / TS, ntiles = nt * (nt + 1) / 2;
     if (a.layout == LRX_LAYOUT_PACKED) {
         const size_t lds = sizeof(T) * (size_t)TS * (TS + 1);
-        hipLaunchKernelGGL((pf_pk_tile_kernel<T, 0>), dim3((unsigned)(a.W * ntiles)), dim3(kThreads), lds, s, a, nt,
-                           ntiles);
+        const dim3 grid((unsigned)(a.W * ntiles));
+        if (a.delay > 0) {   // delayed form on packed storage: A_0^-1 x from the tiles, then slot tau
+            hipLaunchKernelGGL((pf_pk_tile_kernel<T, 2>), grid, dim3(kThreads), lds, s, a, nt, ntiles);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL((pf_fused_commit_kernel<T, true, true>), dim3((unsigned)a.W), dim3(kThreads), 0, s, a,
+                               nt, ntiles);
+            return hipGetLastError();
+        }
+        hipLaunchKernelGGL((pf_pk_tile_kernel<T, 0>), grid, dim3(kThreads), lds, s, a, nt, ntiles);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL((pf_fused_commit_kernel<T, true>), dim3((unsigned)a.W), dim3(kThreads), 0, s, a, nt, ntiles);
         return hipGetLastError();
@@ -391,7 +479,7 @@ template <class T> hipError_t fused_accept_t(const StepArgs &a, hipStream_t s) {
 
 template <class T> hipError_t packed_flush_t(const StepArgs &a, hipStream_t s) {
     const int nt = (a.n + TS - 1) / TS, ntiles = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL((pf_pk_tile_kernel<T, 1>), dim3((unsigned)(a.W * ntiles)), dim3(kThreads), 0, s, a, nt, ntiles);
+    hipLaunchKernelGGL(pf_pk_flush_kernel<T>, dim3((unsigned)(a.W * ntiles)), dim3(kThreads), 0, s, a, nt, ntiles);
     return hipGetLastError();
 }
 

@@ -282,6 +282,8 @@ def test_layout_sizes_and_checks():
     # at n = 1024 the packed triangle is 136 of 256 tiles
     big = lrx.lrx_state_sizes(lrx.LRX_PF, lrx.LRX_F32, 1, 1024, 1, 0, lrx.LRX_LAYOUT_PACKED)
     assert big["inv"] == 136 * 4096 * 4
+    pdel = lrx.lrx_state_sizes(lrx.LRX_PF, lrx.LRX_C128, W, n, 1, 4, lrx.LRX_LAYOUT_PACKED)
+    assert pdel["inv"] == packed["inv"] and pdel["fa"] == W * 4 * 2 * n * es and pdel["fb"] == W * 4 * 4 * es
     for args in [(lrx.LRX_DET, lrx.LRX_F64, 2, 8, 1, 0, lrx.LRX_LAYOUT_FUSED),      # DET
                  (lrx.LRX_PF, lrx.LRX_C64, 2, 8, 1, 4, lrx.LRX_LAYOUT_FUSED),       # delayed
                  (lrx.LRX_PF, lrx.LRX_C64, 2, 8, 2, 0, lrx.LRX_LAYOUT_PACKED),      # k_max 2

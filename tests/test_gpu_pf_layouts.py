@@ -100,6 +100,43 @@ def test_pf_layout_read_inverse_with_pending(layout):
         assert np.array_equal(m0, -np.swapaxes(m0, 1, 2)), "the pass keeps M0 exactly skew"
 
 
+@pytest.mark.parametrize("dt,n,K,W,steps", [
+    ("c128", 130, 5, 5, 23),       # ragged last tile row, flushes inside the chain
+    ("f64", 200, 8, 4, 26),
+    ("c128", 64, 32, 3, 36),       # one tile, the Pfaffian workload's delay length
+])
+def test_pf_packed_delayed_chain(dt, n, K, W, steps):
+    """Delayed updates on packed skew storage (A_0^-1 x from the upper tiles, the flush writing
+    the stored tiles only) against the oracle chain; read-outs mid-window equal the oracle's A^-1
+    and are exactly skew."""
+    say(f"pf packed delayed dt={dt} n={n} K={K}")
+    cplx = dt.startswith("c")
+    g, f, occ, emp = pf_inputs(990 + n + K, 2 * n, n, W, cplx)
+    draws = [gen.hop_draws(g, W, n, n, (1,), 1) for _ in range(steps)]
+    u01 = [gen.uniforms(g, W) for _ in range(steps)]
+    wk = Walkers(lrx.LRX_PF, DT[dt], f, occ, emp, 1, K, layout=PACKED)
+    chain = orc.PfChain(f, occ, emp)
+    stats = []
+    worst_r, worst_m, la, ph = run_chain(wk, chain, draws, u01, check_every=7, tol_ratio=1e-10, tol_inv=1e-10,
+                                         bound_fn=pf_bound_fn(f), growth=lambda t: 1.0 + t, stats=stats)
+    say(f"  max rel err ratio {worst_r:.2e} inverse {worst_m:.2e}")
+    np.testing.assert_allclose(la, chain.logabs, atol=1e-8)
+    np.testing.assert_allclose(ph, chain.phase, atol=1e-8)
+    # a few more steps without a flush: the read-out carries the live slots
+    for t in range(min(3, K - 1)):
+        k, elec, slot = gen.hop_draws(g, W, n, n, (1,), 1)
+        wk.set_draws(k, elec, slot)
+        wk.propose()
+        r_o = chain.propose(k, elec, slot)
+        mask = np.abs(r_o) > 0.3
+        wk.decide(mask=mask)
+        wk.apply()
+        chain.accept(k, elec, slot, mask)
+    m = read_inverse(wk)
+    assert np.array_equal(m, -np.swapaxes(m, 1, 2))
+    assert rel_err(m, chain.inv, axis=(1, 2)).max() <= 1e-10
+
+
 def test_pf_read_inverse_delayed_full_layout():
     """read_inverse of a delayed full-storage state mid-window (M0 plus live slots)."""
     say("pf read-out delayed")
@@ -145,8 +182,10 @@ def test_pf_layouts_agree_at_workload_shape():
     say("pf layouts at n=512")
     n, L, W, steps = 512, 1024, 32, 16
     g, f, occ, emp = pf_inputs(970, L, n, W, True)
-    lays = (lrx.LRX_LAYOUT_FULL, FUSED, PACKED)
-    wks = {lay: Walkers(lrx.LRX_PF, torch.complex128, f, occ, emp, 1, 0, layout=lay) for lay in lays}
+    lays = (lrx.LRX_LAYOUT_FULL, FUSED, PACKED, "packed_delayed")
+    wks = {lay: Walkers(lrx.LRX_PF, torch.complex128, f, occ, emp, 1, 0, layout=lay) for lay in lays[:3]}
+    wks["packed_delayed"] = Walkers(lrx.LRX_PF, torch.complex128, f, occ, emp, 1, 6, layout=PACKED)
+    NAME["packed_delayed"] = "packed delayed (K = 6)"
     sample = np.array([3, 21])
     chain = orc.PfChain(f, occ[sample], emp[sample])
     taken = 0
@@ -156,7 +195,7 @@ def test_pf_layouts_agree_at_workload_shape():
         for lay, wk in wks.items():
             wk.set_draws(k, elec, slot)
             rs[lay] = wk.propose().cpu().numpy()
-        for lay in (FUSED, PACKED):
+        for lay in lays[1:]:
             assert rel_err(rs[lay], rs[lrx.LRX_LAYOUT_FULL]).max() <= 1e-9, (NAME[lay], t)
         mask = np.abs(rs[lrx.LRX_LAYOUT_FULL]) > 0.3
         taken += int(mask.sum())
@@ -169,7 +208,7 @@ def test_pf_layouts_agree_at_workload_shape():
     say(f"  accepted {taken} of {W * steps}")
     ref = read_inverse(wks[lrx.LRX_LAYOUT_FULL])
     assert rel_err(ref[sample], chain.inv, axis=(1, 2)).max() <= 1e-9
-    for lay in (FUSED, PACKED):
+    for lay in lays[1:]:
         np.testing.assert_array_equal(wks[lay].occ.cpu().numpy(), wks[lrx.LRX_LAYOUT_FULL].occ.cpu().numpy())
         m = read_inverse(wks[lay])
         e = rel_err(m, ref, axis=(1, 2))
