@@ -699,7 +699,7 @@ def bench_uneven(wl, args, torch):
     # delay window and a multiple of 32 steps since its refresh, 4 sampled walkers
     # against the same-GPU FP64 recompute
     def profile(mode, what):
-        rows = []
+        rows, by_n = [], {}
 
         def probe(kind, part, since):
             if since % 32:
@@ -710,10 +710,23 @@ def bench_uneven(wl, args, torch):
                 idx = torch.as_tensor(np.linspace(0, Wq - 1, 4).astype(int), device="cuda")
                 a_, b_ = state_error(torch, q, idx, q.table, "det", False)
                 rows.append((since, a_, b_))
+                by_n.setdefault(int(q.st.n), []).append((since, a_))
         batch.period(mode, probe)
         torch.cuda.synchronize()
-        return summarize_errors(rows, f"FP64 full recompute on the same GPU (torch.linalg), {what}, 4 sampled "
-                                      "walkers per class or sub-batch at every 32 steps since its refresh", 4)
+        out = summarize_errors(rows, f"FP64 full recompute on the same GPU (torch.linalg), {what}, 4 sampled "
+                                     "walkers per class or sub-batch at every 32 steps since its refresh", 4)
+        # per size class, at its largest steps since refresh: max and median inverse error, and
+        # the share of sampled walker-states (all probe points) above 1e-3 relative
+        cls = {}
+        for n_, rs in sorted(by_n.items()):
+            last = max(r[0] for r in rs)
+            e_last = np.concatenate([r[1] for r in rs if r[0] == last])
+            e_all = np.concatenate([r[1] for r in rs])
+            cls[n_] = {"steps_since_refresh": int(last), "inverse_max": float(e_last.max()),
+                       "inverse_median": float(np.median(e_last)),
+                       "share_above_1e-3": float(np.mean(e_all > 1e-3)), "samples": int(e_all.size)}
+        out["by_class"] = cls
+        return out
     err = profile(lrx.LRX_MH_DEVICE_RNG, "Metropolis chain")
     err["forced_accept"] = profile(lrx.LRX_MH_FORCE, "forced-accept chain")
     dom = max((v for v in per_class.values() if v.get("schedule") == "per-step"),

@@ -28,6 +28,10 @@ from . import inputs as gen
 from . import lrx
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lrx", "autotune.json")
+# Measured results shipped with the package (the same JSON layout as the cache, keyed by
+# device name): consulted when the user cache has no entry, so that a device of a tuned
+# model starts from the same schedule every time instead of re-timing it.
+SEED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_seed.json")
 
 
 def cache_path():
@@ -42,6 +46,15 @@ def _load(path):
         return {}
 
 
+def _entry(table, key):
+    """The entry for key from the cache table, else from the shipped seed (None if neither)."""
+    if key in table:
+        return table[key]
+    if os.environ.get("LRX_TUNE_NO_SEED"):
+        return None
+    return _load(SEED).get(key)
+
+
 def _store(path, table):
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     tmp = path + ".tmp"
@@ -51,7 +64,11 @@ def _store(path, table):
 
 
 def _device_key(device):
-    return torch.cuda.get_device_name(device).replace(" ", "_")
+    """Architecture and compute-unit count (the marketing name is not reliable: some
+    tools report it empty)."""
+    prop = torch.cuda.get_device_properties(device)
+    arch = str(getattr(prop, "gcnArchName", "") or torch.cuda.get_device_name(device)).split(":")[0]
+    return f"{arch.replace(' ', '_')}|cu{prop.multi_processor_count}"
 
 
 def delay_candidates(n, k_max, ranks):
@@ -119,7 +136,7 @@ def tune_class(dtype, n, k_max, ranks, walkers=512, device="cuda", cache=None, s
     table = _load(path)
     dname = str(dtype).replace("torch.", "")
     key = f"{_device_key(device)}|{dname}|n={n}|kmax={k_max}|ranks={list(ranks)}|v3"
-    hit = table.get(key, {})
+    hit = _entry(table, key) or {}
     if all(f in hit for f in ("delay", "rows_per_block", "window")):
         out = {"delay": int(hit["delay"]), "rows_per_block": int(hit["rows_per_block"]), "window": bool(hit["window"])}
         lrx.lrx_autotune_store(dtype, n, k_max, out["delay"], out["rows_per_block"], 0, out["window"])
@@ -163,8 +180,9 @@ def tune_grid(uw, candidates=(1, 2, 3, 4), cache=None):
     shape = ",".join(f"{p.st.n}x{p.st.walkers}/K{p.st.delay}" for p in uw.parts)
     key = f"{_device_key(dev)}|grid|{str(uw.parts[0].st.dtype).replace('torch.', '')}|kmax={uw.k_max}|{shape}"
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
-    if key in table and "wgs_per_cu" in table[key]:
-        uw.grid = int(table[key]["wgs_per_cu"]) * cus
+    hit = _entry(table, key)
+    if hit is not None and "wgs_per_cu" in hit:
+        uw.grid = int(hit["wgs_per_cu"]) * cus
         return uw.grid
     # the trial windows advance the chains; keep the caller's state out of it
     snap = [(p.st.buffers["inv"].clone(), p.st.buffers["fa"].clone(), p.st.buffers["fb"].clone(),
