@@ -28,6 +28,8 @@
 //                  X += Z X[P rows].
 //   final kernel : undo the row pivoting as a column permutation, cast to the
 //                  bulk dtype, and (refresh) measure the drift of the old state.
+#include <algorithm>
+
 #include "lrx_common.hpp"
 #include "lrx_flush_impl.hpp"
 #include "lrx_internal.hpp"
@@ -55,7 +57,7 @@ struct DetAcc {          // per-walker accumulators in the workspace
 };
 
 struct WorkLayout {
-    size_t x, z, piv, src, perm, acc, stride;
+    size_t x, x2, z, piv, src, perm, acc, stride;
 };
 
 // Columns per lane of the register-resident block kernel: the block is 4 CPT
@@ -66,10 +68,12 @@ template <class Wd> int block_cpt(int n) {
     return n <= 512 ? 8 : 2;
 }
 
-inline WorkLayout work_layout(int n, size_t ws) {
+// x2: the second matrix the Parlett-Reid panels alternate with (PF only).
+inline WorkLayout work_layout(int n, size_t ws, bool pf) {
     WorkLayout L;
     size_t off = 0;
     L.x = off; off += al((size_t)n * n * ws);
+    L.x2 = off; off += pf ? al((size_t)n * n * ws) : 0;
     L.z = off; off += al((size_t)n * 32 * ws);
     L.piv = off; off += al((size_t)n * 4);
     L.src = off; off += al((size_t)n * 4);
@@ -223,22 +227,33 @@ __device__ int block_argmax(double val, int idx, double *s_val, int *s_idx) {
 }
 
 // ------------------------------------------------------------------ Parlett-Reid
-// One work-group per matrix, on the workspace copy X of A (PF only), in the
-// every-other-column form: for j = 0, 2, ...: pivot p = argmax_{i>j} |A[j][i]|
-// (|A[i][j]| by skewness), swap index j+1 <-> p (rows and columns, sign flip),
-// alpha = A[j][j+1] (the Pfaffian gains the factor alpha), then the skew
-// rank-2 update A[r][s] += w_r c_s - c_r w_s (r, s >= j+2) with
-// c = A[j][j+2:] / alpha and w = A[j+1][j+2:]  (Appendix A: pf(B A B^T) =
-// det(B) pf(A), and the block Schur step of Eq. pf_block).
+// Per matrix, on the workspace copy X of A (PF only), in the every-other-column
+// form: for j = 0, 2, ...: pivot p = argmax_{i>j} |A[j][i]| (|A[i][j]| by
+// skewness), swap index j+1 <-> p (rows and columns, sign flip), alpha =
+// A[j][j+1] (the Pfaffian gains the factor alpha), then the skew rank-2 update
+// A[r][s] += w_r c_s - c_r w_s (r, s >= j+2) with c = A[j][j+2:] / alpha and
+// w = A[j+1][j+2:]  (Appendix A: pf(B A B^T) = det(B) pf(A), and the block
+// Schur step of Eq. pf_block).
 //
-// Blocked: the rank-2 updates of kPrPairs consecutive pairs are kept as
-// pending vectors (c_t, w_t) in the workspace; the two rows each pair needs
-// are rebuilt from X plus the pending terms, swaps are applied to X and to
-// the pending vectors alike, and at the end of the block the trailing matrix
-// takes all pending terms in one MFMA GEMM of inner dimension 2 kPrPairs
-// (X[J][J] += P Q^T with P = [w_t, -c_t], Q = [c_t, w_t]).  X is then read and
-// written once per block instead of once per pair.
-constexpr int kPrPairs = 16;
+// Blocked in panels of P pairs, two launches per panel:
+//   panel kernel: one work-group per matrix takes the panel's pairs one after
+//                 the other.  Their rank-2 updates stay pending as vectors
+//                 (c_t, w_t) in LDS, and the two rows a pair needs (its pivot
+//                 row j+1 and the next pair's row j+2) are rebuilt from X plus
+//                 the pending terms.  Swaps are not applied to X: a logical ->
+//                 physical index map (the identity at the panel's start) is
+//                 permuted instead, with the pending vectors and the current
+//                 row, so a pair costs one gather of two rows of X, LDS work
+//                 and three barriers.
+//   trail kernel: the panel's trailing matrix, one 64 x 64 tile per
+//                 work-group over all matrices: X'[r][s] = X[pm r][pm s] +
+//                 sum_t w_t[r] c_t[s] - c_t[r] w_t[s], an MFMA GEMM of inner
+//                 dimension 2P started from the gathered tile, written out of
+//                 place to the second workspace matrix in logical order.
+// X is read and written once per panel, by the whole GPU.  P is the largest
+// count (at most 16) whose 2P pending rows, current row and index map fit in
+// one work-group's LDS.
+constexpr int kPrMaxPairs = 16;          // the workspace Z holds 2 x 16 pending rows
 constexpr int kPrThreads = 512;
 
 // Pivot key: |x| for real, |x|^2 for complex (same order, no square root).
@@ -247,118 +262,82 @@ __device__ __forceinline__ double pivkey(cf64 v) { return v.x * v.x + v.y * v.y;
 __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
 __device__ __forceinline__ cf64 recip(cf64 v) { return divv(one<cf64>(), v); }
 
-// X[r][s] += sum_{t<T} w_t[r] c_t[s] - c_t[r] w_t[s] for r, s in [j0, n).
-// 64 x 64 tiles, one per four waves; wave wv % 4 owns 16 rows of its tile as
-// four 16x16 MFMA blocks.
-template <class Wd>
-__device__ __forceinline__ void pr_trailing_update(Wd *X, const Wd *Cp, const Wd *Wp, int n, int T, int j0) {
-    using R = typename Real<Wd>::type;
-    using A4 = typename Acc<R>::type;
-    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) & 3, kq = lane >> 4, lc = lane & 15;
-    const int m = n - j0, nt = (m + 63) / 64, K2 = 2 * T;
-    for (int tile = threadIdx.x >> 8; tile < nt * nt; tile += kPrThreads / 256) {
-        const int r0 = j0 + (tile / nt) * 64, s0 = j0 + (tile % nt) * 64;
-        const int rbase = r0 + wv * 16;
-        A4 re[4], im[4];
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const int sc = min(s0 + jb * 16 + lc, n - 1);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const Wd v = X[(size_t)min(rbase + acc_row<R>(lane, r), n - 1) * n + sc];
-                re[jb][r] = re_(v);
-                im[jb][r] = im_(v);
-            }
-        }
-        const int ra = min(rbase + lc, n - 1);
-        for (int k0 = 0; k0 < K2; k0 += 4) {
-            const int k = k0 + kq;
-            const bool kin = k < K2;
-            const int t = kin ? (k < T ? k : k - T) : 0;
-            // P[r][k]: w_k[r] (k < T), -c_{k-T}[r]; Q[k][s]: c_k[s] (k < T), w_{k-T}[s]
-            const Wd *pa = (k < T ? Wp : Cp) + (size_t)t * n;
-            const Wd *qb = (k < T ? Cp : Wp) + (size_t)t * n;
-            Wd av = pa[ra];
-            av = !kin ? zero<Wd>() : (k < T ? av : -av);
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) {
-                const Wd bv = kin ? qb[min(s0 + jb * 16 + lc, n - 1)] : zero<Wd>();
-                mac<Wd>(av, bv, re[jb], im[jb]);
-            }
-        }
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const int sc = s0 + jb * 16 + lc;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int q = rbase + acc_row<R>(lane, r);
-                if (q < n && sc < n) X[(size_t)q * n + sc] = make_<Wd>(re[jb][r], im[jb][r]);
-            }
-        }
-    }
+template <class Wd> __device__ __forceinline__ Wd *pr_buf(const FA &a, int w, int b) {
+    return reinterpret_cast<Wd *>(a.work + (size_t)w * a.L.stride + (b ? a.L.x2 : a.L.x));
+}
+
+template <class Wd> size_t pr_lds(int n, int P) {
+    return sizeof(Wd) * ((size_t)2 * P * n + n) + sizeof(int) * (size_t)n;
+}
+template <class Wd> int pr_pairs(int n, size_t budget) {
+    const size_t fixed = sizeof(Wd) * (size_t)n + sizeof(int) * (size_t)n;
+    const size_t per = sizeof(Wd) * (size_t)2 * n;
+    const size_t p = budget > fixed ? (budget - fixed) / per : 0;
+    return (int)std::min<size_t>(std::max<size_t>(p, 1), kPrMaxPairs);
 }
 
 template <class Wd>
-__global__ __launch_bounds__(kPrThreads) void parlett_reid_kernel(FA a) {
-    __shared__ Wd s_rj[LRX_MAX_N];                // row j of the current matrix (entries > j)
-    __shared__ Wd s_cf[2 * kPrPairs];            // c_t[i], w_t[i] at the row being rebuilt
+__global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int P, int cur) {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_val[kPrThreads / 64];
     __shared__ int s_idx[kPrThreads / 64];
     const int w = blockIdx.x, n = a.n, tid = threadIdx.x;
-    Wd *X = wX<Wd>(a, w);
-    Wd *Cp = wZ<Wd>(a, w);                       // [kPrPairs][n]
-    Wd *Wp = Cp + (size_t)kPrPairs * n;          // [kPrPairs][n]
+    Wd *s_c = reinterpret_cast<Wd *>(smem);             // [P][n] pending c_t, logical index
+    Wd *s_w = s_c + (size_t)P * n;                      // [P][n] pending w_t
+    Wd *s_rj = s_w + (size_t)P * n;                     // [n]    row j of the current matrix
+    int *s_pm = reinterpret_cast<int *>(s_rj + n);      // [n]    logical -> physical index in X
     DetAcc *d = wAcc(a, w);
+    const Wd *X = pr_buf<Wd>(a, w, cur);
+    Wd *Cg = wZ<Wd>(a, w);                              // [kPrMaxPairs][n], for the trail kernel
+    Wd *Wg = Cg + (size_t)kPrMaxPairs * n;
     double la = 0.0;
     Wd ph = one<Wd>();
-    bool zero_pf = (n & 1) != 0;
-    int T = 0;
-    // row i of the current matrix at entry e: X[i][e] + sum_t (w_t[i] c_t[e] - c_t[i] w_t[e]),
-    // with s_cf holding c_t[i], w_t[i]
-    auto cur = [&](int i, int e) {
-        Wd v = X[(size_t)i * n + e];
-        for (int t = 0; t < T; ++t) v = v + (s_cf[kPrPairs + t] * Cp[(size_t)t * n + e] - s_cf[t] * Wp[(size_t)t * n + e]);
-        return v;
-    };
-    for (int j = 0; j + 1 < n && !zero_pf; j += 2) {
-        if (tid < T) { s_cf[tid] = Cp[(size_t)tid * n + j]; s_cf[kPrPairs + tid] = Wp[(size_t)tid * n + j]; }
-        __syncthreads();
+    if (j0 > 0) {
+        if (d->pf_zero) return;
+        la = d->pf_logabs;
+        ph = get_ph<Wd>(d->pf_ph);
+    } else if (n & 1) {                                 // odd order: pf = 0
+        if (tid == 0) { d->pf_zero = 1; d->pf_logabs = -INFINITY; set_ph(d->pf_ph, zero<Wd>()); }
+        return;
+    }
+    for (int e = j0 + tid; e < n; e += kPrThreads) {
+        s_pm[e] = e;
+        s_rj[e] = X[(size_t)j0 * n + e];
+    }
+    __syncthreads();
+    const int pairs = min(P, (n - j0) / 2);
+    bool zero_pf = false;
+    for (int t = 0; t < pairs; ++t) {
+        const int j = j0 + 2 * t, q = j + 1;
+        // row j takes the previous pair's term (the others are in already),
+        // then the pivot search over its entries > j
+        const Wd *lc = s_c + (size_t)(t > 0 ? t - 1 : 0) * n;
+        const Wd *lw = s_w + (size_t)(t > 0 ? t - 1 : 0) * n;
+        const Wd cl = t > 0 ? lc[j] : zero<Wd>(), wl = t > 0 ? lw[j] : zero<Wd>();
         double bv = -1.0;
         int bi = -1;
-        for (int i = j + 1 + tid; i < n; i += kPrThreads) {
-            const Wd v = cur(j, i);
-            s_rj[i] = v;
+        for (int e = q + tid; e < n; e += kPrThreads) {
+            Wd v = s_rj[e];
+            if (t > 0) v = v + (wl * lc[e] - cl * lw[e]);
+            s_rj[e] = v;
             const double kv = pivkey(v);
-            if (bi < 0 || kv > bv) { bv = kv; bi = i; }
+            if (bi < 0 || kv > bv) { bv = kv; bi = e; }
         }
         const int p = block_argmax<kPrThreads>(bv, bi, s_val, s_idx);
-        const int q = j + 1;
         if (p != q) {
-            // swap index q <-> p: rows of X (entries >= j), the pending vectors, row j
-            for (int c = j + tid; c < n; c += kPrThreads) {
-                const Wd t0 = X[(size_t)q * n + c];
-                X[(size_t)q * n + c] = X[(size_t)p * n + c];
-                X[(size_t)p * n + c] = t0;
-            }
-            if (tid < T) {
-                Wd t0 = Cp[(size_t)tid * n + q];
-                Cp[(size_t)tid * n + q] = Cp[(size_t)tid * n + p];
-                Cp[(size_t)tid * n + p] = t0;
-                t0 = Wp[(size_t)tid * n + q];
-                Wp[(size_t)tid * n + q] = Wp[(size_t)tid * n + p];
-                Wp[(size_t)tid * n + p] = t0;
-            }
+            // swap index q <-> p in the map, the current row and the pending vectors
             if (tid == 0) {
-                const Wd t0 = s_rj[q];
+                const int ti = s_pm[q];
+                s_pm[q] = s_pm[p];
+                s_pm[p] = ti;
+                const Wd tv = s_rj[q];
                 s_rj[q] = s_rj[p];
-                s_rj[p] = t0;
+                s_rj[p] = tv;
             }
-            __syncthreads();
-            // columns of X (rows >= j)
-            for (int r = j + tid; r < n; r += kPrThreads) {
-                const Wd t0 = X[(size_t)r * n + q];
-                X[(size_t)r * n + q] = X[(size_t)r * n + p];
-                X[(size_t)r * n + p] = t0;
+            if (tid < t) {
+                Wd *c = s_c + (size_t)tid * n, *wv = s_w + (size_t)tid * n;
+                Wd tv = c[q]; c[q] = c[p]; c[p] = tv;
+                tv = wv[q]; wv[q] = wv[p]; wv[p] = tv;
             }
             ph = -ph;
         }
@@ -367,31 +346,119 @@ __global__ __launch_bounds__(kPrThreads) void parlett_reid_kernel(FA a) {
         if (is_zero(alpha)) { zero_pf = true; break; }
         la += log(absv(alpha));
         ph = ph * unit(alpha);
-        if (tid < T) { s_cf[tid] = Cp[(size_t)tid * n + q]; s_cf[kPrPairs + tid] = Wp[(size_t)tid * n + q]; }
-        __syncthreads();
-        // the new pending pair: c = row j / alpha, w = row j+1, on entries > j+1
         const Wd inva = recip(alpha);
-        for (int i = tid; i < n; i += kPrThreads) {
-            Wd c = zero<Wd>(), wv = zero<Wd>();
-            if (i > q) {
-                wv = cur(q, i);
-                c = s_rj[i] * inva;
+        // the new pending pair (c = row j / alpha, w = row q) and row j+2 up
+        // to this pair's term, on entries > q
+        const bool more = t + 1 < pairs;
+        const int j2 = more ? j + 2 : q;
+        const Wd *x1 = X + (size_t)s_pm[q] * n;
+        const Wd *x2 = X + (size_t)s_pm[j2] * n;
+        Wd *ct = s_c + (size_t)t * n, *wt = s_w + (size_t)t * n;
+        for (int e = q + 1 + tid; e < n; e += kPrThreads) {
+            const int pe = s_pm[e];
+            Wd wv = x1[pe];
+            Wd rv = more ? x2[pe] : zero<Wd>();
+            for (int u = 0; u < t; ++u) {
+                const Wd *cu = s_c + (size_t)u * n, *wu = s_w + (size_t)u * n;
+                const Wd ce = cu[e], we = wu[e];
+                wv = wv + (wu[q] * ce - cu[q] * we);
+                if (more) rv = rv + (wu[j2] * ce - cu[j2] * we);
             }
-            Cp[(size_t)T * n + i] = c;
-            Wp[(size_t)T * n + i] = wv;
+            const Wd c = s_rj[e] * inva;
+            ct[e] = c;
+            wt[e] = wv;
+            if (more) s_rj[e] = rv;
         }
-        ++T;
         __syncthreads();
-        if (T == kPrPairs || j + 3 >= n) {
-            if (j + 2 < n) pr_trailing_update<Wd>(X, Cp, Wp, n, T, j + 2);
-            T = 0;
-            __syncthreads();
-        }
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         d->pf_zero = zero_pf ? 1 : 0;
         d->pf_logabs = zero_pf ? -INFINITY : la;
         set_ph(d->pf_ph, zero_pf ? zero<Wd>() : ph);
+    }
+    // the map and the pending vectors as the last swap left them, on the
+    // entries the trail kernel reads
+    int *pm = wPerm(a, w);
+    for (int e = j0 + tid; e < n; e += kPrThreads) pm[e] = s_pm[e];
+    if (zero_pf) return;
+    const int j1 = j0 + 2 * pairs;
+    for (int t = 0; t < pairs; ++t) {
+        for (int e = j1 + tid; e < n; e += kPrThreads) {
+            Cg[(size_t)t * n + e] = s_c[(size_t)t * n + e];
+            Wg[(size_t)t * n + e] = s_w[(size_t)t * n + e];
+        }
+    }
+}
+
+// The trailing matrix of the panel that ended at j1 (T pairs): 64 x 64 tile
+// (I, J), I <= J, of X' = X[pm][pm] + P Q^T with P = [w_t, -c_t], Q = [c_t,
+// w_t]; wave wv owns 16 rows of the tile as four 16x16 MFMA blocks.  X' is
+// skew like X, so only the upper tiles are computed: an off-diagonal tile is
+// stored twice, as itself and negated at the mirrored position; a diagonal
+// tile is stored as computed.  Rows and columns beyond n are clamped on load
+// and dropped on store.
+template <class Wd>
+__global__ __launch_bounds__(kT) void pr_trail_kernel(FA a, int j1, int T, int cur, int nt) {
+    using R = typename Real<Wd>::type;
+    using A4 = typename Acc<R>::type;
+    const int per = nt * (nt + 1) / 2;
+    const int w = blockIdx.x / per;
+    int tile = blockIdx.x - w * per, ti = 0;
+    while (tile >= nt - ti) { tile -= nt - ti; ++ti; }
+    const int tj = ti + tile;
+    if (wAcc(a, w)->pf_zero) return;
+    const int n = a.n;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kq = lane >> 4, lc = lane & 15;
+    const Wd *X = pr_buf<Wd>(a, w, cur);
+    Wd *Y = pr_buf<Wd>(a, w, cur ^ 1);
+    const Wd *Cp = wZ<Wd>(a, w);
+    const Wd *Wp = Cp + (size_t)kPrMaxPairs * n;
+    const int *pm = wPerm(a, w);
+    const int r0 = j1 + ti * 64, s0 = j1 + tj * 64;
+    const int rbase = r0 + wv * 16, K2 = 2 * T;
+    int pcol[4], prow[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) pcol[jb] = pm[min(s0 + jb * 16 + lc, n - 1)];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) prow[r] = pm[min(rbase + acc_row<R>(lane, r), n - 1)];
+    A4 re[4], im[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const Wd v = X[(size_t)prow[r] * n + pcol[jb]];
+            re[jb][r] = re_(v);
+            im[jb][r] = im_(v);
+        }
+    }
+    const int ra = min(rbase + lc, n - 1);
+    for (int k0 = 0; k0 < K2; k0 += 4) {
+        const int k = k0 + kq;
+        const bool kin = k < K2;
+        const int t = kin ? (k < T ? k : k - T) : 0;
+        const Wd *pa = (k < T ? Wp : Cp) + (size_t)t * n;
+        const Wd *qb = (k < T ? Cp : Wp) + (size_t)t * n;
+        Wd av = pa[ra];
+        av = !kin ? zero<Wd>() : (k < T ? av : -av);
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            const Wd bv = kin ? qb[min(s0 + jb * 16 + lc, n - 1)] : zero<Wd>();
+            mac<Wd>(av, bv, re[jb], im[jb]);
+        }
+    }
+    const bool mirror = ti != tj;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int sc = s0 + jb * 16 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = rbase + acc_row<R>(lane, r);
+            if (q < n && sc < n) {
+                const Wd v = make_<Wd>(re[jb][r], im[jb][r]);
+                Y[(size_t)q * n + sc] = v;
+                if (mirror) Y[(size_t)sc * n + q] = -v;
+            }
+        }
     }
 }
 
@@ -1193,6 +1260,40 @@ hipError_t launch_block(const FA &fa, int j0, int nbw, int write_z, int o0, hipS
     return hipGetLastError();
 }
 
+template <class Wd>
+hipError_t launch_pr(const FA &fa, hipStream_t s) {
+    const int n = fa.n;
+    int dev = 0, lds_max = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    // the kernel's static arrays and a margin stay out of the budget
+    const int P = pr_pairs<Wd>(n, lds_max > 1024 ? (size_t)lds_max - 1024 : 0);
+    const size_t lds = pr_lds<Wd>(n, P);
+    if (lds > 65536) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&pr_panel_kernel<Wd>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((unsigned)fa.W), block(kPrThreads);
+    if (n & 1) {                                        // records pf = 0
+        hipLaunchKernelGGL(pr_panel_kernel<Wd>, grid, block, lds, s, fa, 0, P, 0);
+        return hipGetLastError();
+    }
+    int cur = 0;
+    for (int j0 = 0; j0 < n; j0 += 2 * P) {
+        hipLaunchKernelGGL(pr_panel_kernel<Wd>, grid, block, lds, s, fa, j0, P, cur);
+        const int j1 = j0 + 2 * P;
+        if (j1 < n) {
+            const int nt = (n - j1 + 63) / 64;
+            hipLaunchKernelGGL(pr_trail_kernel<Wd>, dim3((unsigned)(fa.W * nt * (nt + 1) / 2)), dim3(kT), 0, s, fa, j1,
+                               P, cur, nt);
+            cur ^= 1;
+        }
+    }
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     using Wd = typename Wide<T>::type;
@@ -1200,7 +1301,7 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     a.kind = in.kind; a.W = in.W; a.n = in.n; a.sites = in.sites;
     a.src = in.src; a.occ = in.occ;
     a.work = static_cast<uint8_t *>(in.work);
-    a.L = work_layout(in.n, sizeof(Wd));
+    a.L = work_layout(in.n, sizeof(Wd), in.kind == LRX_PF);
     a.inv = in.inv; a.logabs = in.logabs; a.phase = in.phase; a.flags = in.flags;
     a.report = in.report; a.refresh = in.refresh; a.packed = in.packed;
     const int n = in.n, W = in.W;
@@ -1209,7 +1310,7 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     hipLaunchKernelGGL(init_acc_kernel<Wd>, dim3((W + 255) / 256), dim3(256), 0, s, a);
     if (a.kind == LRX_PF) {
         hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
-        hipLaunchKernelGGL(parlett_reid_kernel<Wd>, dim3(W), dim3(kPrThreads), 0, s, a);
+        if ((e = launch_pr<Wd>(a, s)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1251,8 +1352,7 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
 namespace lrx {
 
 size_t factor_work_bytes(int kind, int dtype, int W, int n) {
-    (void)kind;
-    return (size_t)W * work_layout(n, wide_bytes(dtype)).stride;
+    return (size_t)W * work_layout(n, wide_bytes(dtype), kind == LRX_PF).stride;
 }
 
 hipError_t factor(const FactorArgs &a, hipStream_t s) {
