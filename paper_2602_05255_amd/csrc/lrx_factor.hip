@@ -9,7 +9,8 @@
 //        brings the largest entry of the leading column next to the diagonal,
 //        pf(B A B^T) = det(B) pf(A), then the block Schur step of Appendix A,
 //        Eq. pf_block, which splits off a 2x2 block whose Pfaffian is its (0,1)
-//        entry); A^-1 by the same Gauss-Jordan kernels, then M = (X - X^T)/2.
+//        entry); A^-1 from the same factorisation, A = Pi U^T D U Pi^T, as
+//        Pi U^-1 D^-1 U^-T Pi^T, then M = (X - X^T)/2.
 //
 // Two-level blocked Gauss-Jordan (all in the workspace X, row-major).  The
 // columns are taken in outer panels of up to 64; inside an outer panel, blocks
@@ -57,7 +58,7 @@ struct DetAcc {          // per-walker accumulators in the workspace
 };
 
 struct WorkLayout {
-    size_t x, x2, z, piv, src, perm, acc, stride;
+    size_t x, x2, x3, z, piv, src, perm, orig, ia, acc, stride;
 };
 
 // Columns per lane of the register-resident block kernel: the block is 4 CPT
@@ -68,16 +69,22 @@ template <class Wd> int block_cpt(int n) {
     return n <= 512 ? 8 : 2;
 }
 
-// x2: the second matrix the Parlett-Reid panels alternate with (PF only).
+// PF only: x2, the second matrix the Parlett-Reid panels alternate with; x3,
+// the columns of L; orig, the original index of every position; ia, 1 / alpha
+// of every pair.
 inline WorkLayout work_layout(int n, size_t ws, bool pf) {
     WorkLayout L;
     size_t off = 0;
-    L.x = off; off += al((size_t)n * n * ws);
-    L.x2 = off; off += pf ? al((size_t)n * n * ws) : 0;
+    const size_t mat = al((size_t)n * n * ws);
+    L.x = off; off += mat;
+    L.x2 = off; off += pf ? mat : 0;
+    L.x3 = off; off += pf ? mat : 0;
     L.z = off; off += al((size_t)n * 32 * ws);
     L.piv = off; off += al((size_t)n * 4);
     L.src = off; off += al((size_t)n * 4);
     L.perm = off; off += al((size_t)n * 4);
+    L.orig = off; off += pf ? al((size_t)n * 4) : 0;
+    L.ia = off; off += pf ? al((size_t)n * ws) : 0;
     L.acc = off; off += al(sizeof(DetAcc));
     L.stride = off;
     return L;
@@ -114,6 +121,12 @@ __device__ __forceinline__ int *wSrc(const FA &a, int w) {
 // (written by the block kernels, read by the outer update).
 __device__ __forceinline__ int *wPerm(const FA &a, int w) {
     return reinterpret_cast<int *>(a.work + (size_t)w * a.L.stride + a.L.perm);
+}
+__device__ __forceinline__ int *wOrig(const FA &a, int w) {
+    return reinterpret_cast<int *>(a.work + (size_t)w * a.L.stride + a.L.orig);
+}
+template <class Wd> __device__ __forceinline__ Wd *wIa(const FA &a, int w) {
+    return reinterpret_cast<Wd *>(a.work + (size_t)w * a.L.stride + a.L.ia);
 }
 __device__ __forceinline__ DetAcc *wAcc(const FA &a, int w) {
     return reinterpret_cast<DetAcc *>(a.work + (size_t)w * a.L.stride + a.L.acc);
@@ -281,6 +294,7 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_val[kPrThreads / 64];
     __shared__ int s_idx[kPrThreads / 64];
+    __shared__ Wd s_ia[kPrMaxPairs];                    // 1 / alpha of the panel's pairs
     const int w = blockIdx.x, n = a.n, tid = threadIdx.x;
     Wd *s_c = reinterpret_cast<Wd *>(smem);             // [P][n] pending c_t, logical index
     Wd *s_w = s_c + (size_t)P * n;                      // [P][n] pending w_t
@@ -298,6 +312,7 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         ph = get_ph<Wd>(d->pf_ph);
     } else if (n & 1) {                                 // odd order: pf = 0
         if (tid == 0) { d->pf_zero = 1; d->pf_logabs = -INFINITY; set_ph(d->pf_ph, zero<Wd>()); }
+        for (int e = tid; e < n; e += kPrThreads) wSrc(a, w)[e] = e;
         return;
     }
     for (int e = j0 + tid; e < n; e += kPrThreads) {
@@ -347,6 +362,7 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         la += log(absv(alpha));
         ph = ph * unit(alpha);
         const Wd inva = recip(alpha);
+        if (tid == 0) s_ia[t] = inva;
         // the new pending pair (c = row j / alpha, w = row q) and row j+2 up
         // to this pair's term, on entries > q
         const bool more = t + 1 < pairs;
@@ -379,14 +395,53 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
     // the map and the pending vectors as the last swap left them, on the
     // entries the trail kernel reads
     int *pm = wPerm(a, w);
+    int *src = wSrc(a, w);
     for (int e = j0 + tid; e < n; e += kPrThreads) pm[e] = s_pm[e];
-    if (zero_pf) return;
+    if (zero_pf) {                                      // no inverse: identity column order
+        for (int e = tid; e < n; e += kPrThreads) src[e] = e;
+        return;
+    }
     const int j1 = j0 + 2 * pairs;
     for (int t = 0; t < pairs; ++t) {
         for (int e = j1 + tid; e < n; e += kPrThreads) {
             Cg[(size_t)t * n + e] = s_c[(size_t)t * n + e];
             Wg[(size_t)t * n + e] = s_w[(size_t)t * n + e];
         }
+    }
+    // For the inverse (A = Pi U^T D U Pi^T, U = L^T): the original index of
+    // every position at the panel's end, orig_b(e) = orig_{b-1}(pm e), and
+    // the panel's rows of U (columns of L: -w_t / alpha_t and c_t below the
+    // pair), scattered by it, so that later panels' swaps need not touch them.
+    int *orig = wOrig(a, w);
+    Wd *LT = reinterpret_cast<Wd *>(a.work + (size_t)w * a.L.stride + a.L.x3);
+    int o[2];                                           // n <= 2 kPrThreads
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = j0 + tid + u * kPrThreads;
+        o[u] = e < n ? (j0 > 0 ? orig[s_pm[e]] : s_pm[e]) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = j0 + tid + u * kPrThreads;
+        if (e < n) orig[e] = o[u];
+    }
+    for (int t = 0; t < pairs; ++t) {
+        const Wd iat = s_ia[t];
+        Wd *l0 = LT + (size_t)(j0 + 2 * t) * n, *l1 = l0 + n;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = j0 + tid + u * kPrThreads;
+            if (e < n && e > j0 + 2 * t + 1) {
+                l0[o[u]] = -(s_w[(size_t)t * n + e] * iat);
+                l1[o[u]] = s_c[(size_t)t * n + e];
+            }
+        }
+    }
+    if (tid < pairs) wIa<Wd>(a, w)[j0 / 2 + tid] = s_ia[tid];
+    if (j1 == n) {                                      // last panel: src = orig^-1
+        __syncthreads();
+        for (int e = tid; e < n; e += kPrThreads) src[orig[e]] = e;
     }
 }
 
@@ -457,6 +512,195 @@ __global__ __launch_bounds__(kT) void pr_trail_kernel(FA a, int j1, int T, int c
                 const Wd v = make_<Wd>(re[jb][r], im[jb][r]);
                 Y[(size_t)q * n + sc] = v;
                 if (mirror) Y[(size_t)sc * n + q] = -v;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ PF inverse
+// From the Parlett-Reid factorisation itself: with the final order of the
+// positions Pi (orig) and B = Pi^T A Pi = U^T D U, U = L^T unit upper
+// triangular with identity 2x2 diagonal blocks and D the 2x2 blocks
+// [[0, alpha_t], [-alpha_t, 0]],
+//   A^-1 = Pi V D^-1 V^T Pi^T,   V = U^-1,
+// so B^-1 = sum_t (V[:, 2t+1] V[:, 2t]^T - V[:, 2t] V[:, 2t+1]^T) / alpha_t
+// (D^-1 has the blocks [[0, -1/alpha], [1/alpha, 0]]).  Four steps, all on
+// 64 x 64 tiles:
+//   U assembly : row c of U from the stored columns of L, gathered through
+//                Pi (they were scattered by original index);
+//   V diagonal : V_II = U_II^-1 by back substitution in LDS;
+//   V rows     : block rows I = nt-2 .. 0, all J > I at once:
+//                V_IJ = -V_II sum_{K=I+1..J} U_IK V_KJ (two MFMA products);
+//   product    : upper tiles of B^-1 = P Q^T with P[i][2t] = V[i][2t+1] /
+//                alpha_t, P[i][2t+1] = -V[i][2t] / alpha_t, Q = V, over the
+//                columns m >= the tile's column start (V is upper triangular),
+//                written to row Pi(i) of X, and negated at the mirror.
+// The final kernel then reads X with the column source Pi^-1 and stores
+// (X' - X'^T) / 2.  About n^3 / 3 complex multiply-adds against n^3 for a
+// Gauss-Jordan inverse, in MFMA products over many work-groups.
+template <class Wd> __device__ __forceinline__ Wd *pr_buf3(const FA &a, int w) {
+    return reinterpret_cast<Wd *>(a.work + (size_t)w * a.L.stride + a.L.x3);
+}
+
+// U (into X): four rows per work-group, one per wave.
+template <class Wd>
+__global__ __launch_bounds__(kT) void pr_uasm_kernel(FA a, int bpw) {
+    const int w = blockIdx.x / bpw;
+    const int c = (blockIdx.x - w * bpw) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63, n = a.n;
+    if (c >= n || wAcc(a, w)->pf_zero) return;
+    const Wd *lt = pr_buf3<Wd>(a, w) + (size_t)c * n;
+    const int *pi = wOrig(a, w);
+    Wd *u = wX<Wd>(a, w) + (size_t)c * n;
+    const int lo = c | 1;
+    for (int f = lane; f < n; f += 64) u[f] = f > lo ? lt[pi[f]] : (f == c ? one<Wd>() : zero<Wd>());
+}
+
+// V_II = U_II^-1 (into x2), tile I of walker w.  Past n the tile is taken as
+// the identity.  64 threads solve one column each; the tile is written whole
+// (zeros below the diagonal).
+template <class Wd> constexpr int vd_stride() { return 65; }
+template <class Wd> size_t vdiag_lds() { return sizeof(Wd) * (size_t)2 * 64 * vd_stride<Wd>(); }
+template <class Wd>
+__global__ __launch_bounds__(kT) void pr_vdiag_kernel(FA a, int nt) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int S = vd_stride<Wd>();
+    Wd *sU = reinterpret_cast<Wd *>(smem), *sV = sU + 64 * S;
+    const int w = blockIdx.x / nt, I = blockIdx.x - w * nt, n = a.n, r0 = I * 64;
+    if (wAcc(a, w)->pf_zero) return;
+    const Wd *U = wX<Wd>(a, w);
+    Wd *V = pr_buf<Wd>(a, w, 1);
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += kT) {
+        const int i = idx >> 6, k = idx & 63, gi = r0 + i, gk = r0 + k;
+        sU[i * S + k] = (gi < n && gk < n) ? U[(size_t)gi * n + gk] : (i == k ? one<Wd>() : zero<Wd>());
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int j = threadIdx.x;
+        for (int i = 63; i >= 0; --i) {
+            Wd v = i == j ? one<Wd>() : zero<Wd>();
+            for (int k = i + 1; k <= j; ++k) v = v - sU[i * S + k] * sV[k * S + j];
+            sV[i * S + j] = v;
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += kT) {
+        const int i = idx >> 6, k = idx & 63, gi = r0 + i, gk = r0 + k;
+        if (gi < n && gk < n) V[(size_t)gi * n + gk] = sV[i * S + k];
+    }
+}
+
+// Block row I of V, tile J = I + 1 + (block index mod (nt - 1 - I)).  The
+// first product sum_K U_IK V_KJ is staged in LDS as the B operand of the
+// second, V_II times it.
+template <class Wd> size_t vrow_lds() { return sizeof(Wd) * (size_t)64 * 65; }
+template <class Wd>
+__global__ __launch_bounds__(kT) void pr_vrow_kernel(FA a, int I, int nt) {
+    using R = typename Real<Wd>::type;
+    using A4 = typename Acc<R>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int S = 65;
+    Wd *sT = reinterpret_cast<Wd *>(smem);
+    const int per = nt - 1 - I;
+    const int w = blockIdx.x / per, J = I + 1 + (blockIdx.x - w * per), n = a.n;
+    if (wAcc(a, w)->pf_zero) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kq = lane >> 4, lc = lane & 15;
+    const Wd *U = wX<Wd>(a, w);
+    Wd *V = pr_buf<Wd>(a, w, 1);
+    const int r0 = I * 64, s0 = J * 64, rbase = r0 + wv * 16;
+    const int ra = min(rbase + lc, n - 1);
+    int col[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) col[jb] = min(s0 + jb * 16 + lc, n - 1);
+    A4 re[4], im[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) { re[jb] = A4{}; im[jb] = A4{}; }
+    const int kend = min((J + 1) * 64, n);
+    for (int k0 = r0 + 64; k0 < kend; k0 += 4) {
+        const int k = k0 + kq;
+        const bool kin = k < kend;
+        const int kc = min(k, n - 1);
+        const Wd av = kin ? U[(size_t)ra * n + kc] : zero<Wd>();
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) {
+            const Wd bv = kin ? V[(size_t)kc * n + col[jb]] : zero<Wd>();
+            mac<Wd>(av, bv, re[jb], im[jb]);
+        }
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            sT[(wv * 16 + acc_row<R>(lane, r)) * S + jb * 16 + lc] = make_<Wd>(re[jb][r], im[jb][r]);
+    __syncthreads();
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) { re[jb] = A4{}; im[jb] = A4{}; }
+    for (int k0 = 0; k0 < 64; k0 += 4) {
+        const int k = k0 + kq;
+        const Wd av = r0 + k < n ? V[(size_t)ra * n + r0 + k] : zero<Wd>();
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) mac<Wd>(av, sT[k * S + jb * 16 + lc], re[jb], im[jb]);
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int sc = s0 + jb * 16 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = rbase + acc_row<R>(lane, r);
+            if (q < n && sc < n) V[(size_t)q * n + sc] = -make_<Wd>(re[jb][r], im[jb][r]);
+        }
+    }
+}
+
+// Upper tile (I, J) of B^-1 into X at the rows Pi(i), mirrored; a walker
+// with pf = 0 gets zeros in identity order.
+template <class Wd>
+__global__ __launch_bounds__(kT) void pr_inv_kernel(FA a, int nt) {
+    using R = typename Real<Wd>::type;
+    using A4 = typename Acc<R>::type;
+    const int per = nt * (nt + 1) / 2;
+    const int w = blockIdx.x / per;
+    int tile = blockIdx.x - w * per, ti = 0;
+    while (tile >= nt - ti) { tile -= nt - ti; ++ti; }
+    const int tj = ti + tile, n = a.n;
+    const bool zero_pf = wAcc(a, w)->pf_zero != 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kq = lane >> 4, lc = lane & 15;
+    const Wd *V = pr_buf<Wd>(a, w, 1);
+    const Wd *ia = wIa<Wd>(a, w);
+    const int *pi = wOrig(a, w);
+    Wd *X = wX<Wd>(a, w);
+    const int r0 = ti * 64, s0 = tj * 64, rbase = r0 + wv * 16;
+    A4 re[4], im[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) { re[jb] = A4{}; im[jb] = A4{}; }
+    if (!zero_pf) {
+        const int ra = min(rbase + lc, n - 1);
+        int col[4];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) col[jb] = min(s0 + jb * 16 + lc, n - 1);
+        for (int m0 = s0; m0 < n; m0 += 4) {
+            const int m = m0 + kq;
+            const bool in = m < n;
+            const int mc = min(m, n - 1);
+            Wd av = in ? V[(size_t)ra * n + (mc ^ 1)] * ia[mc >> 1] : zero<Wd>();
+            if (m & 1) av = -av;
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const Wd bv = in ? V[(size_t)col[jb] * n + mc] : zero<Wd>();
+                mac<Wd>(av, bv, re[jb], im[jb]);
+            }
+        }
+    }
+    const bool mirror = ti != tj;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int sc = s0 + jb * 16 + lc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = rbase + acc_row<R>(lane, r);
+            if (q < n && sc < n) {
+                const Wd v = make_<Wd>(re[jb][r], im[jb][r]);
+                X[(size_t)(zero_pf ? q : pi[q]) * n + sc] = v;
+                if (mirror) X[(size_t)(zero_pf ? sc : pi[sc]) * n + q] = -v;
             }
         }
     }
@@ -1294,6 +1538,26 @@ hipError_t launch_pr(const FA &fa, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <class Wd>
+hipError_t launch_pf_inverse(const FA &fa, hipStream_t s) {
+    const int n = fa.n, W = fa.W, nt = (n + 63) / 64;
+    hipError_t e;
+    const size_t ld = vdiag_lds<Wd>(), lr = vrow_lds<Wd>();
+    if (ld > 65536 && (e = hipFuncSetAttribute(reinterpret_cast<const void *>(&pr_vdiag_kernel<Wd>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)ld)) != hipSuccess)
+        return e;
+    if (lr > 65536 && (e = hipFuncSetAttribute(reinterpret_cast<const void *>(&pr_vrow_kernel<Wd>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr)) != hipSuccess)
+        return e;
+    const int bpw = (n + 3) / 4;
+    hipLaunchKernelGGL(pr_uasm_kernel<Wd>, dim3((unsigned)(W * bpw)), dim3(kT), 0, s, fa, bpw);
+    hipLaunchKernelGGL(pr_vdiag_kernel<Wd>, dim3((unsigned)(W * nt)), dim3(kT), ld, s, fa, nt);
+    for (int I = nt - 2; I >= 0; --I)
+        hipLaunchKernelGGL(pr_vrow_kernel<Wd>, dim3((unsigned)(W * (nt - 1 - I))), dim3(kT), lr, s, fa, I, nt);
+    hipLaunchKernelGGL(pr_inv_kernel<Wd>, dim3((unsigned)(W * nt * (nt + 1) / 2)), dim3(kT), 0, s, fa, nt);
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     using Wd = typename Wide<T>::type;
@@ -1311,6 +1575,15 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
     if (a.kind == LRX_PF) {
         hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
         if ((e = launch_pr<Wd>(a, s)) != hipSuccess) return e;
+        if ((e = launch_pf_inverse<Wd>(a, s)) != hipSuccess) return e;
+        const int pairs = tiles * (tiles + 1) / 2;
+        hipLaunchKernelGGL((final_pf_kernel<T, Wd>), dim3((unsigned)(W * pairs)), dim3(kT), 0, s, a, tiles);
+        if (a.packed && (n & 63)) {
+            const int nt = (n + 63) / 64;
+            hipLaunchKernelGGL(pk_zero_tail_kernel<T>, dim3((unsigned)(W * nt)), dim3(kT), 0, s, a, nt);
+        }
+        hipLaunchKernelGGL(finish_kernel<Wd>, dim3((W + 255) / 256), dim3(256), 0, s, a);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1330,19 +1603,10 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(src_perm_kernel, dim3(W), dim3(kT), sizeof(int) * 2 * (size_t)n, s, a);
-    if (a.kind == LRX_DET) {
-        const int rpb = 8;
-        const int bpw = (n + rpb - 1) / rpb;
-        hipLaunchKernelGGL((final_det_kernel<T, Wd>), dim3((unsigned)(W * bpw)), dim3(kT), sizeof(int) * (size_t)n, s,
-                           a, rpb, bpw);
-    } else {
-        const int pairs = tiles * (tiles + 1) / 2;
-        hipLaunchKernelGGL((final_pf_kernel<T, Wd>), dim3((unsigned)(W * pairs)), dim3(kT), 0, s, a, tiles);
-        if (a.packed && (n & 63)) {
-            const int nt = (n + 63) / 64;
-            hipLaunchKernelGGL(pk_zero_tail_kernel<T>, dim3((unsigned)(W * nt)), dim3(kT), 0, s, a, nt);
-        }
-    }
+    const int rpb = 8;
+    const int bpw = (n + rpb - 1) / rpb;
+    hipLaunchKernelGGL((final_det_kernel<T, Wd>), dim3((unsigned)(W * bpw)), dim3(kT), sizeof(int) * (size_t)n, s,
+                       a, rpb, bpw);
     hipLaunchKernelGGL(finish_kernel<Wd>, dim3((W + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
