@@ -556,7 +556,8 @@ __global__ __launch_bounds__(kT) void pr_uasm_kernel(FA a, int bpw) {
 }
 
 // V_II = U_II^-1 (into x2), tile I of walker w.  Past n the tile is taken as
-// the identity.  64 threads solve one column each; the tile is written whole
+// the identity.  A lane quad solves one column by back substitution, each
+// lane taking every fourth term of a dot product; the tile is written whole
 // (zeros below the diagonal).
 template <class Wd> constexpr int vd_stride() { return 65; }
 template <class Wd> size_t vdiag_lds() { return sizeof(Wd) * (size_t)2 * 64 * vd_stride<Wd>(); }
@@ -574,12 +575,16 @@ __global__ __launch_bounds__(kT) void pr_vdiag_kernel(FA a, int nt) {
         sU[i * S + k] = (gi < n && gk < n) ? U[(size_t)gi * n + gk] : (i == k ? one<Wd>() : zero<Wd>());
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-        const int j = threadIdx.x;
+    {
+        // column j = 4 waves x 16 quads; the quad's lane 0 stores each entry,
+        // which its wave reads back in the next step (LDS order within a wave)
+        const int j = threadIdx.x >> 2, part = threadIdx.x & 3;
         for (int i = 63; i >= 0; --i) {
-            Wd v = i == j ? one<Wd>() : zero<Wd>();
-            for (int k = i + 1; k <= j; ++k) v = v - sU[i * S + k] * sV[k * S + j];
-            sV[i * S + j] = v;
+            Wd acc = zero<Wd>();
+            for (int k = i + 1 + part; k <= j; k += 4) acc = acc + sU[i * S + k] * sV[k * S + j];
+            acc = acc + shfl_xor_v(acc, 1);
+            acc = acc + shfl_xor_v(acc, 2);
+            if (part == 0) sV[i * S + j] = i == j ? one<Wd>() : (i > j ? zero<Wd>() : -acc);
         }
     }
     __syncthreads();
@@ -614,17 +619,27 @@ __global__ __launch_bounds__(kT) void pr_vrow_kernel(FA a, int I, int nt) {
     A4 re[4], im[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) { re[jb] = A4{}; im[jb] = A4{}; }
+    // four 4-deep steps per batch, every load of the batch issued before its
+    // MFMAs (unconditional loads from clamped addresses)
     const int kend = min((J + 1) * 64, n);
-    for (int k0 = r0 + 64; k0 < kend; k0 += 4) {
-        const int k = k0 + kq;
-        const bool kin = k < kend;
-        const int kc = min(k, n - 1);
-        const Wd av = kin ? U[(size_t)ra * n + kc] : zero<Wd>();
+    for (int k0 = r0 + 64; k0 < kend; k0 += 16) {
+        Wd av[4], bv[4][4];
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const Wd bv = kin ? V[(size_t)kc * n + col[jb]] : zero<Wd>();
-            mac<Wd>(av, bv, re[jb], im[jb]);
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 4 * u + kq;
+            const int kc = min(k, n - 1);
+            const Wd x = U[(size_t)ra * n + kc];
+            av[u] = k < kend ? x : zero<Wd>();
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const Wd y = V[(size_t)kc * n + col[jb]];
+                bv[u][jb] = k < kend ? y : zero<Wd>();
+            }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) mac<Wd>(av[u], bv[u][jb], re[jb], im[jb]);
     }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
@@ -677,17 +692,21 @@ __global__ __launch_bounds__(kT) void pr_inv_kernel(FA a, int nt) {
         int col[4];
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) col[jb] = min(s0 + jb * 16 + lc, n - 1);
-        for (int m0 = s0; m0 < n; m0 += 4) {
-            const int m = m0 + kq;
-            const bool in = m < n;
-            const int mc = min(m, n - 1);
-            Wd av = in ? V[(size_t)ra * n + (mc ^ 1)] * ia[mc >> 1] : zero<Wd>();
-            if (m & 1) av = -av;
+        for (int m0 = s0; m0 < n; m0 += 16) {           // four 4-deep steps per batch
+            Wd av[4], bv[4][4];
 #pragma unroll
-            for (int jb = 0; jb < 4; ++jb) {
-                const Wd bv = in ? V[(size_t)col[jb] * n + mc] : zero<Wd>();
-                mac<Wd>(av, bv, re[jb], im[jb]);
+            for (int u = 0; u < 4; ++u) {
+                const int m = m0 + 4 * u + kq;
+                const int mc = min(m, n - 1);
+                const Wd x = V[(size_t)ra * n + (mc ^ 1)] * ia[mc >> 1];
+                av[u] = m < n ? (m & 1 ? -x : x) : zero<Wd>();
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) bv[u][jb] = V[(size_t)col[jb] * n + mc];
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) mac<Wd>(av[u], bv[u][jb], re[jb], im[jb]);
         }
     }
     const bool mirror = ti != tj;
