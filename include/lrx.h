@@ -467,8 +467,12 @@ int lrx_det_lowrank_bwd(const lrx_state *st, int32_t r, const int32_t *occ, int3
 /*
  * Build A_0[w][i][j] = f[occ[w][i]][occ[w][j]] (or the dense skew batch f
  * [W][n][n] when occ is NULL) and factorise from scratch in FP64/complex128:
- * Parlett-Reid elimination for log|pf| and phase (Appendix A), Gauss-Jordan
- * inversion, then M = (X - X^T)/2 so that M is exactly skew.  n must be even.
+ * Parlett-Reid elimination for log|pf| and phase (Appendix A), the inverse
+ * from the same factorisation (A = Pi U^T D U Pi^T with D of 2x2 blocks, so
+ * A^-1 = Pi U^-1 D^-1 U^-T Pi^T), then M = (X - X^T)/2 so that M is exactly
+ * skew.  A zero pivot (pf = 0) flags the walker SINGULAR_A and leaves M = 0.
+ * n must be even.  The workspace grows by two n x n matrices per walker over
+ * the determinant's (lrx_state_sizes).
  *   f: [sites][sites] skew pairing matrix (FP64 or complex128).
  */
 int lrx_pf_init_inverse(lrx_state *st, const void *f, int32_t sites,

@@ -53,6 +53,42 @@ def test_pf_init_matches_oracle(dt, n):
     assert (wk.st.flags.cpu().numpy() == 0).all()
 
 
+@pytest.mark.parametrize("dt", ["c128", "f64"])
+def test_pf_zero_pivot_walker_is_flagged(dt):
+    """A site with no pairing amplitude (zero row and column of F) makes the pairing matrix of
+    the walker that holds it singular: its Parlett-Reid row reaches a zero pivot (in the
+    second panel here: the site sits at position 50 of n = 64, and the zero row is never
+    picked as a pivot partner), pf = 0.  That walker is flagged SINGULAR_A with log|pf| = -inf
+    and a zero inverse; the other walkers, which do not hold the site, match the oracle."""
+    say(f"pf zero pivot dt={dt}")
+    cplx = dt.startswith("c")
+    g, f, occ, emp = pf_inputs(910, 128, 64, 3, cplx)
+    site = int(occ[1, 50])
+    for w in (0, 2):                       # keep the site out of the other walkers
+        if site in occ[w]:
+            i = int(np.where(occ[w] == site)[0][0])
+            occ[w, i] = int(emp[w, 0])
+            emp[w, 0] = site
+    f = f.copy()
+    f[site, :] = 0.0
+    f[:, site] = 0.0
+    wk = Walkers(lrx.LRX_PF, DT[dt], f, occ, emp)
+    torch.cuda.synchronize()
+    flags = wk.st.flags.cpu().numpy()
+    la = wk.st.logabs.cpu().numpy()
+    m = wk.st.inv.cpu().numpy()
+    assert flags[1] & lrx.LRX_FLAG_SINGULAR_A and np.isneginf(la[1])
+    assert not np.any(m[1]), "a singular walker's inverse is left zero"
+    ok = np.array([0, 2])
+    assert (flags[ok] == 0).all()
+    a = orc.pairing_matrices(f, occ[ok])
+    la0, ph0 = orc.slogpf(a)
+    np.testing.assert_allclose(la[ok], la0, rtol=0, atol=1e-9 * 64)
+    np.testing.assert_allclose(wk.st.phase.cpu().numpy()[ok], ph0, rtol=0, atol=1e-9 * 64)
+    em = rel_err(m[ok], orc.skew_inverse(a), axis=(1, 2))
+    assert np.all(em <= np.maximum(1e-10, 64 * np.linalg.cond(a) * 1e-16)), em
+
+
 @pytest.mark.parametrize("dt,n,K,W,steps", [
     ("c128", 64, 0, 6, 25),
     ("c128", 64, 5, 6, 23),
