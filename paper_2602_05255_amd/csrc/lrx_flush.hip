@@ -90,31 +90,72 @@ __global__ __launch_bounds__(256) void pf_flush_kernel(StepArgs a, int tiles_per
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int q = rbase + acc_row<R>(lane, r);
-            T v = (q < n && j < n && q < j) ? M[(size_t)q * n + j] : zero<T>();
+            const T x = M[(size_t)min(q, n - 1) * n + min(j, n - 1)];
+            const T v = (q < n && j < n && q < j) ? x : zero<T>();
             re[jb][r] = re_(v);
             im[jb][r] = im_(v);
         }
     }
-    for (int te0 = 0; te0 < TE; te0 += 4) {
-        const int te = te0 + kq;
-        const bool tin = te < TE;
-        // Atilde[q][te] = sum_s a_t[q][s] R_t^-1[s][te mod KA]
-        T at = zero<T>();
-        if (tin && qa < n) {
-            const int t = te / KA, sp = te - t * KA;
-            for (int s = 0; s < KA; ++s)
-                at = fmac(fa[(size_t)(t * KA + s) * n + qa], rinv[(size_t)t * KA * KA + s * KA + sp], at);
-        }
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const int j = j0 + jb * 16 + (lane & 15);
-            T av = (tin && j < n) ? fa[(size_t)te * n + j] : zero<T>();
-            mac<T>(at, av, re[jb], im[jb]);
-        }
-    }
+    // Four 4-deep steps per batch, every load of the batch issued before its
+    // MFMAs; loads come from clamped addresses and are masked by selects.
+    const int qc = min(qa, n - 1);
+    int jc[4];
+    bool jin[4];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
         const int j = j0 + jb * 16 + (lane & 15);
+        jin[jb] = j < n;
+        jc[jb] = min(j, n - 1);
+    }
+    for (int te0 = 0; te0 < TE; te0 += 16) {
+        T at[4], bv[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int te = te0 + 4 * u + kq;
+            const bool tin = te < TE;
+            const int tc = min(te, TE - 1);
+            const int t = tc / KA, sp = tc - t * KA;
+            // Atilde[q][te] = sum_s a_t[q][s] R_t^-1[s][te mod KA]
+            T x = zero<T>();
+            for (int s = 0; s < KA; ++s)
+                x = fmac(fa[(size_t)(t * KA + s) * n + qc], rinv[(size_t)t * KA * KA + s * KA + sp], x);
+            at[u] = (tin && qa < n) ? x : zero<T>();
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                const T y = fa[(size_t)tc * n + jc[jb]];
+                bv[u][jb] = (tin && jin[jb]) ? y : zero<T>();
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) mac<T>(at[u], bv[u][jb], re[jb], im[jb]);
+    }
+    // Upper entries in place; the mirrored ones (-v at (j, q)) as one store of
+    // the lane's four consecutive rows q when the acc layout gives them
+    // (single precision: rows 4 (lane / 16) + r) and the tile is off-diagonal.
+    const bool offd = ti != tj;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int j = j0 + jb * 16 + (lane & 15);
+        if constexpr (sizeof(R) == 4) {
+            const int q0 = rbase + acc_row<R>(lane, 0);
+            if (offd && j < n && q0 + 3 < n) {
+                struct alignas(4 * sizeof(T)) Q4 { T v[4]; } m4;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    M[(size_t)(q0 + r) * n + j] = make_<T>(re[jb][r], im[jb][r]);
+                    m4.v[r] = make_<T>(-re[jb][r], -im[jb][r]);
+                }
+                if (((size_t)j * n + q0) % 4 == 0) {
+                    *reinterpret_cast<Q4 *>(M + (size_t)j * n + q0) = m4;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) M[(size_t)j * n + q0 + r] = m4.v[r];
+                }
+                continue;
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int q = rbase + acc_row<R>(lane, r);
