@@ -59,11 +59,14 @@ __global__ __launch_bounds__(256, 2) void det_flush_strip_kernel(StepArgs a, int
 }
 
 // ------------------------------------------------------------------ PF
-template <class T>
+// KAC: the slot width 2 k_max when known at compile time (2: single hops, the
+// only width a delayed Pfaffian state has), 0 for a runtime width.  Offsets
+// are 32-bit from the walker's base pointers (n^2 and K 2k_max n fit).
+template <class T, int KAC>
 __global__ __launch_bounds__(256) void pf_flush_kernel(StepArgs a, int tiles_per_dim) {
     using R = typename Real<T>::type;
     using A4 = typename Acc<R>::type;
-    const int n = a.n, KM = a.KM, KA = 2 * KM, TE = a.tau * KA;
+    const int n = a.n, KA = KAC > 0 ? KAC : 2 * a.KM, TE = a.tau * KA;
     const int pairs = tiles_per_dim * (tiles_per_dim + 1) / 2;
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int w = lb / pairs;
@@ -77,6 +80,7 @@ __global__ __launch_bounds__(256) void pf_flush_kernel(StepArgs a, int tiles_per
     const int qa = ti * 64 + wv * 16 + (lane & 15);
     const int kq = lane >> 4;
     const int j0 = tj * 64;
+    const uint32_t un = (uint32_t)n;
 
     T *M = static_cast<T *>(a.inv) + (size_t)w * n * n;
     const T *fa = static_cast<const T *>(a.fa) + (size_t)w * (size_t)a.K * KA * n;
@@ -84,13 +88,21 @@ __global__ __launch_bounds__(256) void pf_flush_kernel(StepArgs a, int tiles_per
 
     A4 re[4], im[4];
     const int rbase = ti * 64 + wv * 16;
+    uint32_t jc[4];
+    bool jin[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        const int j = j0 + jb * 16 + (lane & 15);
+        jin[jb] = j < n;
+        jc[jb] = (uint32_t)min(j, n - 1);
+    }
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
         const int j = j0 + jb * 16 + (lane & 15);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int q = rbase + acc_row<R>(lane, r);
-            const T x = M[(size_t)min(q, n - 1) * n + min(j, n - 1)];
+            const T x = M[(uint32_t)min(q, n - 1) * un + jc[jb]];
             const T v = (q < n && j < n && q < j) ? x : zero<T>();
             re[jb][r] = re_(v);
             im[jb][r] = im_(v);
@@ -98,15 +110,8 @@ __global__ __launch_bounds__(256) void pf_flush_kernel(StepArgs a, int tiles_per
     }
     // Four 4-deep steps per batch, every load of the batch issued before its
     // MFMAs; loads come from clamped addresses and are masked by selects.
-    const int qc = min(qa, n - 1);
-    int jc[4];
-    bool jin[4];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-        const int j = j0 + jb * 16 + (lane & 15);
-        jin[jb] = j < n;
-        jc[jb] = min(j, n - 1);
-    }
+    const uint32_t qc = (uint32_t)min(qa, n - 1);
+    const bool qin = qa < n;
     for (int te0 = 0; te0 < TE; te0 += 16) {
         T at[4], bv[4][4];
 #pragma unroll
@@ -117,12 +122,16 @@ __global__ __launch_bounds__(256) void pf_flush_kernel(StepArgs a, int tiles_per
             const int t = tc / KA, sp = tc - t * KA;
             // Atilde[q][te] = sum_s a_t[q][s] R_t^-1[s][te mod KA]
             T x = zero<T>();
-            for (int s = 0; s < KA; ++s)
-                x = fmac(fa[(size_t)(t * KA + s) * n + qc], rinv[(size_t)t * KA * KA + s * KA + sp], x);
-            at[u] = (tin && qa < n) ? x : zero<T>();
+#pragma unroll
+            for (int s = 0; s < (KAC > 0 ? KAC : 1); ++s)
+                x = fmac(fa[(uint32_t)(t * KA + s) * un + qc], rinv[(uint32_t)(t * KA * KA + s * KA + sp)], x);
+            if constexpr (KAC == 0)
+                for (int s = 1; s < KA; ++s)
+                    x = fmac(fa[(uint32_t)(t * KA + s) * un + qc], rinv[(uint32_t)(t * KA * KA + s * KA + sp)], x);
+            at[u] = (tin && qin) ? x : zero<T>();
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) {
-                const T y = fa[(size_t)tc * n + jc[jb]];
+                const T y = fa[(uint32_t)tc * un + jc[jb]];
                 bv[u][jb] = (tin && jin[jb]) ? y : zero<T>();
             }
         }
@@ -144,14 +153,15 @@ __global__ __launch_bounds__(256) void pf_flush_kernel(StepArgs a, int tiles_per
                 struct alignas(4 * sizeof(T)) Q4 { T v[4]; } m4;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    M[(size_t)(q0 + r) * n + j] = make_<T>(re[jb][r], im[jb][r]);
+                    M[(uint32_t)(q0 + r) * un + (uint32_t)j] = make_<T>(re[jb][r], im[jb][r]);
                     m4.v[r] = make_<T>(-re[jb][r], -im[jb][r]);
                 }
-                if (((size_t)j * n + q0) % 4 == 0) {
-                    *reinterpret_cast<Q4 *>(M + (size_t)j * n + q0) = m4;
+                const uint32_t mo = (uint32_t)j * un + (uint32_t)q0;
+                if (mo % 4 == 0) {
+                    *reinterpret_cast<Q4 *>(M + mo) = m4;
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) M[(size_t)j * n + q0 + r] = m4.v[r];
+                    for (int r = 0; r < 4; ++r) M[mo + r] = m4.v[r];
                 }
                 continue;
             }
@@ -162,10 +172,10 @@ __global__ __launch_bounds__(256) void pf_flush_kernel(StepArgs a, int tiles_per
             if (q >= n || j >= n) continue;
             if (q < j) {
                 T v = make_<T>(re[jb][r], im[jb][r]);
-                M[(size_t)q * n + j] = v;
-                M[(size_t)j * n + q] = make_<T>(-re[jb][r], -im[jb][r]);
+                M[(uint32_t)q * un + (uint32_t)j] = v;
+                M[(uint32_t)j * un + (uint32_t)q] = make_<T>(-re[jb][r], -im[jb][r]);
             } else if (q == j) {
-                M[(size_t)q * n + j] = zero<T>();
+                M[(uint32_t)q * un + (uint32_t)j] = zero<T>();
             }
         }
     }
@@ -184,7 +194,10 @@ template <class T> hipError_t det_flush_t(const StepArgs &a, hipStream_t s) {
 template <class T> hipError_t pf_flush_t(const StepArgs &a, hipStream_t s) {
     const int tpd = (a.n + 63) / 64;
     const int pairs = tpd * (tpd + 1) / 2;
-    hipLaunchKernelGGL(pf_flush_kernel<T>, dim3((unsigned)(a.W * pairs)), dim3(256), 0, s, a, tpd);
+    if (a.KM == 1)
+        hipLaunchKernelGGL((pf_flush_kernel<T, 2>), dim3((unsigned)(a.W * pairs)), dim3(256), 0, s, a, tpd);
+    else
+        hipLaunchKernelGGL((pf_flush_kernel<T, 0>), dim3((unsigned)(a.W * pairs)), dim3(256), 0, s, a, tpd);
     return hipGetLastError();
 }
 
