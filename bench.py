@@ -36,6 +36,16 @@ FP64_PEAK_TFS = 78.6
 FP32_PEAK_TFS = 157.3
 
 
+def source_code_bytes(text: bytes) -> bytes:
+    """The code of a C/C++/HIP source for the counter-profile hash: comments removed and
+    blank lines dropped, so that documentation edits do not void the recorded counters
+    (any change to the code itself does)."""
+    import re
+    code = re.sub(rb"/\*.*?\*/", b"", text, flags=re.S)
+    code = re.sub(rb"//[^\n]*", b"", code)
+    return b"\n".join(line.rstrip() for line in code.split(b"\n") if line.strip())
+
+
 def counter_traffic(profile, sources, walkers_per_launch, key=None):
     """HBM bytes measured by the FETCH_SIZE / WRITE_SIZE counter passes recorded in
     profiles/<profile>, or None when the kernel sources changed since.  With
@@ -49,7 +59,7 @@ def counter_traffic(profile, sources, walkers_per_launch, key=None):
     h = hashlib.sha256()
     for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+            h.update(source_code_bytes(fh.read()))
     keys = {}
     for line in open(path):
         part = line.strip().split(":", 1)
