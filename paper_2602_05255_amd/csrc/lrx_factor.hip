@@ -1244,20 +1244,26 @@ __global__ __launch_bounds__(kT) void gj_outer_kernel(FA a, int j0, int nbo, int
     struct Buf { Wd x[NTL][4]; Wd z[NK]; };
     // block index t = 0 .. nblk-1: the other blocks in order, the P block last
     auto blk_of = [&](int t) { return t < nblk - 1 ? (t < pblk ? t : t + 1) : pblk; };
+    // The four row sources of the block are read from LDS once, and the row
+    // loads are unconditional (the P block reads valid rows and selects zero),
+    // so all of a block's loads issue back to back.
     auto issue = [&](int t, Buf &b) {
         const int blk = blk_of(t);
         const int rbase = blk * 64 + wv * 16;
         const bool pb = blk == pblk;
+        uint32_t ro[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ro[r] = (uint32_t)perm[min(rbase + acc_row<R>(lane, r), n - 1)] * (uint32_t)n;
 #pragma unroll
         for (int jt = 0; jt < NTL; ++jt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = min(rbase + acc_row<R>(lane, r), n - 1);
-                b.x[jt][r] = pb ? zero<Wd>() : X[(size_t)perm[i] * n + col[jt]];
+                const Wd v = X[ro[r] + (uint32_t)col[jt]];
+                b.x[jt][r] = pb ? zero<Wd>() : v;
             }
-        const int zrow = min(rbase + lc, n - 1);
+        const uint32_t zo = (uint32_t)min(rbase + lc, n - 1) * (uint32_t)n;
 #pragma unroll
-        for (int kk = 0; kk < NK; ++kk) b.z[kk] = X[(size_t)zrow * n + min(j0 + kk * 4 + kq, n - 1)];
+        for (int kk = 0; kk < NK; ++kk) b.z[kk] = X[zo + (uint32_t)min(j0 + kk * 4 + kq, n - 1)];
     };
     auto consume = [&](int t, Buf &b) {
         const int blk = blk_of(t);
