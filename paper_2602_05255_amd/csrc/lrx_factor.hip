@@ -279,6 +279,18 @@ template <class Wd> __device__ __forceinline__ Wd *pr_buf(const FA &a, int w, in
     return reinterpret_cast<Wd *>(a.work + (size_t)w * a.L.stride + (b ? a.L.x2 : a.L.x));
 }
 
+// Entry (r, c) of a trailing matrix whose update started at index `base`: the
+// trail kernel stores the 64 x 64 tiles on and above the diagonal of the
+// tiling that starts at base (diagonal tiles whole), so an entry below them is
+// the negated transposed one.  The loaded A holds both triangles, which base 0
+// reads the same way.
+template <class Wd>
+__device__ __forceinline__ Wd pr_stored(const Wd *X, int n, int base, int r, int c) {
+    const bool up = ((r - base) >> 6) <= ((c - base) >> 6);
+    const Wd v = X[up ? (size_t)r * n + c : (size_t)c * n + r];
+    return up ? v : -v;
+}
+
 template <class Wd> size_t pr_lds(int n, int P) {
     return sizeof(Wd) * ((size_t)2 * P * n + n) + sizeof(int) * (size_t)n;
 }
@@ -367,13 +379,12 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         // to this pair's term, on entries > q
         const bool more = t + 1 < pairs;
         const int j2 = more ? j + 2 : q;
-        const Wd *x1 = X + (size_t)s_pm[q] * n;
-        const Wd *x2 = X + (size_t)s_pm[j2] * n;
+        const int p1 = s_pm[q], p2 = s_pm[j2];
         Wd *ct = s_c + (size_t)t * n, *wt = s_w + (size_t)t * n;
         for (int e = q + 1 + tid; e < n; e += kPrThreads) {
             const int pe = s_pm[e];
-            Wd wv = x1[pe];
-            Wd rv = more ? x2[pe] : zero<Wd>();
+            Wd wv = pr_stored<Wd>(X, n, j0, p1, pe);
+            Wd rv = more ? pr_stored<Wd>(X, n, j0, p2, pe) : zero<Wd>();
             for (int u = 0; u < t; ++u) {
                 const Wd *cu = s_c + (size_t)u * n, *wu = s_w + (size_t)u * n;
                 const Wd ce = cu[e], we = wu[e];
@@ -448,10 +459,10 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
 // The trailing matrix of the panel that ended at j1 (T pairs): 64 x 64 tile
 // (I, J), I <= J, of X' = X[pm][pm] + P Q^T with P = [w_t, -c_t], Q = [c_t,
 // w_t]; wave wv owns 16 rows of the tile as four 16x16 MFMA blocks.  X' is
-// skew like X, so only the upper tiles are computed: an off-diagonal tile is
-// stored twice, as itself and negated at the mirrored position; a diagonal
-// tile is stored as computed.  Rows and columns beyond n are clamped on load
-// and dropped on store.
+// skew like X, so only the upper tiles are computed and stored (a diagonal
+// tile whole); readers take an entry below them as the negated transposed one
+// (pr_stored), the lower triangle is never written.  Rows and columns beyond n
+// are clamped on load and dropped on store.
 template <class Wd>
 __global__ __launch_bounds__(kT) void pr_trail_kernel(FA a, int j1, int T, int cur, int nt) {
     using R = typename Real<Wd>::type;
@@ -477,11 +488,12 @@ __global__ __launch_bounds__(kT) void pr_trail_kernel(FA a, int j1, int T, int c
 #pragma unroll
     for (int r = 0; r < 4; ++r) prow[r] = pm[min(rbase + acc_row<R>(lane, r), n - 1)];
     A4 re[4], im[4];
+    const int base = j1 - 2 * T;                        // where the previous trail update started
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const Wd v = X[(size_t)prow[r] * n + pcol[jb]];
+            const Wd v = pr_stored<Wd>(X, n, base, prow[r], pcol[jb]);
             re[jb][r] = re_(v);
             im[jb][r] = im_(v);
         }
@@ -501,18 +513,13 @@ __global__ __launch_bounds__(kT) void pr_trail_kernel(FA a, int j1, int T, int c
             mac<Wd>(av, bv, re[jb], im[jb]);
         }
     }
-    const bool mirror = ti != tj;
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
         const int sc = s0 + jb * 16 + lc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int q = rbase + acc_row<R>(lane, r);
-            if (q < n && sc < n) {
-                const Wd v = make_<Wd>(re[jb][r], im[jb][r]);
-                Y[(size_t)q * n + sc] = v;
-                if (mirror) Y[(size_t)sc * n + q] = -v;
-            }
+            if (q < n && sc < n) Y[(size_t)q * n + sc] = make_<Wd>(re[jb][r], im[jb][r]);
         }
     }
 }
