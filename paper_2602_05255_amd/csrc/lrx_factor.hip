@@ -208,9 +208,10 @@ __global__ void init_acc_kernel(FA a) {
 // Returns the index on every thread (-1 when the block saw no candidate).  One
 // barrier: every thread reduces the per-wave results itself; the caller must
 // pass another barrier before calling again (s_val / s_idx are reused).
-__device__ __forceinline__ void argmax_pair(double &val, int &idx, int m) {
-    const double ov = __shfl_xor(val, m, 64);
-    const int oi = __shfl_xor(idx, m, 64);
+template <int M>
+__device__ __forceinline__ void argmax_pair(double &val, int &idx) {
+    const double ov = shfl_xor_v(val, M);                 // DPP / swizzle exchanges (xshfl_i32)
+    const int oi = xshfl_i32(idx, M);
     const bool take = (oi >= 0) && (idx < 0 || ov > val || (ov == val && oi < idx));
     val = take ? ov : val;
     idx = take ? oi : idx;
@@ -218,12 +219,12 @@ __device__ __forceinline__ void argmax_pair(double &val, int &idx, int m) {
 template <int NT>
 __device__ int block_argmax(double val, int idx, double *s_val, int *s_idx) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    argmax_pair(val, idx, 32);
-    argmax_pair(val, idx, 16);
-    argmax_pair(val, idx, 8);
-    argmax_pair(val, idx, 4);
-    argmax_pair(val, idx, 2);
-    argmax_pair(val, idx, 1);
+    argmax_pair<32>(val, idx);
+    argmax_pair<16>(val, idx);
+    argmax_pair<8>(val, idx);
+    argmax_pair<4>(val, idx);
+    argmax_pair<2>(val, idx);
+    argmax_pair<1>(val, idx);
     if (lane == 0) { s_val[wv] = val; s_idx[wv] = idx; }
     __syncthreads();
     double bv = s_val[0];
@@ -307,6 +308,8 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
     __shared__ double s_val[kPrThreads / 64];
     __shared__ int s_idx[kPrThreads / 64];
     __shared__ Wd s_ia[kPrMaxPairs];                    // 1 / alpha of the panel's pairs
+    __shared__ Wd s_al[kPrMaxPairs];                    // alpha of the panel's pairs
+    __shared__ int s_sw[kPrMaxPairs];                   // the pair swapped (sign flip)
     const int w = blockIdx.x, n = a.n, tid = threadIdx.x;
     Wd *s_c = reinterpret_cast<Wd *>(smem);             // [P][n] pending c_t, logical index
     Wd *s_w = s_c + (size_t)P * n;                      // [P][n] pending w_t
@@ -366,15 +369,14 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
                 Wd tv = c[q]; c[q] = c[p]; c[p] = tv;
                 tv = wv[q]; wv[q] = wv[p]; wv[p] = tv;
             }
-            ph = -ph;
         }
         __syncthreads();
         const Wd alpha = s_rj[q];
         if (is_zero(alpha)) { zero_pf = true; break; }
-        la += log(absv(alpha));
-        ph = ph * unit(alpha);
+        // log|pf| and the phase take alpha and the swap sign at the panel's end,
+        // off the pair chain
         const Wd inva = recip(alpha);
-        if (tid == 0) s_ia[t] = inva;
+        if (tid == 0) { s_ia[t] = inva; s_al[t] = alpha; s_sw[t] = p != q; }
         // the new pending pair (c = row j / alpha, w = row q) and row j+2 up
         // to this pair's term, on entries > q
         const bool more = t + 1 < pairs;
@@ -398,7 +400,21 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         }
         __syncthreads();
     }
-    if (tid == 0) {
+    __shared__ double s_lg[kPrMaxPairs];
+    __shared__ Wd s_un[kPrMaxPairs];
+    if (!zero_pf && tid < pairs) {                      // the pairs' factors in parallel ...
+        s_lg[tid] = log(absv(s_al[tid]));
+        s_un[tid] = unit(s_al[tid]);
+    }
+    __syncthreads();
+    if (tid == 0) {                                     // ... accumulated in pair order
+        if (!zero_pf) {
+            for (int t = 0; t < pairs; ++t) {
+                la += s_lg[t];
+                if (s_sw[t]) ph = -ph;
+                ph = ph * s_un[t];
+            }
+        }
         d->pf_zero = zero_pf ? 1 : 0;
         d->pf_logabs = zero_pf ? -INFINITY : la;
         set_ph(d->pf_ph, zero_pf ? zero<Wd>() : ph);
@@ -1544,7 +1560,7 @@ hipError_t launch_pr(const FA &fa, hipStream_t s) {
     if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
     // the kernel's static arrays and a margin stay out of the budget
-    const int P = pr_pairs<Wd>(n, lds_max > 1024 ? (size_t)lds_max - 1024 : 0);
+    const int P = pr_pairs<Wd>(n, lds_max > 2048 ? (size_t)lds_max - 2048 : 0);
     const size_t lds = pr_lds<Wd>(n, P);
     if (lds > 65536) {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&pr_panel_kernel<Wd>),
