@@ -28,12 +28,13 @@ def pf_inputs(seed, L, n, W, cplx):
 
 
 @pytest.mark.parametrize("dt,n", [(dt, n) for dt in ("c128", "f64", "c64") for n in (2, 8, 34, 100, 256)] +
-                         [("c128", 520), ("f64", 616)])
+                         [("c128", 520), ("f64", 616), ("c128", 1024)])
 def test_pf_init_matches_oracle(dt, n):
     """Pfaffian init: blocked Parlett-Reid (panels of 16 real / 8-9 complex pairs, set by the
     LDS, so several panels with a ragged last one from n = 34 on; 9 complex pairs at n = 520,
-    15 real at 616) and the Gauss-Jordan inverse (n > 512: 32- or 8-wide register blocks with
-    the MFMA sub-block update)."""
+    15 real at 616, 4 complex at the largest order 1024) and the inverse from the same
+    factorisation (64 x 64 tiles of U, V = U^-1 and V D^-1 V^T; ragged last tiles at 34, 100,
+    520, 616)."""
     say(f"pf init dt={dt} n={n}")
     cplx = dt.startswith("c")
     g, f, occ, emp = pf_inputs(300 + n, 2 * n, n, 4, cplx)
