@@ -362,6 +362,13 @@ __device__ __forceinline__ void ld16(const T *p, T (&o)[vec16<T>()]) {
     uint4 raw = *reinterpret_cast<const uint4 *>(p);
     __builtin_memcpy(&o[0], &raw, 16);
 }
+// Non-temporal variant: the data is read once (streamed), no reuse to keep.
+template <class T>
+__device__ __forceinline__ void ld16_nt(const T *p, T (&o)[vec16<T>()]) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 raw = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    __builtin_memcpy(&o[0], &raw, 16);
+}
 template <class T>
 __device__ __forceinline__ void st16(T *p, const T (&o)[vec16<T>()]) {
     uint4 raw;

@@ -391,7 +391,7 @@ __device__ __forceinline__ void accept_rows(const AcceptCtx<T> &c) {
                 const int j0 = ch * V * LRX_WAVE + lane * V;
                 if constexpr (VEC) {
                     T tmp[V];
-                    ld16<T>(row + (j0 < n ? j0 : 0), tmp);
+                    ld16_nt<T>(row + (j0 < n ? j0 : 0), tmp);
 #pragma unroll
                     for (int v = 0; v < V; ++v) x[r][ch * V + v] = tmp[v];
                 } else {
