@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void pf_rowdot_kernel(StepArgs a, int row
                 const T *row = M + (size_t)q * n;
                 T tmp[V];
                 if (q < q1 && vec_ok && j0 + V <= n) {
-                    ld16<T>(row + j0, tmp);
+                    ld16_nt<T>(row + j0, tmp);   // streamed once per step
                 } else {
 #pragma unroll
                     for (int v = 0; v < V; ++v) tmp[v] = (q < q1 && j0 + v < n) ? row[j0 + v] : zero<T>();
