@@ -259,14 +259,17 @@ __device__ int block_argmax(double val, int idx, double *s_val, int *s_idx) {
 //                 permuted instead, with the pending vectors and the current
 //                 row, so a pair costs one gather of two rows of X, LDS work
 //                 and three barriers.
-//   trail kernel: the panel's trailing matrix, one 64 x 64 tile per
+//   trail kernel: the panel's trailing matrix, one upper 64 x 64 tile per
 //                 work-group over all matrices: X'[r][s] = X[pm r][pm s] +
 //                 sum_t w_t[r] c_t[s] - c_t[r] w_t[s], an MFMA GEMM of inner
 //                 dimension 2P started from the gathered tile, written out of
-//                 place to the second workspace matrix in logical order.
-// X is read and written once per panel, by the whole GPU.  P is the largest
-// count (at most 16) whose 2P pending rows, current row and index map fit in
-// one work-group's LDS.
+//                 place to the second workspace matrix in logical order (the
+//                 lower triangle is read as the negated transpose, pr_stored).
+// The upper half of X is read and written once per panel, by the whole GPU.
+// P is the largest count (at most 16) whose 2P pending rows, current row and
+// index map fit in one work-group's LDS.  The panel also records, for the
+// inverse, the columns of L, 1/alpha and the original index of every
+// position (see the PF inverse below).
 constexpr int kPrMaxPairs = 16;          // the workspace Z holds 2 x 16 pending rows
 constexpr int kPrThreads = 512;
 
