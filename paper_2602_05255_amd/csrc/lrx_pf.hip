@@ -67,10 +67,42 @@ __global__ __launch_bounds__(kThreads) void pf_build_hop_kernel(HopArgs a) {
 // ------------------------------------------------------------------ propose
 // Slot columns per unrolled round of loads in the column pass of the propose.
 constexpr int kPfPropRound = 16;
+// The propose runs one work-group of 8 waves per walker.  Where the columns
+// fit in fewer threads, the column pass splits the slot columns over groups of
+// threads whose partial sums meet in LDS; the slot correction spreads the
+// slots over the 8 waves.  Larger work-groups shorten the chain of dependent
+// loads further but are harder to place beside the other sub-batches' kernels.
+constexpr int kPropThreads = 512;
+constexpr int kPropWaves = kPropThreads / LRX_WAVE;
+
+// Columns of the column pass covered at once (whole waves, at most the
+// work-group); kPropThreads / pf_prop_cols(n) thread groups share the slots.
+__host__ __device__ constexpr int pf_prop_cols(int n) {
+    return n <= 64 ? 64 : ((n + 63) / 64 * 64 < kPropThreads ? (n + 63) / 64 * 64 : kPropThreads);
+}
+
+// One round of the column pass: c += sum_j fa[r*R + j][q] s_m[r*R + j] over a
+// round of kPfPropRound slot columns (clamped addresses; s_m is zero-padded).
+template <class T>
+__device__ __forceinline__ T pf_prop_round(const T *fa, const T *s_m, int n, int TE, int r, int q, T c) {
+    T fv[kPfPropRound];
+#pragma unroll
+    for (int j = 0; j < kPfPropRound; ++j) fv[j] = fa[(size_t)min(r * kPfPropRound + j, TE - 1) * n + q];
+#pragma unroll
+    for (int j = 0; j < kPfPropRound; ++j) c = fmac(fv[j], s_m[r * kPfPropRound + j], c);
+    return c;
+}
+
+// col_q = A0^-1[q][i] = -A0^-1[i][q], from dense or packed skew storage.
+template <class T, bool PK>
+__device__ __forceinline__ T pf_prop_m(const T *M, int n, int nt, int i, int q) {
+    if constexpr (PK) return (i >> 6) <= (q >> 6) ? -M[pk_offset(nt, i, q)] : M[pk_offset(nt, q, i)];
+    else return -M[(size_t)i * n + q];
+}
 
 // PK: M0 in packed skew storage (upper 64 x 64 tiles, LRX_LAYOUT_PACKED).
 template <class T, bool PK>
-__global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
+__global__ __launch_bounds__(kPropThreads) void pf_propose_kernel(StepArgs a) {
     using Wd = typename Wide<T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = blockIdx.x, n = a.n, tau = a.tau, TE = tau * KA;
@@ -89,9 +121,11 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
     // they meet are zero-padded to whole rounds, so padded terms add nothing.
     const int TEp = (TE + kPfPropRound - 1) / kPfPropRound * kPfPropRound;
     const int npx = (n + 8 * 64 - 1) / (8 * 64) * (8 * 64);
+    const int QW = pf_prop_cols(n), S = kPropThreads / QW;
     T *s_m = reinterpret_cast<T *>(smem);      // [TEp] R_t^-1 a_t[i,:]^T
-    T *s_red = s_m + TEp;                      // [kWaves]
-    T *s_x = s_red + kWaves;                   // [npx] x
+    T *s_red = s_m + TEp;                      // [kPropWaves]
+    T *s_x = s_red + kPropWaves;               // [npx] x
+    T *s_part = s_x + npx;                     // [(S - 1) * QW] column partial sums
     // With a hop table the hop vector is built here, x[j] = f[s'][occ_j] -
     // f[s][occ_j] (j != i), and written to x for the accept that follows.
     const bool fused = a.hop_table != nullptr;
@@ -122,7 +156,7 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
         const Wd *fs = tab + (size_t)s_src * a.sites, *fd = tab + (size_t)s_dst * a.sites;
         const int32_t *occ = a.occ + (size_t)w * n;
         T *xw = const_cast<T *>(x);
-        for (int j = tid; j < npx; j += kThreads) {
+        for (int j = tid; j < npx; j += kPropThreads) {
             T v = zero<T>();
             if (j < n && !s_bad && j != i) {
                 const int oj = occ[j];
@@ -132,13 +166,13 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
             s_x[j] = v;
         }
     } else {
-        for (int j = tid; j < npx; j += kThreads) {
+        for (int j = tid; j < npx; j += kPropThreads) {
             T v = zero<T>();
             if (j < n) v = x[j];
             s_x[j] = v;
         }
     }
-    for (int te = tid; te < TEp; te += kThreads) {
+    for (int te = tid; te < TEp; te += kPropThreads) {
         const int t = te / KA, s = te - t * KA;
         T v = zero<T>();
         if (te < TE)
@@ -146,27 +180,37 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
         s_m[te] = v;
     }
     __syncthreads();
+    // col_q = -A0^-1[i][q] + sum_te fa[te][q] s_m[te]; ratio - 1 = x . col.
     T part = zero<T>();
-    for (int q = tid; q < n; q += kThreads) {
-        // col_q = A0^-1[q][i] = -A0^-1[i][q]
-        T c;
-        if constexpr (PK) c = (i >> 6) <= (q >> 6) ? -M[pk_offset(nt, i, q)] : M[pk_offset(nt, q, i)];
-        else c = -M[(size_t)i * n + q];
-        for (int t0 = 0; t0 < TE; t0 += kPfPropRound) {
-            T fv[kPfPropRound];
-#pragma unroll
-            for (int j = 0; j < kPfPropRound; ++j) fv[j] = fa[(size_t)min(t0 + j, TE - 1) * n + q];
-#pragma unroll
-            for (int j = 0; j < kPfPropRound; ++j) c = fmac(fv[j], s_m[t0 + j], c);
+    const int nr = TEp / kPfPropRound;
+    if (S == 1) {
+        for (int q = tid; q < n; q += kPropThreads) {
+            T c = pf_prop_m<T, PK>(M, n, nt, i, q);
+            for (int r = 0; r < nr; ++r) c = pf_prop_round(fa, s_m, n, TE, r, q, c);
+            col[q] = c;
+            part = fmac(s_x[q], c, part);
         }
-        col[q] = c;
-        part = fmac(s_x[q], c, part);
+    } else {
+        // Thread group g takes the rounds r = g, g + S, ... of column q.
+        const int g = tid / QW, q = tid - g * QW, qc = min(q, n - 1);
+        T c = zero<T>();
+        if (n > 0 && g < S) {
+            if (g == 0) c = pf_prop_m<T, PK>(M, n, nt, i, qc);
+            for (int r = g; r < nr; r += S) c = pf_prop_round(fa, s_m, n, TE, r, qc, c);
+            if (g > 0) s_part[(g - 1) * QW + q] = c;
+        }
+        __syncthreads();
+        if (g == 0 && q < n) {
+            for (int gp = 1; gp < S; ++gp) c = c + s_part[(gp - 1) * QW + q];
+            col[q] = c;
+            part = fmac(s_x[q], c, part);
+        }
     }
     part = wave_sum(part);
     if (lane == 0) s_red[wv] = part;
     // h_t = R_t^-1 (a_t^T x): the slot correction of A_{tau-1}^-1 x.
     if (a.K > 0) {
-        for (int t = wv; t < tau; t += kWaves) {
+        for (int t = wv; t < tau; t += kPropWaves) {
             T g[KA];
 #pragma unroll
             for (int s = 0; s < KA; ++s) g[s] = zero<T>();
@@ -197,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void pf_propose_kernel(StepArgs a) {
     __syncthreads();
     if (tid == 0) {
         T tot = one<T>();
-        for (int q = 0; q < kWaves; ++q) tot = tot + s_red[q];
+        for (int q = 0; q < kPropWaves; ++q) tot = tot + s_red[q];
         Wd r = conv<Wd>(tot);
         if (s_bad) r = zero<Wd>();
         static_cast<Wd *>(a.ratio)[w] = r;
@@ -450,11 +494,12 @@ template <class T> hipError_t build_hop_t(const HopArgs &a, hipStream_t s) {
 template <class T> hipError_t propose_t(const StepArgs &a, hipStream_t s) {
     const size_t tep = ((size_t)a.tau * KA + kPfPropRound - 1) / kPfPropRound * kPfPropRound;
     const size_t npx = ((size_t)a.n + 8 * 64 - 1) / (8 * 64) * (8 * 64);
-    size_t lds = sizeof(T) * (tep + kWaves + npx);
+    const size_t qw = pf_prop_cols(a.n);
+    size_t lds = sizeof(T) * (tep + kPropWaves + npx + (kPropThreads / qw - 1) * qw);
     if (a.layout == LRX_LAYOUT_PACKED)
-        hipLaunchKernelGGL((pf_propose_kernel<T, true>), dim3(a.W), dim3(kThreads), lds, s, a);
+        hipLaunchKernelGGL((pf_propose_kernel<T, true>), dim3(a.W), dim3(kPropThreads), lds, s, a);
     else
-        hipLaunchKernelGGL((pf_propose_kernel<T, false>), dim3(a.W), dim3(kThreads), lds, s, a);
+        hipLaunchKernelGGL((pf_propose_kernel<T, false>), dim3(a.W), dim3(kPropThreads), lds, s, a);
     return hipGetLastError();
 }
 
