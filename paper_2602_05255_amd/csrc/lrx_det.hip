@@ -30,8 +30,19 @@ template <class T> hipError_t build_hop_t(const HopArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Dynamic LDS a propose work-group may take: the per-wave partials of G grow
+// with the live slot columns (FP64, k_max = 8, K = 32 needs about 83 KB at four
+// waves), so beyond 64 KB the kernel's limit is raised first.
+constexpr size_t kProposeLdsMax = 160 * 1024 - 4096;
+
 template <class T, int KM, int NW, int NI> hipError_t propose_t(const StepArgs &a, hipStream_t s) {
     const size_t lds = propose_lds_bytes<T, KM, NW>(a.tau);
+    if (lds > kProposeLdsMax) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&det_propose_kernel<T, KM, NW, NI>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((det_propose_kernel<T, KM, NW, NI>), dim3(a.W), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
 }

@@ -113,6 +113,8 @@ def test_slater_n32_fp64_every_step():
     (64, 8, (1, 3, 8), 4, 6, 13),        # largest rank, odd ranks
     (33, 1, (1,), 3, 5, 10),             # odd n (unaligned rows)
     (128, 8, (1, 4, 8), 16, 6, 36),      # K k_max = 128 > 64 live slot columns (wider G grouping)
+    (600, 4, (1, 2, 4), 16, 3, 24),      # n > 512: four entries a thread in the propose, ragged n
+    (200, 8, (8,), 32, 3, 40),           # 256 live slot columns: propose LDS above 64 KB
 ])
 def test_delayed_det_chain_fp64(n, k_max, ranks, K, W, steps):
     say(f"delayed det chain n={n} k_max={k_max} K={K} W={W}")
