@@ -693,7 +693,9 @@ __global__ __launch_bounds__(kT) void pr_vrow_kernel(FA a, int I, int nt) {
 }
 
 // Upper tile (I, J) of B^-1 into X at the rows Pi(i), mirrored; a walker
-// with pf = 0 gets zeros in identity order.
+// with pf = 0 gets zeros in identity order.  A diagonal tile writes each
+// entry above its diagonal with the negated mirror and zeros on the diagonal,
+// so X holds an exactly skew matrix (rows permuted).
 template <class Wd>
 __global__ __launch_bounds__(kT) void pr_inv_kernel(FA a, int nt) {
     using R = typename Real<Wd>::type;
@@ -735,17 +737,17 @@ __global__ __launch_bounds__(kT) void pr_inv_kernel(FA a, int nt) {
                 for (int jb = 0; jb < 4; ++jb) mac<Wd>(av[u], bv[u][jb], re[jb], im[jb]);
         }
     }
-    const bool mirror = ti != tj;
+    const bool diag = ti == tj;
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) {
         const int sc = s0 + jb * 16 + lc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int q = rbase + acc_row<R>(lane, r);
-            if (q < n && sc < n) {
-                const Wd v = make_<Wd>(re[jb][r], im[jb][r]);
+            if (q < n && sc < n && (!diag || q <= sc)) {
+                const Wd v = (q == sc) ? zero<Wd>() : make_<Wd>(re[jb][r], im[jb][r]);
                 X[(size_t)(zero_pf ? q : pi[q]) * n + sc] = v;
-                if (mirror) X[(size_t)(zero_pf ? sc : pi[sc]) * n + q] = -v;
+                if (q != sc) X[(size_t)(zero_pf ? sc : pi[sc]) * n + q] = -v;
             }
         }
     }
@@ -1396,64 +1398,54 @@ __global__ __launch_bounds__(kT) void final_det_kernel(FA a, int rows_per_block,
     }
 }
 
-// PF: X' = X with columns src-permuted (= A^-1); M = (X' - X'^T)/2 on 32x32
-// tile pairs (ti <= tj), writing both triangles so M is exactly skew.
+// PF: M = A^-1 = X', X'[i][j] = X[i][src[j]]: the inverse kernel left the rows
+// in place and X exactly skew, so only the columns are gathered here.  One
+// wave per row: the row is read coalesced into LDS and gathered from there,
+// and M is written row by row (the packed layout keeps the tiles at or above
+// the row's diagonal tile).  The drift report weighs an entry of a strictly
+// upper packed tile twice, for its unstored mirror.
 template <class T, class Wd>
-__global__ __launch_bounds__(kT) void final_pf_kernel(FA a, int tiles) {
-    __shared__ Wd t1[32][33], t2[32][33];
+__global__ __launch_bounds__(kT) void final_pf_kernel(FA a, int groups) {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double s_d[kT / 64], s_nrm[kT / 64];
-    const int pairs = tiles * (tiles + 1) / 2;
-    const int w = blockIdx.x / pairs;
-    int p = blockIdx.x - w * pairs;
-    int ti = 0;
-    while (p >= tiles - ti) { p -= tiles - ti; ++ti; }
-    const int tj = ti + p;
+    constexpr int RW = kT / 64;                   // rows per work-group
     const int n = a.n;
+    const int w = blockIdx.x / groups;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = (blockIdx.x - w * groups) * RW + wv;
     const Wd *X = wX<Wd>(a, w);
     const int *src = wSrc(a, w);
-    // Full storage, or the packed upper 64 x 64 tiles (LRX_LAYOUT_PACKED): entry
-    // (i, j), i <= j by tile, at pk_offset; the lower triangle is kept only inside
-    // diagonal tiles.
+    Wd *s_row = reinterpret_cast<Wd *>(smem) + (size_t)wv * n;
+    if (i < n)
+        for (int c = lane; c < n; c += 64) s_row[c] = X[(size_t)i * n + c];
+    __syncthreads();
     const int nt = (n + 63) >> 6;
     T *M = static_cast<T *>(a.inv) + (size_t)w * (a.packed ? lrx_pk_elems_dev(n) : (size_t)n * n);
-    auto at = [&](int r, int c) -> T * { return a.packed ? M + pk_offset(nt, r, c) : M + (size_t)r * n + c; };
-    const bool lower_kept = !a.packed || ti / 2 == tj / 2;      // (j, i) stored: 32-tile pair inside one 64-tile
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int r = ty; r < 32; r += 8) {
-        const int i = ti * 32 + r, j = tj * 32 + tx;
-        t1[r][tx] = (i < n && j < n) ? X[(size_t)i * n + src[j]] : zero<Wd>();   // X'[i][j]
-        const int i2 = tj * 32 + r, j2 = ti * 32 + tx;
-        t2[r][tx] = (i2 < n && j2 < n) ? X[(size_t)i2 * n + src[j2]] : zero<Wd>();   // X'[j][i] block
-    }
-    __syncthreads();
     double dsq = 0.0, nsq = 0.0;
-    for (int r = ty; r < 32; r += 8) {
-        const int i = ti * 32 + r, j = tj * 32 + tx;
-        if (i < n && j < n && (ti < tj || r < tx)) {
-            // upper entry (i, j): (X'[i][j] - X'[j][i]) / 2
-            const Wd h = half_of(t1[r][tx] - t2[tx][r]);
-            const Wd nh = -h;
+    if (i < n) {
+        const int ti = i >> 6;
+        for (int j = lane; j < n; j += 64) {
+            const int tj = j >> 6;
+            if (a.packed && tj < ti) continue;
+            const int sj = min(max(src[j], 0), n - 1);
+            const Wd h = (j == i) ? zero<Wd>() : s_row[sj];
+            T *dst = a.packed ? M + pk_offset(nt, i, j) : M + (size_t)i * n + j;
             if (a.report) {
-                const Wd o1 = conv<Wd>(*at(i, j));
-                const Wd o2 = lower_kept ? conv<Wd>(*at(j, i)) : -o1;
-                dsq += abs2(o1 - h) + abs2(o2 - nh);
-                nsq += 2.0 * abs2(h);
+                const double wgt = (a.packed && tj > ti) ? 2.0 : 1.0;
+                dsq += wgt * abs2(conv<Wd>(*dst) - h);
+                nsq += wgt * abs2(h);
             }
-            *at(i, j) = conv<T>(h);
-            if (lower_kept) *at(j, i) = conv<T>(nh);
-        } else if (i < n && j < n && ti == tj && r == tx) {
-            if (a.report) dsq += abs2(conv<Wd>(*at(i, i)));
-            *at(i, i) = zero<T>();
+            *dst = conv<T>(h);
         }
     }
     if (a.report) {
         dsq = wave_sum(dsq);
         nsq = wave_sum(nsq);
-        if ((threadIdx.x & 63) == 0) { s_d[threadIdx.x >> 6] = dsq; s_nrm[threadIdx.x >> 6] = nsq; }
+        if (lane == 0) { s_d[wv] = dsq; s_nrm[wv] = nsq; }
         __syncthreads();
         if (threadIdx.x == 0) {
             double s0 = 0, s1 = 0;
-            for (int q = 0; q < kT / 64; ++q) { s0 += s_d[q]; s1 += s_nrm[q]; }
+            for (int q = 0; q < RW; ++q) { s0 += s_d[q]; s1 += s_nrm[q]; }
             DetAcc *d = wAcc(a, w);
             atomicAdd(&d->dsq, s0);
             atomicAdd(&d->nsq, s1);
@@ -1627,8 +1619,13 @@ hipError_t factor_t(const FactorArgs &in, hipStream_t s) {
         hipLaunchKernelGGL(load_kernel<Wd>, dim3((unsigned)(W * tiles * tiles)), dim3(kT), 0, s, a, tiles);
         if ((e = launch_pr<Wd>(a, s)) != hipSuccess) return e;
         if ((e = launch_pf_inverse<Wd>(a, s)) != hipSuccess) return e;
-        const int pairs = tiles * (tiles + 1) / 2;
-        hipLaunchKernelGGL((final_pf_kernel<T, Wd>), dim3((unsigned)(W * pairs)), dim3(kT), 0, s, a, tiles);
+        const int groups = (n + kT / 64 - 1) / (kT / 64);
+        const size_t flds = (size_t)(kT / 64) * n * sizeof(Wd);   // one row per wave (64 KB at n = 1024, complex128)
+        if (flds > 60 * 1024 &&
+            (e = hipFuncSetAttribute(reinterpret_cast<const void *>(&final_pf_kernel<T, Wd>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)flds)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((final_pf_kernel<T, Wd>), dim3((unsigned)(W * groups)), dim3(kT), flds, s, a, groups);
         if (a.packed && (n & 63)) {
             const int nt = (n + 63) / 64;
             hipLaunchKernelGGL(pk_zero_tail_kernel<T>, dim3((unsigned)(W * nt)), dim3(kT), 0, s, a, nt);
