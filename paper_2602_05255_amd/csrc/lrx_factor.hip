@@ -720,21 +720,40 @@ __global__ __launch_bounds__(kT) void pr_inv_kernel(FA a, int nt) {
         int col[4];
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) col[jb] = min(s0 + jb * 16 + lc, n - 1);
-        for (int m0 = s0; m0 < n; m0 += 16) {           // four 4-deep steps per batch
-            Wd av[4], bv[4][4];
+        // Batches of four 4-deep steps, software pipelined over two register
+        // sets: the next batch's loads (clamped addresses) are in flight
+        // while the current one goes through the matrix cores.
+        auto load = [&](int m0, Wd (&xa)[4], Wd (&ya)[4], Wd (&bb)[4][4]) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int mc = min(m0 + 4 * u + kq, n - 1);
+                xa[u] = V[(size_t)ra * n + (mc ^ 1)];
+                ya[u] = ia[mc >> 1];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) bb[u][jb] = V[(size_t)col[jb] * n + mc];
+            }
+        };
+        auto comp = [&](int m0, const Wd (&xa)[4], const Wd (&ya)[4], const Wd (&bb)[4][4]) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int m = m0 + 4 * u + kq;
-                const int mc = min(m, n - 1);
-                const Wd x = V[(size_t)ra * n + (mc ^ 1)] * ia[mc >> 1];
-                av[u] = m < n ? (m & 1 ? -x : x) : zero<Wd>();
+                const Wd x = xa[u] * ya[u];
+                const Wd av = m < n ? (m & 1 ? -x : x) : zero<Wd>();
 #pragma unroll
-                for (int jb = 0; jb < 4; ++jb) bv[u][jb] = V[(size_t)col[jb] * n + mc];
+                for (int jb = 0; jb < 4; ++jb) mac<Wd>(av, bb[u][jb], re[jb], im[jb]);
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) mac<Wd>(av[u], bv[u][jb], re[jb], im[jb]);
+        };
+        Wd x0[4], y0[4], b0[4][4], x1[4], y1[4], b1[4][4];
+        int m0 = s0;
+        load(m0, x0, y0, b0);
+        while (m0 < n) {
+            load(m0 + 16, x1, y1, b1);
+            comp(m0, x0, y0, b0);
+            m0 += 16;
+            if (m0 >= n) break;
+            load(m0 + 16, x0, y0, b0);
+            comp(m0, x1, y1, b1);
+            m0 += 16;
         }
     }
     const bool diag = ti == tj;
