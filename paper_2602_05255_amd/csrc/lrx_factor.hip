@@ -266,8 +266,10 @@ __device__ int block_argmax(double val, int idx, double *s_val, int *s_idx) {
 //                 place to the second workspace matrix in logical order (the
 //                 lower triangle is read as the negated transpose, pr_stored).
 // The upper half of X is read and written once per panel, by the whole GPU.
-// P is the largest count (at most 16) whose 2P pending rows, current row and
-// index map fit in one work-group's LDS.  The panel also records, for the
+// Each panel's P is the largest count (at most 16) whose 2P pending vectors,
+// current row and index map fit in one work-group's LDS; they span only the
+// panel's n - j0 logical indices, so later panels take more pairs.  The panel
+// also records, for the
 // inverse, the columns of L, 1/alpha and the original index of every
 // position (see the PF inverse below).
 constexpr int kPrMaxPairs = 16;          // the workspace Z holds 2 x 16 pending rows
@@ -295,6 +297,8 @@ __device__ __forceinline__ Wd pr_stored(const Wd *X, int n, int base, int r, int
     return up ? v : -v;
 }
 
+// LDS of a panel over m = n - j0 logical indices with P pairs, and the most
+// pairs (up to kPrMaxPairs) that fit a budget.
 template <class Wd> size_t pr_lds(int n, int P) {
     return sizeof(Wd) * ((size_t)2 * P * n + n) + sizeof(int) * (size_t)n;
 }
@@ -314,10 +318,12 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
     __shared__ Wd s_al[kPrMaxPairs];                    // alpha of the panel's pairs
     __shared__ int s_sw[kPrMaxPairs];                   // the pair swapped (sign flip)
     const int w = blockIdx.x, n = a.n, tid = threadIdx.x;
-    Wd *s_c = reinterpret_cast<Wd *>(smem);             // [P][n] pending c_t, logical index
-    Wd *s_w = s_c + (size_t)P * n;                      // [P][n] pending w_t
-    Wd *s_rj = s_w + (size_t)P * n;                     // [n]    row j of the current matrix
-    int *s_pm = reinterpret_cast<int *>(s_rj + n);      // [n]    logical -> physical index in X
+    // LDS arrays over the panel's logical indices j0 .. n-1, entry e at e - j0
+    const int L = n - j0;
+    Wd *s_c = reinterpret_cast<Wd *>(smem);             // [P][L] pending c_t
+    Wd *s_w = s_c + (size_t)P * L;                      // [P][L] pending w_t
+    Wd *s_rj = s_w + (size_t)P * L;                     // [L]    row j of the current matrix
+    int *s_pm = reinterpret_cast<int *>(s_rj + L);      // [L]    logical -> physical index in X
     DetAcc *d = wAcc(a, w);
     const Wd *X = pr_buf<Wd>(a, w, cur);
     Wd *Cg = wZ<Wd>(a, w);                              // [kPrMaxPairs][n], for the trail kernel
@@ -334,8 +340,8 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         return;
     }
     for (int e = j0 + tid; e < n; e += kPrThreads) {
-        s_pm[e] = e;
-        s_rj[e] = X[(size_t)j0 * n + e];
+        s_pm[e - j0] = e;
+        s_rj[e - j0] = X[(size_t)j0 * n + e];
     }
     __syncthreads();
     const int pairs = min(P, (n - j0) / 2);
@@ -344,15 +350,15 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         const int j = j0 + 2 * t, q = j + 1;
         // row j takes the previous pair's term (the others are in already),
         // then the pivot search over its entries > j
-        const Wd *lc = s_c + (size_t)(t > 0 ? t - 1 : 0) * n;
-        const Wd *lw = s_w + (size_t)(t > 0 ? t - 1 : 0) * n;
-        const Wd cl = t > 0 ? lc[j] : zero<Wd>(), wl = t > 0 ? lw[j] : zero<Wd>();
+        const Wd *lc = s_c + (size_t)(t > 0 ? t - 1 : 0) * L;
+        const Wd *lw = s_w + (size_t)(t > 0 ? t - 1 : 0) * L;
+        const Wd cl = t > 0 ? lc[j - j0] : zero<Wd>(), wl = t > 0 ? lw[j - j0] : zero<Wd>();
         double bv = -1.0;
         int bi = -1;
         for (int e = q + tid; e < n; e += kPrThreads) {
-            Wd v = s_rj[e];
-            if (t > 0) v = v + (wl * lc[e] - cl * lw[e]);
-            s_rj[e] = v;
+            Wd v = s_rj[e - j0];
+            if (t > 0) v = v + (wl * lc[e - j0] - cl * lw[e - j0]);
+            s_rj[e - j0] = v;
             const double kv = pivkey(v);
             if (bi < 0 || kv > bv) { bv = kv; bi = e; }
         }
@@ -360,21 +366,22 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         if (p != q) {
             // swap index q <-> p in the map, the current row and the pending vectors
             if (tid == 0) {
-                const int ti = s_pm[q];
-                s_pm[q] = s_pm[p];
-                s_pm[p] = ti;
-                const Wd tv = s_rj[q];
-                s_rj[q] = s_rj[p];
-                s_rj[p] = tv;
+                const int ti = s_pm[q - j0];
+                s_pm[q - j0] = s_pm[p - j0];
+                s_pm[p - j0] = ti;
+                const Wd tv = s_rj[q - j0];
+                s_rj[q - j0] = s_rj[p - j0];
+                s_rj[p - j0] = tv;
             }
             if (tid < t) {
-                Wd *c = s_c + (size_t)tid * n, *wv = s_w + (size_t)tid * n;
-                Wd tv = c[q]; c[q] = c[p]; c[p] = tv;
-                tv = wv[q]; wv[q] = wv[p]; wv[p] = tv;
+                Wd *c = s_c + (size_t)tid * L, *wv = s_w + (size_t)tid * L;
+                const int qo = q - j0, po = p - j0;
+                Wd tv = c[qo]; c[qo] = c[po]; c[po] = tv;
+                tv = wv[qo]; wv[qo] = wv[po]; wv[po] = tv;
             }
         }
         __syncthreads();
-        const Wd alpha = s_rj[q];
+        const Wd alpha = s_rj[q - j0];
         if (is_zero(alpha)) { zero_pf = true; break; }
         // log|pf| and the phase take alpha and the swap sign at the panel's end,
         // off the pair chain
@@ -384,22 +391,22 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         // to this pair's term, on entries > q
         const bool more = t + 1 < pairs;
         const int j2 = more ? j + 2 : q;
-        const int p1 = s_pm[q], p2 = s_pm[j2];
-        Wd *ct = s_c + (size_t)t * n, *wt = s_w + (size_t)t * n;
+        const int p1 = s_pm[q - j0], p2 = s_pm[j2 - j0];
+        Wd *ct = s_c + (size_t)t * L, *wt = s_w + (size_t)t * L;
         for (int e = q + 1 + tid; e < n; e += kPrThreads) {
-            const int pe = s_pm[e];
+            const int pe = s_pm[e - j0];
             Wd wv = pr_stored<Wd>(X, n, j0, p1, pe);
             Wd rv = more ? pr_stored<Wd>(X, n, j0, p2, pe) : zero<Wd>();
             for (int u = 0; u < t; ++u) {
-                const Wd *cu = s_c + (size_t)u * n, *wu = s_w + (size_t)u * n;
-                const Wd ce = cu[e], we = wu[e];
-                wv = wv + (wu[q] * ce - cu[q] * we);
-                if (more) rv = rv + (wu[j2] * ce - cu[j2] * we);
+                const Wd *cu = s_c + (size_t)u * L, *wu = s_w + (size_t)u * L;
+                const Wd ce = cu[e - j0], we = wu[e - j0];
+                wv = wv + (wu[q - j0] * ce - cu[q - j0] * we);
+                if (more) rv = rv + (wu[j2 - j0] * ce - cu[j2 - j0] * we);
             }
-            const Wd c = s_rj[e] * inva;
-            ct[e] = c;
-            wt[e] = wv;
-            if (more) s_rj[e] = rv;
+            const Wd c = s_rj[e - j0] * inva;
+            ct[e - j0] = c;
+            wt[e - j0] = wv;
+            if (more) s_rj[e - j0] = rv;
         }
         __syncthreads();
     }
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
     // entries the trail kernel reads
     int *pm = wPerm(a, w);
     int *src = wSrc(a, w);
-    for (int e = j0 + tid; e < n; e += kPrThreads) pm[e] = s_pm[e];
+    for (int e = j0 + tid; e < n; e += kPrThreads) pm[e] = s_pm[e - j0];
     if (zero_pf) {                                      // no inverse: identity column order
         for (int e = tid; e < n; e += kPrThreads) src[e] = e;
         return;
@@ -434,8 +441,8 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
     const int j1 = j0 + 2 * pairs;
     for (int t = 0; t < pairs; ++t) {
         for (int e = j1 + tid; e < n; e += kPrThreads) {
-            Cg[(size_t)t * n + e] = s_c[(size_t)t * n + e];
-            Wg[(size_t)t * n + e] = s_w[(size_t)t * n + e];
+            Cg[(size_t)t * n + e] = s_c[(size_t)t * L + e - j0];
+            Wg[(size_t)t * n + e] = s_w[(size_t)t * L + e - j0];
         }
     }
     // For the inverse (A = Pi U^T D U Pi^T, U = L^T): the original index of
@@ -448,7 +455,7 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int e = j0 + tid + u * kPrThreads;
-        o[u] = e < n ? (j0 > 0 ? orig[s_pm[e]] : s_pm[e]) : 0;
+        o[u] = e < n ? (j0 > 0 ? orig[s_pm[e - j0]] : s_pm[e - j0]) : 0;
     }
     __syncthreads();
 #pragma unroll
@@ -463,8 +470,8 @@ __global__ __launch_bounds__(kPrThreads) void pr_panel_kernel(FA a, int j0, int 
         for (int u = 0; u < 2; ++u) {
             const int e = j0 + tid + u * kPrThreads;
             if (e < n && e > j0 + 2 * t + 1) {
-                l0[o[u]] = -(s_w[(size_t)t * n + e] * iat);
-                l1[o[u]] = s_c[(size_t)t * n + e];
+                l0[o[u]] = -(s_w[(size_t)t * L + e - j0] * iat);
+                l1[o[u]] = s_c[(size_t)t * L + e - j0];
             }
         }
     }
@@ -1573,22 +1580,25 @@ hipError_t launch_pr(const FA &fa, hipStream_t s) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
-    // the kernel's static arrays and a margin stay out of the budget
-    const int P = pr_pairs<Wd>(n, lds_max > 2048 ? (size_t)lds_max - 2048 : 0);
-    const size_t lds = pr_lds<Wd>(n, P);
-    if (lds > 65536) {
+    // the kernel's static arrays and a margin stay out of the budget; a panel
+    // starting at j0 keeps n - j0 entries per pending vector, so the later
+    // panels take more pairs
+    const size_t budget = lds_max > 2048 ? (size_t)lds_max - 2048 : 0;
+    if (pr_lds<Wd>(n, pr_pairs<Wd>(n, budget)) > 65536) {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&pr_panel_kernel<Wd>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget);
         if (e != hipSuccess) return e;
     }
     const dim3 grid((unsigned)fa.W), block(kPrThreads);
     if (n & 1) {                                        // records pf = 0
-        hipLaunchKernelGGL(pr_panel_kernel<Wd>, grid, block, lds, s, fa, 0, P, 0);
+        const int P = pr_pairs<Wd>(n, budget);
+        hipLaunchKernelGGL(pr_panel_kernel<Wd>, grid, block, pr_lds<Wd>(n, P), s, fa, 0, P, 0);
         return hipGetLastError();
     }
     int cur = 0;
-    for (int j0 = 0; j0 < n; j0 += 2 * P) {
-        hipLaunchKernelGGL(pr_panel_kernel<Wd>, grid, block, lds, s, fa, j0, P, cur);
+    for (int j0 = 0, P = 0; j0 < n; j0 += 2 * P) {
+        P = pr_pairs<Wd>(n - j0, budget);
+        hipLaunchKernelGGL(pr_panel_kernel<Wd>, grid, block, pr_lds<Wd>(n - j0, P), s, fa, j0, P, cur);
         const int j1 = j0 + 2 * P;
         if (j1 < n) {
             const int nt = (n - j1 + 63) / 64;
